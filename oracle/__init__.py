@@ -1,0 +1,286 @@
+"""FP64 CPU oracle of the damped-current PML particle-in-cell step.
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU-baseline leg
+of the benchmark may use this package; the product library never does.  It wraps the
+plain C implementation in ``pml_oracle.c`` (built by ``oracle/build.py`` with gcc) via
+ctypes, and shares no code with the HIP library.
+
+A simulation is configured from any object with the attributes ``dim, n, pml, dx,
+dt, shape_order, alpha_mode, damping_scale, sigma_coef, push, charge, mass``.
+Functions whose result has no independent pin say so in their docstring
+("parity unpinned").
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+NPARTS = 12
+PART_NAMES = ["Exy", "Exz", "Eyz", "Eyx", "Ezx", "Ezy",
+              "Bxy", "Bxz", "Byz", "Byx", "Bzx", "Bzy"]
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("n", C.c_int * 3), ("pml", (C.c_int * 2) * 3),
+        ("dx", C.c_double * 3), ("dt", C.c_double), ("shape_order", C.c_int),
+        ("alpha_mode", C.c_int), ("damping_scale", C.c_double), ("n_sigma_coef", C.c_int),
+        ("sigma_coef", (C.c_double * 16) * 3), ("push", C.c_int),
+        ("charge", C.c_double), ("mass", C.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    from . import build as _b
+    return _b.build(force=force)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        d, vp, i, l, sz = C.c_double, C.c_void_p, C.c_int, C.c_long, C.c_size_t
+        dp = P(C.c_double)
+        lp = P(C.c_long)
+        sig = {
+            "orc_shape": (d, [i, d]),
+            "orc_sigma": (d, [vp, i, d]),
+            "orc_alpha_axis": (d, [vp, i, d]),
+            "orc_alpha": (d, [vp, dp]),
+            "orc_create": (vp, [P(OrcParams)]),
+            "orc_destroy": (None, [vp]),
+            "orc_num_samples": (sz, [vp]),
+            "orc_num_particles": (l, [vp]),
+            "orc_step_count": (l, [vp]),
+            "orc_add_particles": (i, [vp, l, dp, dp, dp]),
+            "orc_set_particles": (i, [vp, l, lp, dp, dp, dp]),
+            "orc_get_particles": (None, [vp, lp, dp, dp, dp]),
+            "orc_get_fields": (None, [vp, dp]),
+            "orc_set_fields": (None, [vp, dp]),
+            "orc_get_current": (None, [vp, dp]),
+            "orc_set_current": (None, [vp, dp]),
+            "orc_get_rho_static": (None, [vp, dp]),
+            "orc_set_rho_static": (None, [vp, dp]),
+            "orc_gather": (None, [vp, dp, dp]),
+            "orc_boris": (None, [d, dp, dp, dp]),
+            "orc_deposit_into": (None, [vp, dp, dp, d, d]),
+            "orc_zero_current": (None, [vp]),
+            "orc_damp_current": (None, [vp]),
+            "orc_advance_B": (None, [vp, d]),
+            "orc_advance_E": (None, [vp, d]),
+            "orc_step": (None, [vp, i]),
+            "orc_diagnose": (None, [vp, dp]),
+            "orc_rho": (None, [vp, dp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _pad3(X) -> np.ndarray:
+    v = np.zeros(3)
+    a = np.asarray(X, dtype=np.float64).reshape(-1)
+    v[: len(a)] = a
+    return v
+
+
+def _lp(a: np.ndarray):
+    assert a.dtype == np.int64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_long))
+
+
+def shape(order: int, d: float) -> float:
+    """Centred B-spline shape factor of the given order at distance d (cells)."""
+    return lib().orc_shape(order, float(d))
+
+
+def boris(qdt_2m: float, E, B, u) -> np.ndarray:
+    """One relativistic Boris update of u = gamma v in fields E, B."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    uu = np.array(u, dtype=np.float64)
+    lib().orc_boris(float(qdt_2m), _dp(E), _dp(B), _dp(uu))
+    return uu
+
+
+def make_params(cfg) -> OrcParams:
+    p = OrcParams()
+    p.dim = int(cfg.dim)
+    for d in range(3):
+        p.n[d] = int(cfg.n[d]) if d < cfg.dim else 0
+        p.pml[d][0] = int(cfg.pml[d][0]) if d < cfg.dim else 0
+        p.pml[d][1] = int(cfg.pml[d][1]) if d < cfg.dim else 0
+        p.dx[d] = float(cfg.dx[d]) if d < cfg.dim else 1.0
+    p.dt = float(cfg.dt)
+    p.shape_order = int(cfg.shape_order)
+    p.alpha_mode = int(cfg.alpha_mode)
+    p.damping_scale = float(cfg.damping_scale)
+    coef = np.zeros((3, 16))
+    for d, row in enumerate(cfg.sigma_coef):
+        coef[d, : len(row)] = row
+    p.n_sigma_coef = 16
+    for d in range(3):
+        for k in range(16):
+            p.sigma_coef[d][k] = coef[d, k]
+    p.push = int(cfg.push)
+    p.charge = float(cfg.charge)
+    p.mass = float(cfg.mass)
+    return p
+
+
+class OracleSim:
+    """Plain FP64 simulation (split fields everywhere, absolute grid coordinates)."""
+
+    def __init__(self, cfg):
+        self.cfg = cfg
+        self._p = make_params(cfg)
+        self._h = lib().orc_create(C.byref(self._p))
+        if not self._h:
+            raise ValueError("oracle: invalid parameters")
+        self.dim = int(cfg.dim)
+        self.M = [int(cfg.n[d]) + int(cfg.pml[d][0]) + int(cfg.pml[d][1]) if d < cfg.dim else 0
+                  for d in range(3)]
+        self.nn = [m + 1 if d < cfg.dim else 1 for d, m in enumerate(self.M)]
+        self.nsamp = int(lib().orc_num_samples(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    # ---- particles
+    def add_particles(self, x, u, w):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, self.dim)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        lib().orc_add_particles(self._h, len(w), _dp(x), _dp(u), _dp(w))
+
+    def set_particles(self, ids, X, u, w):
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        lib().orc_set_particles(self._h, len(w), _lp(ids), _dp(X), _dp(u), _dp(w))
+
+    @property
+    def num_particles(self) -> int:
+        return int(lib().orc_num_particles(self._h))
+
+    @property
+    def step_count(self) -> int:
+        return int(lib().orc_step_count(self._h))
+
+    def particles(self):
+        """(ids, X grid coordinates n x 3, u n x 3, w n)."""
+        n = self.num_particles
+        ids = np.zeros(n, np.int64)
+        X = np.zeros((n, 3))
+        u = np.zeros((n, 3))
+        w = np.zeros(n)
+        if n:
+            lib().orc_get_particles(self._h, _lp(ids), _dp(X), _dp(u), _dp(w))
+        return ids, X, u, w
+
+    # ---- fields
+    def _shape(self):
+        return (self.nn[2], self.nn[1], self.nn[0])
+
+    def split_fields(self) -> np.ndarray:
+        """(12, nz, ny, nx) split parts in the order of PART_NAMES."""
+        out = np.zeros((NPARTS, self.nsamp))
+        lib().orc_get_fields(self._h, _dp(out))
+        return out.reshape((NPARTS,) + self._shape())
+
+    def set_split_fields(self, F: np.ndarray):
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(NPARTS, self.nsamp)
+        lib().orc_set_fields(self._h, _dp(F))
+
+    def fields(self) -> np.ndarray:
+        """(6, nz, ny, nx) totals Ex Ey Ez Bx By Bz (Eq. MaxwellSum)."""
+        F = self.split_fields()
+        return F[0::2] + F[1::2]
+
+    def current(self) -> np.ndarray:
+        out = np.zeros((3, self.nsamp))
+        lib().orc_get_current(self._h, _dp(out))
+        return out.reshape((3,) + self._shape())
+
+    def set_current(self, J):
+        J = np.ascontiguousarray(J, dtype=np.float64).reshape(3, self.nsamp)
+        lib().orc_set_current(self._h, _dp(J))
+
+    def rho_static(self):
+        out = np.zeros(self.nsamp)
+        lib().orc_get_rho_static(self._h, _dp(out))
+        return out.reshape(self._shape())
+
+    def set_rho_static(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+        lib().orc_set_rho_static(self._h, _dp(r))
+
+    def rho(self):
+        out = np.zeros(self.nsamp)
+        lib().orc_rho(self._h, _dp(out))
+        return out.reshape(self._shape())
+
+    # ---- phases
+    def gather(self, X) -> np.ndarray:
+        X = _pad3(X)
+        out = np.zeros(6)
+        lib().orc_gather(self._h, _dp(X), _dp(out))
+        return out
+
+    def deposit(self, X0, X1, vz, qw):
+        X0 = _pad3(X0)
+        X1 = _pad3(X1)
+        lib().orc_deposit_into(self._h, _dp(X0), _dp(X1), float(vz), float(qw))
+
+    def zero_current(self):
+        lib().orc_zero_current(self._h)
+
+    def damp_current(self):
+        lib().orc_damp_current(self._h)
+
+    def advance_B(self, tau):
+        lib().orc_advance_B(self._h, float(tau))
+
+    def advance_E(self, tau):
+        lib().orc_advance_E(self._h, float(tau))
+
+    def step(self, n: int = 1):
+        lib().orc_step(self._h, int(n))
+
+    def sigma(self, d: int, X: float) -> float:
+        return lib().orc_sigma(self._h, d, float(X))
+
+    def alpha_axis(self, d: int, X: float) -> float:
+        return lib().orc_alpha_axis(self._h, d, float(X))
+
+    def alpha(self, X) -> float:
+        X = _pad3(X)
+        return lib().orc_alpha(self._h, _dp(X))
+
+    def diagnose(self) -> dict:
+        out = np.zeros(7)
+        lib().orc_diagnose(self._h, _dp(out))
+        return {"u_interior": out[0], "u_pml": out[1], "gauss_max": out[2],
+                "gauss_l2": out[3], "rho_max": out[4], "n_particles": int(out[5]),
+                "step": int(out[6])}

@@ -1,0 +1,667 @@
+/*
+ * FP64 CPU oracle of the damped-current PML particle-in-cell step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call this
+ * file; only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * use it.  It shares no code, header, table or constant with the HIP library.
+ *
+ * The oracle is deliberately plain: absolute FP64 grid coordinates for particles,
+ * all twelve split field parts stored everywhere (in the interior both parts of a
+ * component are undamped, so only their sum matters), direct loops, no blocking or
+ * fusion, compiled with -O2 -ffp-contract=off.
+ *
+ * What it computes, and where each part comes from (Lehe et al., "Absorption of
+ * charged particles in Perfectly-Matched-Layers by optimal damping of the deposited
+ * current"):
+ *   - split-field Maxwell equations with the damped current source: Sec. II.A,
+ *     Eqs. (MaxwellE), (MaxwellB), (MaxwellSum), written for a PML normal along any
+ *     axis (cyclic relabelling of the paper's z-face equations);
+ *   - damping coefficient alpha = exp(-(1/v) int sigma/eps0): Sec. II.A, Eq. (alpha),
+ *     evaluated at nodes and cell centres in closed form (Sec. II.B);
+ *   - alpha = 0 (standard Berenger PML) and alpha = 1 (undamped deposition): the two
+ *     comparison schemes of Sec. I / Fig. 1 caption;
+ *   - Yee staggering and FDTD (Sec. II.B), 2D by dropping z derivatives (end of
+ *     Sec. II.A);
+ *   - Esirkepov charge-conserving deposition with B-spline shapes (App. A);
+ *   - static opposite-charge partner at the initial position, E = B = 0 at t = 0
+ *     (App. A.1);
+ *   - energy-norm error integrand over physical cells (Sec. III, Eq. (error)).
+ * Readings where the paper is silent (time discretisation of the PML terms, split
+ * of the current in corners, alpha in corners, gather/push) are stated next to the
+ * code that makes them.
+ *
+ * Units: c = eps0 = mu0 = 1.  Grid coordinates X are in node-index units; node i
+ * along axis d sits at physical position (i - pml_lo[d]) * dx[d], so the physical
+ * box is [0, n[d] dx[d]] and the PML lies outside it.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "pml_oracle.h"
+
+#define NPART 12
+
+/* ---------------------------------------------------------------- B-spline shapes */
+
+/* Centred cardinal B-spline of degree `order` (1 linear, 2 quadratic, 3 cubic),
+ * the particle shape factor of App. A (linear for the cavity runs, cubic "piecewise
+ * cubic spline" for the single-particle runs).  Argument d is the distance from the
+ * node in cell units. */
+double orc_shape(int order, double d)
+{
+    double a = fabs(d);
+    if (order == 1) {
+        return a < 1.0 ? 1.0 - a : 0.0;
+    } else if (order == 2) {
+        if (a < 0.5) return 0.75 - a * a;
+        if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+        return 0.0;
+    } else if (order == 3) {
+        if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+        if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+        return 0.0;
+    }
+    return 0.0;
+}
+
+/* ---------------------------------------------------------------- PML profiles */
+
+/* Depth (physical length) of grid coordinate X inside the PML of axis d; 0 in the
+ * physical box.  Also returns the thickness (physical length) of that side's PML. */
+static double depth(const orc_sim *s, int d, double X, double *thick)
+{
+    double lo = (double)s->p.pml[d][0];
+    double hi = (double)(s->p.pml[d][0] + s->p.n[d]);
+    *thick = 0.0;
+    if (d >= s->p.dim) return 0.0;
+    if (X < lo) { *thick = s->p.pml[d][0] * s->p.dx[d]; return (lo - X) * s->p.dx[d]; }
+    if (X > hi) { *thick = s->p.pml[d][1] * s->p.dx[d]; return (X - hi) * s->p.dx[d]; }
+    return 0.0;
+}
+
+/* sigma/eps0 at depth delta: the graded profile sum_k a_k (delta/L)^k (the paper's
+ * Eq. (conductivity) is the k = 2 member with a_2 = 4 (L/6)^2 / dx). */
+static double sigma_of_depth(const orc_sim *s, int d, double delta, double L)
+{
+    if (delta <= 0.0 || L <= 0.0) return 0.0;
+    double r = delta / L, acc = 0.0, pw = 1.0;
+    for (int k = 0; k < s->p.n_sigma_coef; ++k) { acc += s->p.sigma_coef[d][k] * pw; pw *= r; }
+    return acc;
+}
+
+/* Phi(delta) = int_0^delta sigma(z')/eps0 dz', exact integral of the polynomial. */
+static double phi_of_depth(const orc_sim *s, int d, double delta, double L)
+{
+    if (delta <= 0.0 || L <= 0.0) return 0.0;
+    double r = delta / L, acc = 0.0, pw = r;
+    for (int k = 0; k < s->p.n_sigma_coef; ++k) {
+        acc += s->p.sigma_coef[d][k] * L * pw / (double)(k + 1);
+        pw *= r;
+    }
+    return acc;
+}
+
+double orc_sigma(const orc_sim *s, int d, double X)
+{
+    double L, del = depth(s, d, X, &L);
+    return sigma_of_depth(s, d, del, L);
+}
+
+/* Eq. (alpha): alpha_d = exp(-(1/v) Phi_d), with damping_scale = 1/v (c = 1). */
+double orc_alpha_axis(const orc_sim *s, int d, double X)
+{
+    double L, del = depth(s, d, X, &L);
+    return exp(-s->p.damping_scale * phi_of_depth(s, d, del, L));
+}
+
+/* Current-damping factor at a sample with grid coordinates X[3] (in-plane axes only).
+ *   mode 0: alpha = 0 anywhere in the PML (standard Berenger PML, no source there);
+ *   mode 1: alpha = 1 (undamped deposition);
+ *   mode 2: Eq. (alpha); in edges and corners the product of the per-axis factors
+ *           (reading: reduces to Eq. (alpha) on a face). */
+double orc_alpha(const orc_sim *s, const double X[3])
+{
+    int mode = s->p.alpha_mode;
+    if (mode == 1) return 1.0;
+    double a = 1.0;
+    for (int d = 0; d < s->p.dim; ++d) {
+        double L, del = depth(s, d, X[d], &L);
+        if (mode == 0) { if (del > 0.0) return 0.0; }
+        else a *= exp(-s->p.damping_scale * phi_of_depth(s, d, del, L));
+    }
+    return a;
+}
+
+/* Exponential time-differencing factors for dF/dt = -sig F + rhs over tau:
+ * F <- e F + g rhs with e = exp(-sig tau), g = (1 - e)/sig (g = tau when sig = 0).
+ * Reading of "the usual FDTD discretization" of Sec. II.B (Berenger's scheme). */
+static void expfac(double sig, double tau, double *e, double *g)
+{
+    if (sig == 0.0) { *e = 1.0; *g = tau; return; }
+    *e = exp(-sig * tau);
+    *g = -expm1(-sig * tau) / sig;
+}
+
+/* ---------------------------------------------------------------- indexing */
+
+static int nvalid(const orc_sim *s, int d, int stag)
+{
+    if (d >= s->p.dim) return 1;
+    return s->M[d] + (stag ? 0 : 1);
+}
+
+/* component c: 0..2 = E_x,E_y,E_z ; 3..5 = B_x,B_y,B_z.  stagger along axis d. */
+static int stag_of(int c, int d)
+{
+    int a = c % 3;
+    if (c < 3) return d == a;   /* E_a: half-integer along a */
+    return d != a;              /* B_a: half-integer across a */
+}
+
+static size_t idx3(const orc_sim *s, int i, int j, int k)
+{
+    return ((size_t)k * s->nn[1] + (size_t)j) * s->nn[0] + (size_t)i;
+}
+
+static int in_range(const orc_sim *s, int c, const int ii[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        if (ii[d] < 0 || ii[d] >= nvalid(s, d, stag_of(c, d))) return 0;
+    }
+    return 1;
+}
+
+static double total_at(const orc_sim *s, int c, const int ii[3])
+{
+    if (!in_range(s, c, ii)) return 0.0;
+    size_t q = idx3(s, ii[0], ii[1], ii[2]);
+    return s->F[2 * c][q] + s->F[2 * c + 1][q];
+}
+
+/* grid coordinate of sample ii of component c (J_a shares E_a's positions) */
+static void sample_pos(int c, const int ii[3], double X[3])
+{
+    for (int d = 0; d < 3; ++d) X[d] = ii[d] + (stag_of(c, d) ? 0.5 : 0.0);
+}
+
+/* ---------------------------------------------------------------- lifecycle */
+
+orc_sim *orc_create(const orc_params *p)
+{
+    if (p->dim != 2 && p->dim != 3) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->p = *p;
+    for (int d = 0; d < 3; ++d) {
+        if (d < p->dim) { s->M[d] = p->n[d] + p->pml[d][0] + p->pml[d][1]; s->nn[d] = s->M[d] + 1; }
+        else { s->M[d] = 0; s->nn[d] = 1; }
+    }
+    s->nsamp = (size_t)s->nn[0] * s->nn[1] * s->nn[2];
+    for (int q = 0; q < NPART; ++q) s->F[q] = (double *)calloc(s->nsamp, sizeof(double));
+    for (int a = 0; a < 3; ++a) s->J[a] = (double *)calloc(s->nsamp, sizeof(double));
+    s->rho_static = (double *)calloc(s->nsamp, sizeof(double));
+    s->cap = 0; s->np = 0; s->next_id = 0;
+    return s;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    for (int q = 0; q < NPART; ++q) free(s->F[q]);
+    for (int a = 0; a < 3; ++a) free(s->J[a]);
+    free(s->rho_static); free(s->X); free(s->U); free(s->W); free(s->id);
+    free(s);
+}
+
+size_t orc_num_samples(const orc_sim *s) { return s->nsamp; }
+long orc_num_particles(const orc_sim *s) { return s->np; }
+long orc_step_count(const orc_sim *s) { return s->step; }
+
+static void reserve(orc_sim *s, long n)
+{
+    if (n <= s->cap) return;
+    long c = s->cap ? s->cap : 16;
+    while (c < n) c *= 2;
+    s->X = (double *)realloc(s->X, sizeof(double) * 3 * c);
+    s->U = (double *)realloc(s->U, sizeof(double) * 3 * c);
+    s->W = (double *)realloc(s->W, sizeof(double) * c);
+    s->id = (long *)realloc(s->id, sizeof(long) * c);
+    s->cap = c;
+}
+
+/* charge density of one particle at the nodes, added with factor `sign` into rho */
+static void deposit_rho(const orc_sim *s, const double X[3], double qw, double sign, double *rho)
+{
+    double dV = 1.0;
+    for (int d = 0; d < s->p.dim; ++d) dV *= s->p.dx[d];
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < s->p.dim; ++d) { lo[d] = (int)floor(X[d]) - 3; hi[d] = (int)floor(X[d]) + 4; }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+    for (int j = lo[1]; j <= hi[1]; ++j)
+    for (int i = lo[0]; i <= hi[0]; ++i) {
+        int ii[3] = {i, j, k};
+        double w = 1.0;
+        for (int d = 0; d < s->p.dim; ++d) w *= orc_shape(s->p.shape_order, X[d] - ii[d]);
+        if (w == 0.0) continue;
+        int ok = 1;
+        for (int d = 0; d < 3; ++d) if (ii[d] < 0 || ii[d] >= s->nn[d]) ok = 0;
+        if (!ok) continue;
+        rho[idx3(s, i, j, k)] += sign * qw * w / dV;
+    }
+}
+
+/* Adds particles given physical positions x (n x dim, origin at the physical-box
+ * corner), momenta u = gamma v (n x 3) and weights w.  Each one also gets a
+ * motionless opposite-charge partner at its initial position (App. A.1), which
+ * enters only the charge density. */
+int orc_add_particles(orc_sim *s, long n, const double *x, const double *u, const double *w)
+{
+    reserve(s, s->np + n);
+    for (long t = 0; t < n; ++t) {
+        long q = s->np++;
+        for (int d = 0; d < 3; ++d) {
+            s->X[3 * q + d] = d < s->p.dim ? x[s->p.dim * t + d] / s->p.dx[d] + s->p.pml[d][0] : 0.0;
+            s->U[3 * q + d] = u[3 * t + d];
+        }
+        s->W[q] = w[t];
+        s->id[q] = s->next_id++;
+        deposit_rho(s, &s->X[3 * q], s->p.charge * w[t], -1.0, s->rho_static);
+    }
+    return 0;
+}
+
+/* Replaces the particle list (grid coordinates X, n x 3; ids given), without
+ * touching the static partner density. */
+int orc_set_particles(orc_sim *s, long n, const long *id, const double *X, const double *u, const double *w)
+{
+    s->np = 0;
+    reserve(s, n);
+    for (long t = 0; t < n; ++t) {
+        for (int d = 0; d < 3; ++d) { s->X[3 * t + d] = X[3 * t + d]; s->U[3 * t + d] = u[3 * t + d]; }
+        s->W[t] = w[t]; s->id[t] = id[t];
+        if (id[t] >= s->next_id) s->next_id = id[t] + 1;
+    }
+    s->np = n;
+    return 0;
+}
+
+void orc_get_particles(const orc_sim *s, long *id, double *X, double *u, double *w)
+{
+    for (long t = 0; t < s->np; ++t) {
+        id[t] = s->id[t]; w[t] = s->W[t];
+        for (int d = 0; d < 3; ++d) { X[3 * t + d] = s->X[3 * t + d]; u[3 * t + d] = s->U[3 * t + d]; }
+    }
+}
+
+/* fields as 12 split parts, each nsamp doubles, order
+ * E_xy E_xz E_yz E_yx E_zx E_zy B_xy B_xz B_yz B_yx B_zx B_zy */
+void orc_get_fields(const orc_sim *s, double *out)
+{
+    for (int q = 0; q < NPART; ++q) memcpy(out + q * s->nsamp, s->F[q], sizeof(double) * s->nsamp);
+}
+
+void orc_set_fields(orc_sim *s, const double *in)
+{
+    for (int q = 0; q < NPART; ++q) memcpy(s->F[q], in + q * s->nsamp, sizeof(double) * s->nsamp);
+}
+
+void orc_get_current(const orc_sim *s, double *out)
+{
+    for (int a = 0; a < 3; ++a) memcpy(out + a * s->nsamp, s->J[a], sizeof(double) * s->nsamp);
+}
+
+void orc_get_rho_static(const orc_sim *s, double *out)
+{
+    memcpy(out, s->rho_static, sizeof(double) * s->nsamp);
+}
+
+void orc_set_rho_static(orc_sim *s, const double *in)
+{
+    memcpy(s->rho_static, in, sizeof(double) * s->nsamp);
+}
+
+/* ---------------------------------------------------------------- particles */
+
+/* Field gather: each total component (sum of its split parts, Eq. (MaxwellSum)) at
+ * grid position X, with the same-order B-spline at that component's staggered
+ * sample positions.  Samples outside the grid (beyond the PEC walls) count as 0.
+ * (Reading: the paper does not spell out the gather.) */
+void orc_gather(const orc_sim *s, const double X[3], double EB[6])
+{
+    int m = s->p.shape_order;
+    for (int c = 0; c < 6; ++c) {
+        double acc = 0.0;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int d = 0; d < s->p.dim; ++d) { lo[d] = (int)floor(X[d]) - 3; hi[d] = (int)floor(X[d]) + 3; }
+        for (int k = lo[2]; k <= hi[2]; ++k)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+            int ii[3] = {i, j, k};
+            double wgt = 1.0;
+            for (int d = 0; d < s->p.dim; ++d)
+                wgt *= orc_shape(m, X[d] - (ii[d] + (stag_of(c, d) ? 0.5 : 0.0)));
+            if (wgt == 0.0) continue;
+            acc += wgt * total_at(s, c, ii);
+        }
+        EB[c] = acc;
+    }
+}
+
+/* Relativistic Boris rotation (Boris 1970), u = gamma v:
+ * half electric kick, magnetic rotation, half electric kick. */
+void orc_boris(double qdt_2m, const double E[3], const double B[3], double u[3])
+{
+    double um[3], t[3], up[3], sv[3], cr[3];
+    for (int d = 0; d < 3; ++d) um[d] = u[d] + qdt_2m * E[d];
+    double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int d = 0; d < 3; ++d) t[d] = qdt_2m * B[d] / gm;
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int d = 0; d < 3; ++d) sv[d] = 2.0 * t[d] / (1.0 + t2);
+    cr[0] = um[1] * t[2] - um[2] * t[1];
+    cr[1] = um[2] * t[0] - um[0] * t[2];
+    cr[2] = um[0] * t[1] - um[1] * t[0];
+    for (int d = 0; d < 3; ++d) up[d] = um[d] + cr[d];
+    cr[0] = up[1] * sv[2] - up[2] * sv[1];
+    cr[1] = up[2] * sv[0] - up[0] * sv[2];
+    cr[2] = up[0] * sv[1] - up[1] * sv[0];
+    for (int d = 0; d < 3; ++d) u[d] = um[d] + cr[d] + qdt_2m * E[d];
+}
+
+static void add_J(orc_sim *s, int a, const int ii[3], double v, double *const J[3])
+{
+    if (!in_range(s, a, ii)) return;   /* guard samples beyond the walls are dropped */
+    J[a][idx3(s, ii[0], ii[1], ii[2])] += v;
+}
+
+/* Esirkepov charge-conserving deposition (Esirkepov 2001, used in App. A) of one
+ * particle of charge qw moving X0 -> X1 during dt, into J[3] (J_a at E_a's samples).
+ * vz is its z velocity, used only in 2D (2D3V current along the invariant axis).
+ *   2D: W_x = dSx (S0y + S1y)/2, W_y = dSy (S0x + S1x)/2,
+ *       W_z = S0xS0y/3 + S1xS0y/6 + S0xS1y/6 + S1xS1y/3;
+ *   3D: W_x = dSx (S0yS0z/3 + S1yS0z/6 + S0yS1z/6 + S1yS1z/3) and cyclic.
+ * J_a(i_a + 1/2) - J_a(i_a - 1/2) = -qw W_a / (dt * product of the other dx),
+ * accumulated from zero at the low end of the stencil. */
+void orc_deposit(orc_sim *s, const double X0[3], const double X1[3], double vz, double qw, double *const J[3])
+{
+    int dim = s->p.dim, m = s->p.shape_order;
+    enum { WN = 12 };
+    int lo[3] = {0, 0, 0}, n[3] = {1, 1, 1};
+    double S0[3][WN], S1[3][WN], DS[3][WN];
+    for (int d = 0; d < 3; ++d) {
+        for (int t = 0; t < WN; ++t) { S0[d][t] = 1.0; S1[d][t] = 1.0; DS[d][t] = 0.0; }
+    }
+    for (int d = 0; d < dim; ++d) {
+        double mn = X0[d] < X1[d] ? X0[d] : X1[d];
+        double mx = X0[d] < X1[d] ? X1[d] : X0[d];
+        lo[d] = (int)floor(mn) - 3;
+        n[d] = (int)floor(mx) + 4 - lo[d] + 1;
+        if (n[d] > WN) n[d] = WN;  /* moves are below one cell per step */
+        for (int t = 0; t < n[d]; ++t) {
+            S0[d][t] = orc_shape(m, X0[d] - (lo[d] + t));
+            S1[d][t] = orc_shape(m, X1[d] - (lo[d] + t));
+            DS[d][t] = S1[d][t] - S0[d][t];
+        }
+    }
+    double dV = 1.0;
+    for (int d = 0; d < dim; ++d) dV *= s->p.dx[d];
+    double dt = s->p.dt;
+    if (dim == 2) {
+        double cx = qw / (s->p.dx[1] * dt), cy = qw / (s->p.dx[0] * dt);
+        for (int tj = 0; tj < n[1]; ++tj) {           /* J_x: running sum along x */
+            double acc = 0.0;
+            for (int ti = 0; ti < n[0]; ++ti) {
+                double Wx = 0.5 * DS[0][ti] * (S0[1][tj] + S1[1][tj]);
+                acc -= cx * Wx;
+                int ii[3] = {lo[0] + ti, lo[1] + tj, 0};
+                if (acc != 0.0) add_J(s, 0, ii, acc, J);
+            }
+        }
+        for (int ti = 0; ti < n[0]; ++ti) {           /* J_y: running sum along y */
+            double acc = 0.0;
+            for (int tj = 0; tj < n[1]; ++tj) {
+                double Wy = 0.5 * DS[1][tj] * (S0[0][ti] + S1[0][ti]);
+                acc -= cy * Wy;
+                int ii[3] = {lo[0] + ti, lo[1] + tj, 0};
+                if (acc != 0.0) add_J(s, 1, ii, acc, J);
+            }
+        }
+        for (int tj = 0; tj < n[1]; ++tj)              /* J_z: path-averaged shape */
+        for (int ti = 0; ti < n[0]; ++ti) {
+            double Wz = S0[0][ti] * S0[1][tj] / 3.0 + S1[0][ti] * S0[1][tj] / 6.0
+                      + S0[0][ti] * S1[1][tj] / 6.0 + S1[0][ti] * S1[1][tj] / 3.0;
+            if (Wz == 0.0) continue;
+            int ii[3] = {lo[0] + ti, lo[1] + tj, 0};
+            add_J(s, 2, ii, qw * vz * Wz / dV, J);
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            int b = (a + 1) % 3, c = (a + 2) % 3;
+            double coef = qw / (s->p.dx[b] * s->p.dx[c] * dt);
+            for (int tc = 0; tc < n[c]; ++tc)
+            for (int tb = 0; tb < n[b]; ++tb) {
+                double avg = S0[b][tb] * S0[c][tc] / 3.0 + S1[b][tb] * S0[c][tc] / 6.0
+                           + S0[b][tb] * S1[c][tc] / 6.0 + S1[b][tb] * S1[c][tc] / 3.0;
+                double acc = 0.0;
+                for (int ta = 0; ta < n[a]; ++ta) {
+                    acc -= coef * DS[a][ta] * avg;
+                    int ii[3];
+                    ii[a] = lo[a] + ta; ii[b] = lo[b] + tb; ii[c] = lo[c] + tc;
+                    if (acc != 0.0) add_J(s, a, ii, acc, J);
+                }
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------- fields */
+
+/* Levi-Civita symbol for a permutation of (0,1,2) */
+static int levi(int a, int b, int c)
+{
+    if (a == b || b == c || a == c) return 0;
+    return ((a + 1) % 3 == b) ? 1 : -1;
+}
+
+/* Fraction of J_a that enters split part E_ab (derivative axis b; c the third axis).
+ * The paper's z-face equations put the whole current of the transverse components
+ * into the part damped by sigma_z and the longitudinal one into the (undamped)
+ * E_z.  Reading for every face, edge and corner: weight sigma_b/(sigma_b+sigma_c);
+ * where both vanish the whole current goes to the part with b = a+1 (mod 3); there
+ * both parts are undamped, so only their sum matters. */
+static double source_weight(int a, int b, double sb, double sc)
+{
+    if (sb + sc > 0.0) return sb / (sb + sc);
+    return (b == (a + 1) % 3) ? 1.0 : 0.0;
+}
+
+/* Advance every split part of E (is_e = 1, with the damped current) or B (is_e = 0)
+ * by tau.  For part F_ab of component a (b the derivative axis):
+ *   dE_ab/dt =  eps_abc d_b B_c - sigma_b E_ab - w_ab alpha J_a    (Eq. MaxwellE)
+ *   dB_ab/dt = -eps_abc d_b E_c - sigma_b B_ab                     (Eq. MaxwellB)
+ * with sigma_b taken at the sample's coordinate along b, integrated with the
+ * exponential factors of expfac().  In 2D the z derivatives vanish. */
+static void advance(orc_sim *s, int is_e, double tau)
+{
+    for (int a = 0; a < 3; ++a) {
+        int c_self = is_e ? a : 3 + a;
+        for (int side = 0; side < 2; ++side) {
+            int b = (a + 1 + side) % 3;        /* derivative axis of this part */
+            int c = 3 - a - b;                 /* the other field's component */
+            int ci = is_e ? 3 + c : c;         /* B_c for E parts, E_c for B parts */
+            double eps = (double)levi(a, b, c);
+            double *Fp = s->F[2 * c_self + side];
+            int nv[3];
+            for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(c_self, d));
+            for (int k = 0; k < nv[2]; ++k)
+            for (int j = 0; j < nv[1]; ++j)
+            for (int i = 0; i < nv[0]; ++i) {
+                int ii[3] = {i, j, k};
+                if (is_e) {   /* PEC: tangential E on the outer walls stays 0 */
+                    int on_wall = 0;
+                    for (int d = 0; d < s->p.dim; ++d)
+                        if (d != a && (ii[d] == 0 || ii[d] == s->M[d])) on_wall = 1;
+                    if (on_wall) continue;
+                }
+                double X[3];
+                sample_pos(c_self, ii, X);
+                double deriv = 0.0;
+                if (b < s->p.dim) {
+                    int ip[3] = {i, j, k}, im[3] = {i, j, k};
+                    if (is_e) { im[b] -= 1; }  /* B_c sits half a cell off along b */
+                    else { ip[b] += 1; }       /* E_c sits half a cell off along b */
+                    deriv = (total_at(s, ci, ip) - total_at(s, ci, im)) / s->p.dx[b];
+                }
+                double sb = orc_sigma(s, b, X[b]);
+                double e, g;
+                expfac(sb, tau, &e, &g);
+                size_t q = idx3(s, i, j, k);
+                double rhs = (is_e ? eps : -eps) * deriv;
+                if (is_e) {
+                    double sc = orc_sigma(s, c, X[c]);
+                    double w = source_weight(a, b, sb, sc);
+                    rhs -= w * s->J[a][q];    /* J already multiplied by alpha */
+                }
+                Fp[q] = e * Fp[q] + g * rhs;
+            }
+        }
+    }
+}
+
+/* J_a <- alpha J_a at J_a's samples (Eq. MaxwellE source term alpha j). */
+static void damp_current(orc_sim *s)
+{
+    for (int a = 0; a < 3; ++a) {
+        int nv[3];
+        for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(a, d));
+        for (int k = 0; k < nv[2]; ++k)
+        for (int j = 0; j < nv[1]; ++j)
+        for (int i = 0; i < nv[0]; ++i) {
+            int ii[3] = {i, j, k};
+            double X[3];
+            sample_pos(a, ii, X);
+            s->J[a][idx3(s, i, j, k)] *= orc_alpha(s, X);
+        }
+    }
+}
+
+/* public single-phase entry points, for unit pins */
+void orc_damp_current(orc_sim *s) { damp_current(s); }
+void orc_advance_B(orc_sim *s, double tau) { advance(s, 0, tau); }
+void orc_advance_E(orc_sim *s, double tau) { advance(s, 1, tau); }
+void orc_zero_current(orc_sim *s) { for (int a = 0; a < 3; ++a) memset(s->J[a], 0, sizeof(double) * s->nsamp); }
+void orc_set_current(orc_sim *s, const double *in)
+{
+    for (int a = 0; a < 3; ++a) memcpy(s->J[a], in + a * s->nsamp, sizeof(double) * s->nsamp);
+}
+void orc_deposit_into(orc_sim *s, const double X0[3], const double X1[3], double vz, double qw)
+{
+    orc_deposit(s, X0, X1, vz, qw, s->J);
+}
+
+/* One PIC step: E^n, B^n, X^n, u^{n-1/2}  ->  E^{n+1}, B^{n+1}, X^{n+1}, u^{n+1/2}.
+ *  1. per particle: gather E^n, B^n at X^n (totals), Boris push (if enabled),
+ *     X^{n+1} = X^n + dt u/gamma, Esirkepov deposit of X^n -> X^{n+1};
+ *     particles ending outside the PEC box are removed after depositing;
+ *  2. J <- alpha J (Eq. alpha / mode);
+ *  3. B += dt/2 from E^n; E += dt from B^{n+1/2} and alpha J; B += dt/2 from E^{n+1}. */
+void orc_step(orc_sim *s, int nsteps)
+{
+    int dim = s->p.dim;
+    double qdt_2m = s->p.charge * s->p.dt / (2.0 * s->p.mass);
+    for (int it = 0; it < nsteps; ++it) {
+        orc_zero_current(s);
+        long keep = 0;
+        for (long t = 0; t < s->np; ++t) {
+            double *X = &s->X[3 * t], *u = &s->U[3 * t];
+            if (s->p.push) {
+                double EB[6];
+                orc_gather(s, X, EB);
+                orc_boris(qdt_2m, EB, EB + 3, u);
+            }
+            double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            double X1[3] = {X[0], X[1], X[2]};
+            for (int d = 0; d < dim; ++d) X1[d] = X[d] + s->p.dt * u[d] / gam / s->p.dx[d];
+            orc_deposit(s, X, X1, u[2] / gam, s->p.charge * s->W[t], s->J);
+            int out = 0;
+            for (int d = 0; d < dim; ++d) if (X1[d] < 0.0 || X1[d] >= (double)s->M[d]) out = 1;
+            if (out) continue;
+            for (int d = 0; d < 3; ++d) { s->X[3 * keep + d] = X1[d]; s->U[3 * keep + d] = u[d]; }
+            s->W[keep] = s->W[t]; s->id[keep] = s->id[t];
+            ++keep;
+        }
+        s->np = keep;
+        damp_current(s);
+        advance(s, 0, 0.5 * s->p.dt);
+        advance(s, 1, s->p.dt);
+        advance(s, 0, 0.5 * s->p.dt);
+        s->step++;
+    }
+}
+
+/* ---------------------------------------------------------------- diagnostics */
+
+static int in_physical(const orc_sim *s, const double X[3])
+{
+    for (int d = 0; d < s->p.dim; ++d) {
+        if (X[d] < (double)s->p.pml[d][0] || X[d] > (double)(s->p.pml[d][0] + s->p.n[d])) return 0;
+    }
+    return 1;
+}
+
+/* out[0] U over samples in the physical box, out[1] U over the other samples,
+ * out[2] max |div E - rho| and out[3] its RMS over interior nodes (strictly inside
+ * the physical box), out[4] max |rho of the moving particles|, out[5] particle
+ * count, out[6] step.  U = 1/2 sum (E^2 + B^2) dV over each component's samples. */
+void orc_diagnose(const orc_sim *s, double out[7])
+{
+    double dV = 1.0;
+    for (int d = 0; d < s->p.dim; ++d) dV *= s->p.dx[d];
+    double ui = 0.0, up = 0.0;
+    for (int c = 0; c < 6; ++c) {
+        int nv[3];
+        for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(c, d));
+        for (int k = 0; k < nv[2]; ++k)
+        for (int j = 0; j < nv[1]; ++j)
+        for (int i = 0; i < nv[0]; ++i) {
+            int ii[3] = {i, j, k};
+            double X[3], v = total_at(s, c, ii);
+            sample_pos(c, ii, X);
+            if (in_physical(s, X)) ui += 0.5 * v * v * dV; else up += 0.5 * v * v * dV;
+        }
+    }
+    double *rho = (double *)calloc(s->nsamp, sizeof(double));
+    for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * s->W[t], 1.0, rho);
+    double rmax = 0.0;
+    for (size_t q = 0; q < s->nsamp; ++q) if (fabs(rho[q]) > rmax) rmax = fabs(rho[q]);
+    double gmax = 0.0, gsum = 0.0;
+    long cnt = 0;
+    for (int k = 0; k < s->nn[2]; ++k)
+    for (int j = 0; j < s->nn[1]; ++j)
+    for (int i = 0; i < s->nn[0]; ++i) {
+        int ii[3] = {i, j, k};
+        int inner = 1;
+        for (int d = 0; d < s->p.dim; ++d)
+            if (ii[d] <= s->p.pml[d][0] || ii[d] >= s->p.pml[d][0] + s->p.n[d]) inner = 0;
+        if (!inner) continue;
+        double div = 0.0;
+        for (int d = 0; d < s->p.dim; ++d) {
+            int im[3] = {i, j, k};
+            im[d] -= 1;
+            div += (total_at(s, d, ii) - total_at(s, d, im)) / s->p.dx[d];
+        }
+        size_t q = idx3(s, i, j, k);
+        double r = div - rho[q] - s->rho_static[q];
+        if (fabs(r) > gmax) gmax = fabs(r);
+        gsum += r * r;
+        ++cnt;
+    }
+    free(rho);
+    out[0] = ui; out[1] = up; out[2] = gmax; out[3] = cnt ? sqrt(gsum / cnt) : 0.0;
+    out[4] = rmax; out[5] = (double)s->np; out[6] = (double)s->step;
+}
+
+/* charge density of the current particles (without the static partners) */
+void orc_rho(const orc_sim *s, double *rho)
+{
+    memset(rho, 0, sizeof(double) * s->nsamp);
+    for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * s->W[t], 1.0, rho);
+}

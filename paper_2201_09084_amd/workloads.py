@@ -1,0 +1,270 @@
+"""Seeded synthetic workloads: run parameters and input particles.
+
+This module holds only parameter sets and seeded random inputs, none of the
+method's arithmetic, so that the HIP path and the FP64 oracle are fed exactly the
+same numbers.  Normalised units: c = eps0 = mu0 = 1, cell size 1, q/m = -1
+(electrons) unless stated.
+
+The five workloads mirror the paper's problem statement (single-particle exit of
+App. A.1 / Sec. III; beams crossing the PML as in Sec. IV) at the sizes listed in
+each builder's docstring.  The paper uses no dataset; every input is synthetic.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+ALPHA_ZERO, ALPHA_ONE, ALPHA_DAMPED = 0, 1, 2
+
+
+@dataclasses.dataclass
+class SimConfig:
+    dim: int = 2
+    n: tuple = (128, 128, 1)
+    pml: tuple = ((10, 10), (10, 10), (0, 0))
+    dx: tuple = (1.0, 1.0, 1.0)
+    dt: float = 0.7
+    shape_order: int = 1
+    alpha_mode: int = ALPHA_DAMPED
+    damping_scale: float = 1.0          # 1/v in the damping coefficient; v = c
+    sigma_coef: tuple = ((0.0, 0.0, 0.0, 3.2),) * 3   # sigma/eps0 = sum a_k (depth/L)^k
+    push: int = 1
+    charge: float = -1.0
+    mass: float = 1.0
+    precision: int = 64
+    sort_interval: int = 0
+    tile: tuple = (0, 0, 0)
+    max_particles: int = 0
+
+    def total_cells(self) -> int:
+        t = 1
+        for d in range(self.dim):
+            t *= self.n[d] + self.pml[d][0] + self.pml[d][1]
+        return t
+
+    def nodes(self):
+        return [self.n[d] + self.pml[d][0] + self.pml[d][1] + 1 if d < self.dim else 1
+                for d in range(3)]
+
+    def pml_cells(self) -> int:
+        inner = 1
+        for d in range(self.dim):
+            inner *= self.n[d]
+        return self.total_cells() - inner
+
+    def replace(self, **kw) -> "SimConfig":
+        return dataclasses.replace(self, **kw)
+
+
+def cubic_profile(sigma_max: float = 3.2):
+    """sigma/eps0 = sigma_max (depth/L)^3 on every axis."""
+    return ((0.0, 0.0, 0.0, sigma_max),) * 3
+
+
+def paper_conductivity_profile(L: int, dx: float = 1.0, scale_cells: float = 6.0):
+    """The quadratic profile sigma = (4 eps0 c/dx)(z/(scale dx))^2 of App. A
+    (scale 6 for the single-particle runs, 10 for the cavity run), written in the
+    (depth/L)^k form: a_2 = (4/dx) (L/scale)^2."""
+    a2 = 4.0 / dx * (L / scale_cells) ** 2
+    return ((0.0, 0.0, a2),) * 3
+
+
+@dataclasses.dataclass
+class Particles:
+    x: np.ndarray      # (n, dim) physical positions, origin at the physical-box corner
+    u: np.ndarray      # (n, 3) momenta per unit mass, u = gamma v
+    w: np.ndarray      # (n,) weights
+
+    def __len__(self):
+        return len(self.w)
+
+
+def _momentum(gamma, theta):
+    beta = np.sqrt(1.0 - 1.0 / np.asarray(gamma, dtype=np.float64) ** 2)
+    g = np.asarray(gamma, dtype=np.float64)
+    return np.stack([g * beta * np.cos(theta), g * beta * np.sin(theta), np.zeros_like(g)], axis=-1)
+
+
+# ---------------------------------------------------------------- workload 1
+def single_particle_config(precision: int = 64, alpha_mode: int = ALPHA_DAMPED, n=128, pml=10,
+                           order: int = 1, push: int = 1, extend_x: int = 1) -> SimConfig:
+    """2D 128x128 cells, dx = dy = 1, c dt = 0.7, 10-cell PML on all sides with a cubic
+    conductivity profile, linear shape, FP64.  ``extend_x`` > 1 widens the physical box
+    along +x for the reference run of Sec. III (the particle then never exits)."""
+    return SimConfig(dim=2, n=(n * extend_x, n, 1), pml=((pml, pml), (pml, pml), (0, 0)),
+                     dt=0.7, shape_order=order, alpha_mode=alpha_mode, damping_scale=1.0,
+                     sigma_coef=cubic_profile(3.2), push=push, precision=precision)
+
+
+def single_particle(cfg: SimConfig, beta: float = 0.9, theta_deg: float = 0.0,
+                    start: Optional[tuple] = None, w: float = 1.0) -> Particles:
+    """One macroparticle (q = -1, q/m = -1) at the physical-box centre, moving at
+    beta c toward +x (rotated by theta toward +y)."""
+    if start is None:
+        start = (cfg.n[1] / 2.0, cfg.n[1] / 2.0) if cfg.dim == 2 else (cfg.n[1] / 2.0,) * 3
+    gamma = 1.0 / math.sqrt(1.0 - beta * beta)
+    u = _momentum(np.array([gamma]), np.array([math.radians(theta_deg)]))
+    x = np.array([start[: cfg.dim]], dtype=np.float64)
+    return Particles(x=x, u=u, w=np.array([w]))
+
+
+# ---------------------------------------------------------------- workload 2
+def beam2d_config(precision: int = 32, n: int = 1024, pml: int = 16) -> SimConfig:
+    """2D 1024x1024 grid, 16-cell PML, quadratic shape, c dt = 0.7, FP32."""
+    return SimConfig(dim=2, n=(n, n, 1), pml=((pml, pml), (pml, pml), (0, 0)), dt=0.7,
+                     shape_order=2, alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
+                     sigma_coef=cubic_profile(3.2), push=1, precision=precision)
+
+
+def beam2d_particles(cfg: SimConfig, n_particles: int = 1 << 20, sigma: float = 20.0,
+                     seed: int = 1002, w: float = 1e-4) -> Particles:
+    """Gaussian beam (rms `sigma` cells) at the box centre; gamma uniform in [1.5, 10];
+    direction uniform in [0, 30] degrees from +x toward +y."""
+    rng = np.random.default_rng(seed)
+    cx, cy = cfg.n[0] / 2.0, cfg.n[1] / 2.0
+    x = np.empty((n_particles, 2))
+    x[:, 0] = rng.normal(cx, sigma, n_particles)
+    x[:, 1] = rng.normal(cy, sigma, n_particles)
+    x[:, 0] = np.clip(x[:, 0], 1.0, cfg.n[0] - 1.0)
+    x[:, 1] = np.clip(x[:, 1], 1.0, cfg.n[1] - 1.0)
+    gamma = rng.uniform(1.5, 10.0, n_particles)
+    theta = np.radians(rng.uniform(0.0, 30.0, n_particles))
+    return Particles(x=x, u=_momentum(gamma, theta), w=np.full(n_particles, w))
+
+
+# ---------------------------------------------------------------- workload 4
+def beam3d_config(precision: int = 32, n: int = 256, pml: int = 12) -> SimConfig:
+    """3D 256^3 grid, 12-cell PML on all faces, linear shape, c dt = 0.5, FP32."""
+    return SimConfig(dim=3, n=(n, n, n), pml=((pml, pml),) * 3, dt=0.5, shape_order=1,
+                     alpha_mode=ALPHA_DAMPED, damping_scale=1.0, sigma_coef=cubic_profile(3.2),
+                     push=1, precision=precision)
+
+
+def beam3d_particles(cfg: SimConfig, seed: int = 1004, background_ppc: float = 1.0,
+                     n_beam: int = 65536, temperature: float = 1e-3) -> Particles:
+    """Thermal background at `background_ppc` particles per cell (uniform positions,
+    u ~ N(0, sqrt(T)) per component, w = 0.01) plus a beam of gamma = 5 electrons
+    moving along +z in a cylinder of radius 8 cells around the x-y centre,
+    z in [n/4, 3n/4], w = 0.04."""
+    rng = np.random.default_rng(seed)
+    n = cfg.n
+    nb = int(round(background_ppc * n[0] * n[1] * n[2]))
+    xb = rng.uniform(0.0, 1.0, (nb, 3)) * np.array(n[:3], dtype=np.float64)
+    ub = rng.normal(0.0, math.sqrt(temperature), (nb, 3))
+    r = 8.0 * np.sqrt(rng.uniform(0.0, 1.0, n_beam))
+    ph = rng.uniform(0.0, 2 * math.pi, n_beam)
+    xe = np.stack([n[0] / 2 + r * np.cos(ph), n[1] / 2 + r * np.sin(ph),
+                   rng.uniform(n[2] / 4, 3 * n[2] / 4, n_beam)], axis=1)
+    g = 5.0
+    ue = np.zeros((n_beam, 3))
+    ue[:, 2] = math.sqrt(g * g - 1.0)
+    x = np.concatenate([xb, xe])
+    u = np.concatenate([ub, ue])
+    w = np.concatenate([np.full(nb, 0.01), np.full(n_beam, 0.04)])
+    return Particles(x=x, u=u, w=w)
+
+
+# ---------------------------------------------------------------- workload 5
+def adjoint_config(precision: int = 32, n: int = 512, pml: int = 16) -> SimConfig:
+    """2D 512x512 grid, 16-cell PML, quadratic shape, c dt = 0.7."""
+    return SimConfig(dim=2, n=(n, n, 1), pml=((pml, pml), (pml, pml), (0, 0)), dt=0.7,
+                     shape_order=2, alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
+                     sigma_coef=cubic_profile(3.2), push=1, precision=precision)
+
+
+def adjoint_particles(cfg: SimConfig, n_particles: int = 4096, seed: int = 1005) -> Particles:
+    """Gaussian bunch (rms 4 cells) centred 64 cells before the +x interface,
+    gamma = 3, 10 degrees from +x."""
+    rng = np.random.default_rng(seed)
+    x = np.empty((n_particles, 2))
+    x[:, 0] = rng.normal(cfg.n[0] - 64.0, 4.0, n_particles)
+    x[:, 1] = rng.normal(cfg.n[1] / 2.0, 4.0, n_particles)
+    return Particles(x=x, u=_momentum(np.full(n_particles, 3.0), np.full(n_particles, math.radians(10.0))),
+                     w=np.full(n_particles, 1.0 / n_particles))
+
+
+# ---------------------------------------------------------------- workload 3
+@dataclasses.dataclass
+class BatchRun:
+    cfg: SimConfig
+    particles: Particles
+    theta_deg: float
+    gamma: float
+
+
+def batch_runs(n_runs: int = 256, seed: int = 1003, steps_to_cross: int = 300,
+               nmin: int = 64, nmax: int = 512) -> List[BatchRun]:
+    """Independent single-particle exit runs: square grids N ~ U{nmin..nmax},
+    PML thickness ~ U{8..32}, incidence angle ~ U[0, 60] deg, ln gamma ~ U[ln 1.1, ln 20];
+    the particle starts so that it reaches the +x interface after `steps_to_cross`
+    steps (the fixed-crossing protocol of Sec. III)."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for _ in range(n_runs):
+        N = int(rng.integers(nmin, nmax + 1))
+        L = int(rng.integers(8, 33))
+        th = float(rng.uniform(0.0, 60.0))
+        g = float(math.exp(rng.uniform(math.log(1.1), math.log(20.0))))
+        cfg = SimConfig(dim=2, n=(N, N, 1), pml=((L, L), (L, L), (0, 0)), dt=0.7, shape_order=1,
+                        alpha_mode=ALPHA_DAMPED, damping_scale=1.0, sigma_coef=cubic_profile(3.2),
+                        push=1, precision=32)
+        beta = math.sqrt(1.0 - 1.0 / (g * g))
+        vx = beta * math.cos(math.radians(th))
+        x0 = max(4.0, N - steps_to_cross * cfg.dt * vx)
+        y0 = min(max(N / 2.0 - (N - x0) * math.tan(math.radians(th)), 4.0), N - 4.0)
+        runs.append(BatchRun(cfg=cfg, particles=single_particle(cfg, beta, th, start=(x0, y0)),
+                             theta_deg=th, gamma=g))
+    return runs
+
+
+# ---------------------------------------------------------------- random states
+def random_particles(cfg: SimConfig, n: int, seed: int, margin: float = 3.0,
+                     umax: float = 3.0, region=None) -> Particles:
+    """Uniformly placed particles over the whole grid including the PML (kept
+    `margin` cells away from the outer walls), momenta uniform in [-umax, umax]^3."""
+    rng = np.random.default_rng(seed)
+    lo = np.array([-cfg.pml[d][0] + margin for d in range(cfg.dim)])
+    hi = np.array([cfg.n[d] + cfg.pml[d][1] - margin for d in range(cfg.dim)])
+    if region is not None:
+        lo, hi = np.asarray(region[0], float), np.asarray(region[1], float)
+    x = lo + (hi - lo) * rng.uniform(0.0, 1.0, (n, cfg.dim))
+    u = rng.uniform(-umax, umax, (n, 3))
+    w = rng.uniform(0.5, 1.5, n)
+    return Particles(x=x, u=u, w=w)
+
+
+def random_split_fields(cfg: SimConfig, seed: int, amp: float = 1.0) -> np.ndarray:
+    """Random split-field state (12, nz, ny, nx) in the part order
+    Exy Exz Eyz Eyx Ezx Ezy Bxy Bxz Byz Byx Bzx Bzy.  In 2D the parts driven by the
+    invariant z axis are zero, as they are for any run that starts from E = B = 0.
+    Samples outside each component's extent, and tangential E on the outer walls,
+    are zero."""
+    rng = np.random.default_rng(seed)
+    nn = cfg.nodes()
+    shape = (nn[2], nn[1], nn[0])
+    F = amp * rng.uniform(-1.0, 1.0, (12,) + shape)
+    M = [nn[d] - 1 for d in range(3)]
+    for part in range(12):
+        comp = part // 2
+        a = comp % 3
+        b = (a + 1 + part % 2) % 3
+        is_e = comp < 3
+        if cfg.dim == 2 and b == 2:
+            F[part] = 0.0
+            continue
+        for d in range(cfg.dim):
+            stag = (d == a) if is_e else (d != a)
+            sl = [slice(None)] * 3
+            ax = 2 - d
+            if stag:
+                sl[ax] = slice(M[d], None)
+                F[part][tuple(sl)] = 0.0
+            elif is_e and d != a:
+                sl[ax] = 0
+                F[part][tuple(sl)] = 0.0
+                sl[ax] = M[d]
+                F[part][tuple(sl)] = 0.0
+    return F
