@@ -1,0 +1,176 @@
+"""Benchmark of the damped-current PML PIC step on one MI355X.
+
+Default workload: 2D 1024x1024 cells + 16-cell PML on all sides (cubic profile),
+1,048,576 electrons in a Gaussian beam (rms 20 cells, gamma in [1.5, 10], 0-30 deg
+toward +x), quadratic shape, FP32 fields and particles, c dt = 0.7; every step runs
+sort_particles (every 8 steps), gather_push + deposit_current, the alpha damping and
+update_yee_pml.  Inputs are seeded synthetic data, resident in HBM before timing.
+
+Prints one JSON line: particle-pushes/s over the timed steps (whole job), the cell
+update rate, the roofline of the dominant kernel (algorithmic bytes / its average
+duration from HIP events on the library's stream) and the FP64 CPU oracle timed on a
+bounded sample on the host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("particles.hip", "fields.hip", "common.h", "api.hip"):
+        with open(os.path.join(ROOT, "paper_2201_09084_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
+    """Algorithmic HBM bytes of one launch of a phase (each array read/written once)."""
+    dim = cfg.dim
+    cells = cfg.total_cells()
+    pml = cfg.pml_cells()
+    nsplit_e = 1 if dim == 2 else 3
+    if phase == "gather_push":
+        per = (4 + dim * esz + 3 * esz + esz) + (4 + dim * esz + 3 * esz)   # read + write
+        return per * pushes_per_launch
+    if phase == "update_yee_pml_E":
+        return cells * (3 + 3 + 3 + 3) * esz + pml * 2 * nsplit_e * esz     # E r+w, B r, J r
+    if phase == "update_yee_pml_B":
+        return cells * (3 + 3 + 3) * esz + pml * 2 * nsplit_e * esz         # B r+w, E r
+    return None
+
+
+def run_gpu(args, cfg, parts):
+    import torch
+    from paper_2201_09084_amd import binding as B
+
+    sim = B.PmlPic(cfg, max_particles=len(parts))
+    sim.add_particles(parts.x, parts.u, parts.w)
+    torch.cuda.synchronize()
+    if args.warmup:
+        sim.step(args.warmup)
+    d0 = sim.diagnose()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phases = sim.step_profiled(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1 = sim.diagnose(allow_nonfinite=True)
+    elapsed = t1 - t0
+    pushes = d1["n_pushes"] - d0["n_pushes"]
+    return sim, elapsed, pushes, phases, d0, d1
+
+
+def cpu_baseline(cfg, parts, n_steps):
+    import oracle
+    oracle.build.build(force=False)
+    o = oracle.OracleSim(cfg.replace(precision=64))
+    o.add_particles(parts.x, parts.u, parts.w)
+    t0 = time.perf_counter()
+    o.step(n_steps)
+    t1 = time.perf_counter()
+    return len(parts) * n_steps / (t1 - t0), t1 - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=["beam2d", "beam3d"], default="beam2d")
+    ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_09084_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.workload == "beam2d":
+        cfg = W.beam2d_config(precision=args.precision)
+        parts = W.beam2d_particles(cfg)
+        wl = {"workload": "beam2d", "grid": "1024x1024+16pml", "particles": len(parts),
+              "shape_order": 2, "steps_total": args.warmup + args.steps}
+    else:
+        cfg = W.beam3d_config(precision=args.precision)
+        parts = W.beam3d_particles(cfg)
+        wl = {"workload": "beam3d", "grid": "256^3+12pml", "particles": len(parts),
+              "shape_order": 1, "steps_total": args.warmup + args.steps}
+    print("bench: %s, %d particles, %d cells, fp%d; warmup %d, timed %d" %
+          (args.workload, len(parts), cfg.total_cells(), args.precision, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+
+    sim, elapsed, pushes, phases, d0, d1 = run_gpu(args, cfg, parts)
+    esz = 4 if args.precision == 32 else 8
+    cells = cfg.total_cells()
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = pushes / elapsed
+    print("bench: %.3f ms/step, %.3e pushes/s, phases %s" % (ms_per_step, value, phases),
+          file=sys.stderr, flush=True)
+
+    # dominant kernel: the phase with the largest total time
+    dom = max(phases.items(), key=lambda kv: kv[1][0])
+    name, (ms_total, launches) = dom
+    avg_s = ms_total / 1e3 / launches
+    roof = None
+    per_launch = algorithmic_bytes(cfg, name, pushes / max(1, phases.get("gather_push", (0, 1))[1]), esz)
+    if per_launch is not None:
+        ach = per_launch / avg_s / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(per_launch)}
+        tf = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tf):
+            with open(tf) as fh:
+                t = json.load(fh)
+            key = "%s/%s/fp%d" % (args.workload, name, args.precision)
+            if t.get("source_hash") == kernel_source_hash() and key in t.get("bytes_per_launch", {}):
+                roof["traffic"] = t["bytes_per_launch"][key]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_cpu = args.cpu_steps
+        v, secs = cpu_baseline(cfg, parts, n_cpu)
+        cpu = {"value": v, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+               "sample": "%d steps of the same workload from its initial state (%d particles), "
+                         "FP64 single-threaded C oracle, %.1f s" % (n_cpu, len(parts), secs)}
+
+    out = {
+        "metric": "PIC particle-pushes/s & Yee+PML cell-updates/s; FP32 vs FP64 at stated err",
+        "value": value,
+        "unit": "particle-pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == 32 else "f64",
+        "data": "synthetic",
+        "config": wl,
+        "cell_updates_per_s": cells * args.steps / elapsed,
+        "phases_ms": {k: round(v[0], 3) for k, v in phases.items()},
+        "gauss_residual_fp64": d1["gauss_max"],
+        "particles_left": d1["n_particles"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * pml_pic.h -- C ABI of the MI355X (gfx950) damped-current PML particle-in-cell step.
+ *
+ * Method: Lehe, Blelly, Giacomel, Jambunathan, Vay, "Absorption of charged particles
+ * in Perfectly-Matched-Layers by optimal damping of the deposited current".
+ *   - split-field Maxwell equations with the source -alpha j/eps0 in the PML:
+ *     Sec. II.A, Eqs. (MaxwellE), (MaxwellB), (MaxwellSum);
+ *   - damping coefficient alpha(z) = exp(-int_0^z sigma/(eps0 v) dz'): Sec. II.A,
+ *     Eq. (alpha), evaluated in closed form at nodes and cell centres (Sec. II.B);
+ *   - alpha = 0 (standard PML) and alpha = 1 (undamped deposition) comparison
+ *     schemes: Sec. I, Fig. 1 caption;
+ *   - Yee FDTD, Esirkepov charge-conserving deposition with B-spline shapes,
+ *     motionless opposite-charge partner, E = B = 0 at t = 0: Sec. II.B, App. A.
+ *
+ * Units are normalised: c = eps0 = mu0 = 1.  Node i along axis d sits at physical
+ * coordinate (i - pml[d][0]) * dx[d]; the physical box is [0, n[d] dx[d]] and the PML
+ * lies outside it, closed by PEC walls (tangential E = 0).  In 2D the grid is the x-y
+ * plane and fields/momenta keep all three components (2D3V).
+ *
+ * Memory ownership: the caller allocates ONE device buffer of at least
+ * pml_pic_workspace_size() bytes (256-byte aligned) and a HIP stream, and passes both
+ * to pml_pic_create.  The library never allocates device memory; the handle borrows
+ * the buffer and the stream, which must outlive it.  Host arrays passed to the calls
+ * below are read or written before the call returns (the call synchronises the
+ * stream when it copies to or from the host) and stay owned by the caller.
+ *
+ * Errors: every call returns a pml_pic_status; no C++ exception crosses the ABI.
+ * pml_pic_last_error() gives a message for the last failure on a handle.  A handle is
+ * used by one host thread at a time.  Particles that leave through the outer PEC walls
+ * are removed and counted; that is not an error.
+ */
+#ifndef PML_PIC_H
+#define PML_PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PML_PIC_OK = 0,
+    PML_PIC_E_INVALID_ARG = -1,   /* bad parameter, size or pointer */
+    PML_PIC_E_CFL = -2,           /* c dt >= 1/sqrt(sum_d 1/dx_d^2) */
+    PML_PIC_E_WORKSPACE = -3,     /* workspace smaller than pml_pic_workspace_size or misaligned */
+    PML_PIC_E_HIP = -4,           /* a HIP runtime call failed (message has the HIP error) */
+    PML_PIC_E_NONFINITE = -5,     /* pml_pic_diagnose found NaN/Inf in the fields */
+    PML_PIC_E_CAPACITY = -6       /* more particles than max_particles */
+} pml_pic_status;
+
+/* current-damping scheme in the PML (the alpha of Eq. MaxwellE) */
+enum { PML_ALPHA_ZERO = 0, PML_ALPHA_ONE = 1, PML_ALPHA_DAMPED = 2 };
+
+/* pml_pic_params.flags */
+enum {
+    PML_PIC_FLAG_UNFUSED = 1,      /* gather_push and deposit_current as separate launches */
+    PML_PIC_FLAG_NO_SORT = 2,      /* never sort; deposit with global atomics only */
+    PML_PIC_FLAG_SEPARATE_DAMP = 4 /* damp_pml_current as its own pass over the PML */
+};
+
+typedef struct {
+    int32_t dim;                /* 2 (x-y plane, 2D3V) or 3 */
+    int32_t n[3];               /* physical cells per axis (ignored beyond dim) */
+    int32_t pml[3][2];          /* PML cells per axis, low / high face; 0 = bare PEC wall */
+    double dx[3];               /* cell sizes */
+    double dt;                  /* time step; c dt < 1/sqrt(sum 1/dx_d^2) */
+    int32_t shape_order;        /* particle shape: 1 linear, 2 quadratic, 3 cubic */
+    int32_t alpha_mode;         /* PML_ALPHA_ZERO / ONE / DAMPED */
+    double damping_scale;       /* 1/v of Eq. (alpha): alpha = exp(-damping_scale * int sigma/eps0) */
+    int32_t n_sigma_coef;       /* K <= 16 */
+    double sigma_coef[3][16];   /* sigma_d/eps0 = sum_k coef[d][k] (depth/L_d)^k, depth > 0 */
+    int32_t precision;          /* 32 (fields and particles in FP32) or 64 */
+    int32_t push;               /* 1: gather + Boris push; 0: momenta held fixed (ballistic) */
+    int32_t sort_interval;      /* steps between particle sorts; 0 = default */
+    int32_t tile[3];            /* deposit tile in cells; 0 = default */
+    int64_t max_particles;      /* particle capacity of the workspace */
+    double charge, mass;        /* species charge and mass per unit weight */
+    int32_t flags;              /* PML_PIC_FLAG_* */
+} pml_pic_params;
+
+typedef struct {
+    double u_interior;   /* 1/2 sum (E^2 + B^2) dV over samples inside the physical box (FP64 sum) */
+    double u_pml;        /* same over the remaining samples */
+    double gauss_max;    /* max |div E - rho| over nodes strictly inside the physical box */
+    double gauss_l2;     /* RMS of the same residual */
+    double rho_max;      /* max |rho| of the live particles (partners excluded) */
+    int64_t n_particles; /* live particles */
+    int64_t step;        /* steps taken */
+    int64_t n_pushes;    /* particle pushes performed since creation */
+    int32_t nonfinite;   /* 1 if a field value is NaN or Inf */
+} pml_pic_diag;
+
+typedef struct pml_pic_handle pml_pic_handle;
+
+/* Bytes of device workspace needed for these parameters.  Validates them first
+ * (returns PML_PIC_E_INVALID_ARG or PML_PIC_E_CFL on bad input). */
+int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes);
+
+/* Creates a simulation on the current HIP device.  device_workspace: caller-owned
+ * device buffer of `bytes` bytes, 256-byte aligned; stream: a hipStream_t (may be
+ * NULL for the default stream).  Fields start at zero, there are no particles. */
+int pml_pic_create(const pml_pic_params *params, void *device_workspace, size_t bytes,
+                   void *stream, pml_pic_handle **out);
+
+/* Adds n particles from host arrays: x (n x dim, physical coordinates with origin at
+ * the physical-box corner), u = gamma v (n x 3), w (n weights).  Each particle also
+ * gets a motionless opposite-charge partner at its initial position, which enters
+ * only the charge density of the diagnostics (App. A.1).  Positions outside the PEC
+ * box give PML_PIC_E_INVALID_ARG; exceeding max_particles gives PML_PIC_E_CAPACITY.
+ * Particle ids are assigned consecutively from the number added so far. */
+int pml_pic_add_particles(pml_pic_handle *h, int64_t n, const double *x, const double *u,
+                          const double *w);
+
+/* Advances n_steps time steps, asynchronously on the handle's stream. */
+int pml_pic_step(pml_pic_handle *h, int32_t n_steps);
+
+/* Kernel phases timed by pml_pic_step_profiled */
+enum {
+    PML_PIC_PHASE_SORT = 0,        /* sort_particles */
+    PML_PIC_PHASE_CLEAR_J = 1,     /* clearing the current arrays */
+    PML_PIC_PHASE_PUSH = 2,        /* gather_push (fused with deposit_current unless UNFUSED) */
+    PML_PIC_PHASE_DEPOSIT = 3,     /* deposit_current when UNFUSED */
+    PML_PIC_PHASE_DAMP = 4,        /* damp_pml_current when SEPARATE_DAMP */
+    PML_PIC_PHASE_UPDATE_B = 5,    /* update_yee_pml, the two B half steps */
+    PML_PIC_PHASE_UPDATE_E = 6,    /* update_yee_pml, the E step (with alpha J) */
+    PML_PIC_NUM_PHASES = 8
+};
+
+/* Same work as pml_pic_step, with a pair of HIP events on the handle's stream around
+ * every kernel phase.  Adds the elapsed milliseconds of phase p to phase_ms[p] and
+ * the number of timed launches to phase_calls[p] (arrays of PML_PIC_NUM_PHASES
+ * entries, caller-owned).  Synchronises the stream before returning. */
+int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, int64_t *phase_calls);
+
+/* FP64 diagnostics on the device (energies, Gauss residual with an FP64 charge
+ * deposit, counts); synchronises the stream.  Returns PML_PIC_E_NONFINITE (with
+ * *out filled) if a field value is not finite. */
+int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out);
+
+/* Number of sample positions per field component: nn[d] = cells + 1 along each
+ * in-plane axis, 1 along the invariant axis; n_samples = nn0 * nn1 * nn2. */
+int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples);
+
+/* Fields as 12 FP64 split parts of n_samples each, x fastest, in the order
+ * E_xy E_xz E_yz E_yx E_zx E_zy B_xy B_xz B_yz B_yx B_zx B_zy (F_ab is the part of
+ * F_a driven by the derivative along b, Eqs. MaxwellE/MaxwellB).  Sample (i,j,k) of
+ * E_a sits half a cell up along a, of B_a half a cell up along the other two axes.
+ * Where a component is stored unsplit its whole value is reported in one part.
+ * `count` is the number of doubles in `host` (>= 12 n_samples).  Synchronises. */
+int pml_pic_get_fields(pml_pic_handle *h, double *host, int64_t count);
+int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count);
+
+/* The current J_x J_y J_z (3 x n_samples doubles) deposited and damped by the last
+ * step, at E's sample positions.  Synchronises. */
+int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count);
+
+/* Static partner charge density at the nodes (n_samples doubles). */
+int pml_pic_get_rho_static(pml_pic_handle *h, double *host, int64_t count);
+int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count);
+
+/* Live particle count (synchronises). */
+int pml_pic_num_particles(pml_pic_handle *h, int64_t *n);
+
+/* Copies the live particles to host arrays of capacity `cap`: ids, grid coordinates
+ * X (n x 3; node-index units, X = x/dx + pml_lo), u (n x 3), w (n).  Order is the
+ * device order (sorted by cell), not the insertion order.  Synchronises. */
+int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, double *u,
+                          double *w, int64_t *n_out);
+
+/* Replaces all particles by the given ones (grid coordinates as above); the static
+ * partner density is left as it is. */
+int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X,
+                          const double *u, const double *w);
+
+/* Message of the last failed call on h (or of the last failed create if h is NULL). */
+const char *pml_pic_last_error(const pml_pic_handle *h);
+
+/* Releases the host-side handle; the caller frees the workspace afterwards. */
+void pml_pic_destroy(pml_pic_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PML_PIC_H */

@@ -1,0 +1,267 @@
+"""Thin ctypes binding of the C ABI in include/pml_pic.h.
+
+Argument marshalling only: every step of the particle-in-cell path runs in the HIP
+kernels of libpmlpic.so.  PyTorch provides the device workspace (one uint8 tensor)
+and the stream.  There is no CPU fallback: if the library or a GPU is missing,
+constructing a simulation raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmlpic.so")
+
+PML_PIC_OK = 0
+STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_CFL", -3: "E_WORKSPACE", -4: "E_HIP",
+          -5: "E_NONFINITE", -6: "E_CAPACITY"}
+FLAG_UNFUSED, FLAG_NO_SORT, FLAG_SEPARATE_DAMP = 1, 2, 4
+
+EXPORTED = [
+    "pml_pic_workspace_size", "pml_pic_create", "pml_pic_add_particles", "pml_pic_step",
+    "pml_pic_diagnose", "pml_pic_grid_shape", "pml_pic_get_fields", "pml_pic_set_fields",
+    "pml_pic_get_current", "pml_pic_get_rho_static", "pml_pic_set_rho_static",
+    "pml_pic_num_particles", "pml_pic_get_particles", "pml_pic_set_particles",
+    "pml_pic_last_error", "pml_pic_destroy", "pml_pic_step_profiled",
+]
+PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
+          "update_yee_pml_B", "update_yee_pml_E", "unused"]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32 * 3), ("pml", (C.c_int32 * 2) * 3),
+        ("dx", C.c_double * 3), ("dt", C.c_double), ("shape_order", C.c_int32),
+        ("alpha_mode", C.c_int32), ("damping_scale", C.c_double), ("n_sigma_coef", C.c_int32),
+        ("sigma_coef", (C.c_double * 16) * 3), ("precision", C.c_int32), ("push", C.c_int32),
+        ("sort_interval", C.c_int32), ("tile", C.c_int32 * 3), ("max_particles", C.c_int64),
+        ("charge", C.c_double), ("mass", C.c_double), ("flags", C.c_int32),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("u_interior", C.c_double), ("u_pml", C.c_double), ("gauss_max", C.c_double),
+        ("gauss_l2", C.c_double), ("rho_max", C.c_double), ("n_particles", C.c_int64),
+        ("step", C.c_int64), ("n_pushes", C.c_int64), ("nonfinite", C.c_int32),
+    ]
+
+
+class PmlPicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Loads libpmlpic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpmlpic.so is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, P(C.c_double)
+        sig = {
+            "pml_pic_workspace_size": (C.c_int, [P(Params), P(C.c_size_t)]),
+            "pml_pic_create": (C.c_int, [P(Params), vp, C.c_size_t, vp, P(vp)]),
+            "pml_pic_add_particles": (C.c_int, [vp, i64, dp, dp, dp]),
+            "pml_pic_step": (C.c_int, [vp, i32]),
+            "pml_pic_step_profiled": (C.c_int, [vp, i32, dp, P(C.c_int64)]),
+            "pml_pic_diagnose": (C.c_int, [vp, P(Diag)]),
+            "pml_pic_grid_shape": (C.c_int, [vp, P(C.c_int32), P(C.c_int64)]),
+            "pml_pic_get_fields": (C.c_int, [vp, dp, i64]),
+            "pml_pic_set_fields": (C.c_int, [vp, dp, i64]),
+            "pml_pic_get_current": (C.c_int, [vp, dp, i64]),
+            "pml_pic_get_rho_static": (C.c_int, [vp, dp, i64]),
+            "pml_pic_set_rho_static": (C.c_int, [vp, dp, i64]),
+            "pml_pic_num_particles": (C.c_int, [vp, P(C.c_int64)]),
+            "pml_pic_get_particles": (C.c_int, [vp, i64, P(C.c_int64), dp, dp, dp, P(C.c_int64)]),
+            "pml_pic_set_particles": (C.c_int, [vp, i64, P(C.c_int64), dp, dp, dp]),
+            "pml_pic_last_error": (C.c_char_p, [vp]),
+            "pml_pic_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def make_params(cfg, max_particles=None, flags=0) -> Params:
+    """C parameter block from a workloads.SimConfig-like object."""
+    p = Params()
+    p.dim = int(cfg.dim)
+    for d in range(3):
+        p.n[d] = int(cfg.n[d]) if d < cfg.dim else 1
+        p.pml[d][0] = int(cfg.pml[d][0]) if d < cfg.dim else 0
+        p.pml[d][1] = int(cfg.pml[d][1]) if d < cfg.dim else 0
+        p.dx[d] = float(cfg.dx[d]) if d < cfg.dim else 1.0
+        p.tile[d] = int(cfg.tile[d]) if hasattr(cfg, "tile") else 0
+    p.dt = float(cfg.dt)
+    p.shape_order = int(cfg.shape_order)
+    p.alpha_mode = int(cfg.alpha_mode)
+    p.damping_scale = float(cfg.damping_scale)
+    p.n_sigma_coef = 16
+    for d, row in enumerate(cfg.sigma_coef):
+        for k, v in enumerate(row):
+            p.sigma_coef[d][k] = float(v)
+    p.precision = int(cfg.precision)
+    p.push = int(cfg.push)
+    p.sort_interval = int(getattr(cfg, "sort_interval", 0))
+    mp = max_particles if max_particles is not None else int(getattr(cfg, "max_particles", 0))
+    p.max_particles = int(mp)
+    p.charge = float(cfg.charge)
+    p.mass = float(cfg.mass)
+    p.flags = int(flags)
+    return p
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _lp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def workspace_size(params: Params) -> int:
+    n = C.c_size_t(0)
+    rc = load_library().pml_pic_workspace_size(C.byref(params), C.byref(n))
+    if rc != PML_PIC_OK:
+        raise PmlPicError(rc, load_library().pml_pic_last_error(None).decode())
+    return int(n.value)
+
+
+class PmlPic:
+    """One simulation on the current GPU (names follow the C ABI)."""
+
+    def __init__(self, cfg, max_particles=None, flags=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("PmlPic needs a ROCm GPU; there is no CPU fallback")
+        L = load_library()
+        self.cfg = cfg
+        self.params = make_params(cfg, max_particles, flags)
+        nbytes = workspace_size(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = L.pml_pic_create(C.byref(self.params), C.c_void_p(aligned), C.c_size_t(nbytes),
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != PML_PIC_OK:
+            raise PmlPicError(rc, L.pml_pic_last_error(None).decode())
+        self._h = h
+        nn = (C.c_int32 * 3)()
+        ns = C.c_int64()
+        self._check(L.pml_pic_grid_shape(self._h, nn, C.byref(ns)))
+        self.nn = [int(nn[0]), int(nn[1]), int(nn[2])]
+        self.nsamp = int(ns.value)
+
+    def _check(self, rc):
+        if rc != PML_PIC_OK:
+            raise PmlPicError(rc, load_library().pml_pic_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().pml_pic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- particles
+    def add_particles(self, x, u, w):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(load_library().pml_pic_add_particles(self._h, len(w), _dp(x), _dp(u), _dp(w)))
+
+    def set_particles(self, ids, X, u, w):
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(load_library().pml_pic_set_particles(self._h, len(w), _lp(ids), _dp(X), _dp(u), _dp(w)))
+
+    def particles(self, cap=None):
+        """(ids, X grid coordinates n x 3, u n x 3, w) of the live particles, sorted by id."""
+        if cap is None:
+            cap = max(1, int(self.params.max_particles))
+        ids = np.zeros(cap, np.int64)
+        X = np.zeros((cap, 3))
+        u = np.zeros((cap, 3))
+        w = np.zeros(cap)
+        n = C.c_int64()
+        self._check(load_library().pml_pic_get_particles(self._h, cap, _lp(ids), _dp(X), _dp(u), _dp(w),
+                                                         C.byref(n)))
+        n = int(n.value)
+        o = np.argsort(ids[:n], kind="stable")
+        return ids[:n][o], X[:n][o], u[:n][o], w[:n][o]
+
+    @property
+    def num_particles(self) -> int:
+        n = C.c_int64()
+        self._check(load_library().pml_pic_num_particles(self._h, C.byref(n)))
+        return int(n.value)
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, n: int = 1):
+        self._check(load_library().pml_pic_step(self._h, int(n)))
+
+    def step_profiled(self, n: int = 1):
+        """Steps with HIP events around every kernel phase: {phase: (total ms, launches)}."""
+        ms = np.zeros(8)
+        calls = np.zeros(8, np.int64)
+        self._check(load_library().pml_pic_step_profiled(self._h, int(n), _dp(ms), _lp(calls)))
+        return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(8) if calls[k] > 0}
+
+    def diagnose(self, allow_nonfinite=False) -> dict:
+        d = Diag()
+        rc = load_library().pml_pic_diagnose(self._h, C.byref(d))
+        if rc != PML_PIC_OK and not (allow_nonfinite and rc == -5):
+            self._check(rc)
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    # ---------------------------------------------------------------- fields
+    def _shape(self):
+        return (self.nn[2], self.nn[1], self.nn[0])
+
+    def split_fields(self) -> np.ndarray:
+        out = np.zeros(12 * self.nsamp)
+        self._check(load_library().pml_pic_get_fields(self._h, _dp(out), out.size))
+        return out.reshape((12,) + self._shape())
+
+    def set_split_fields(self, F):
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(-1)
+        self._check(load_library().pml_pic_set_fields(self._h, _dp(F), F.size))
+
+    def fields(self) -> np.ndarray:
+        F = self.split_fields()
+        return F[0::2] + F[1::2]
+
+    def current(self) -> np.ndarray:
+        out = np.zeros(3 * self.nsamp)
+        self._check(load_library().pml_pic_get_current(self._h, _dp(out), out.size))
+        return out.reshape((3,) + self._shape())
+
+    def rho_static(self) -> np.ndarray:
+        out = np.zeros(self.nsamp)
+        self._check(load_library().pml_pic_get_rho_static(self._h, _dp(out), out.size))
+        return out.reshape(self._shape())
+
+    def set_rho_static(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+        self._check(load_library().pml_pic_set_rho_static(self._h, _dp(r), r.size))

@@ -1,0 +1,844 @@
+// Host side of the C ABI declared in include/pml_pic.h: parameter validation,
+// workspace layout, per-axis coefficient tables (built in FP64, stored in the run
+// precision), kernel launches on the caller's stream, and state I/O.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "pml_pic.h"
+
+using namespace pmlpic;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  int dim = 2, M[3] = {0, 0, 0}, ext[3] = {1, 1, 1}, nn[3] = {1, 1, 1};
+  long sy = 0, sz = 0, base = 0, nelem = 0;
+  int ntab = 0;
+  size_t esz = 4;
+  int64_t cap = 0;
+  size_t off_field[15] = {};   // E0-2, B0-2, Ea0-2, Ba0-2, J0-2
+  size_t off_tab = 0;
+  size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_id[2] = {};
+  size_t off_oldcell = 0, off_oldf[3] = {};
+  size_t off_count = 0, off_pushes = 0;
+  size_t off_counts = 0, off_rank = 0, off_blocksums = 0;
+  size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
+  int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
+  size_t total = 0;
+};
+
+int fail(std::string *err, int code, const std::string &msg) {
+  if (err) *err = msg;
+  return code;
+}
+
+// depth inside the PML of axis d at grid coordinate X (0 in the physical box) and the
+// thickness of that side (physical lengths)
+double pml_depth(const pml_pic_params &p, int d, double X, double *thick) {
+  const double lo = p.pml[d][0], hi = (double)p.pml[d][0] + p.n[d];
+  *thick = 0.0;
+  if (X < lo) { *thick = p.pml[d][0] * p.dx[d]; return (lo - X) * p.dx[d]; }
+  if (X > hi) { *thick = p.pml[d][1] * p.dx[d]; return (X - hi) * p.dx[d]; }
+  return 0.0;
+}
+
+// sigma/eps0 = sum_k a_k (depth/L)^k and its exact integral Phi over depth
+void profile(const pml_pic_params &p, int d, double X, double *sigma, double *phi) {
+  double L;
+  const double dep = pml_depth(p, d, X, &L);
+  *sigma = 0.0;
+  *phi = 0.0;
+  if (dep <= 0.0 || L <= 0.0) return;
+  const double r = dep / L;
+  double pw = 1.0;
+  for (int k = 0; k < p.n_sigma_coef; ++k) {
+    *sigma += p.sigma_coef[d][k] * pw;
+    *phi += p.sigma_coef[d][k] * L * pw * r / (k + 1);
+    pw *= r;
+  }
+}
+
+int validate(const pml_pic_params *p, std::string *err) {
+  if (!p) return fail(err, PML_PIC_E_INVALID_ARG, "params is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "dim must be 2 or 3");
+  double s2 = 0.0;
+  for (int d = 0; d < p->dim; ++d) {
+    if (p->n[d] < 1) return fail(err, PML_PIC_E_INVALID_ARG, "n[d] must be >= 1");
+    if (p->pml[d][0] < 0 || p->pml[d][1] < 0) return fail(err, PML_PIC_E_INVALID_ARG, "negative PML thickness");
+    if (p->pml[d][0] > p->n[d] || p->pml[d][1] > p->n[d])
+      return fail(err, PML_PIC_E_INVALID_ARG, "PML thicker than the physical box");
+    if (!(p->dx[d] > 0.0) || !std::isfinite(p->dx[d])) return fail(err, PML_PIC_E_INVALID_ARG, "dx must be > 0");
+    s2 += 1.0 / (p->dx[d] * p->dx[d]);
+  }
+  const int M0 = p->n[0] + p->pml[0][0] + p->pml[0][1];
+  const int M1 = p->n[1] + p->pml[1][0] + p->pml[1][1];
+  const int M2 = p->dim == 3 ? p->n[2] + p->pml[2][0] + p->pml[2][1] : 0;
+  if (p->dim == 2 && (M0 > 65533 || M1 > 65533)) return fail(err, PML_PIC_E_INVALID_ARG, "2D grid too large");
+  if (p->dim == 3 && (M0 > 2045 || M1 > 2045 || M2 > 1021)) return fail(err, PML_PIC_E_INVALID_ARG, "3D grid too large");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(err, PML_PIC_E_INVALID_ARG, "dt must be > 0");
+  if (!(p->dt < 1.0 / std::sqrt(s2))) return fail(err, PML_PIC_E_CFL, "c dt violates the Yee CFL limit");
+  if (p->shape_order < 1 || p->shape_order > 3) return fail(err, PML_PIC_E_INVALID_ARG, "shape_order must be 1, 2 or 3");
+  if (p->alpha_mode < 0 || p->alpha_mode > 2) return fail(err, PML_PIC_E_INVALID_ARG, "alpha_mode must be 0, 1 or 2");
+  if (!(p->damping_scale >= 0.0) || !std::isfinite(p->damping_scale))
+    return fail(err, PML_PIC_E_INVALID_ARG, "damping_scale must be >= 0");
+  if (p->n_sigma_coef < 0 || p->n_sigma_coef > 16) return fail(err, PML_PIC_E_INVALID_ARG, "n_sigma_coef must be in [0,16]");
+  for (int d = 0; d < p->dim; ++d) {
+    for (int k = 0; k < p->n_sigma_coef; ++k)
+      if (!std::isfinite(p->sigma_coef[d][k])) return fail(err, PML_PIC_E_INVALID_ARG, "non-finite sigma coefficient");
+    const int M = d == 0 ? M0 : (d == 1 ? M1 : M2);
+    for (int h = 0; h <= 2 * M; ++h) {
+      double s, ph;
+      profile(*p, d, 0.5 * h, &s, &ph);
+      if (s < 0.0) return fail(err, PML_PIC_E_INVALID_ARG, "sigma profile is negative somewhere in the PML");
+    }
+  }
+  if (p->precision != 32 && p->precision != 64) return fail(err, PML_PIC_E_INVALID_ARG, "precision must be 32 or 64");
+  if (p->push != 0 && p->push != 1) return fail(err, PML_PIC_E_INVALID_ARG, "push must be 0 or 1");
+  if (p->max_particles < 0 || p->max_particles > (int64_t)1 << 30)
+    return fail(err, PML_PIC_E_INVALID_ARG, "max_particles must be in [0, 2^30]");
+  if (p->sort_interval < 0) return fail(err, PML_PIC_E_INVALID_ARG, "sort_interval must be >= 0");
+  for (int d = 0; d < 3; ++d)
+    if (p->tile[d] < 0) return fail(err, PML_PIC_E_INVALID_ARG, "tile must be >= 0");
+  if (!(p->mass > 0.0) || !std::isfinite(p->charge)) return fail(err, PML_PIC_E_INVALID_ARG, "need mass > 0, finite charge");
+  return PML_PIC_OK;
+}
+
+void make_layout(const pml_pic_params &p, Layout &L) {
+  L.dim = p.dim;
+  L.esz = p.precision == 64 ? 8 : 4;
+  for (int d = 0; d < 3; ++d) {
+    if (d < p.dim) {
+      L.M[d] = p.n[d] + p.pml[d][0] + p.pml[d][1];
+      L.nn[d] = L.M[d] + 1;
+      L.ext[d] = L.M[d] + 1 + 2 * G;
+    } else { L.M[d] = 0; L.nn[d] = 1; L.ext[d] = 1; }
+  }
+  const long px = (long)align_up((size_t)L.ext[0], 64);
+  L.sy = px;
+  L.sz = (p.dim == 3) ? px * L.ext[1] : 0;
+  L.base = G + G * L.sy + (p.dim == 3 ? G * L.sz : 0);
+  L.nelem = px * L.ext[1] * L.ext[2];
+  L.ntab = *std::max_element(L.M, L.M + 3) + 1 + 2 * G;
+  L.cap = p.max_particles;
+  const int deft[3] = {p.dim == 2 ? 16 : 8, p.dim == 2 ? 16 : 8, p.dim == 2 ? 1 : 8};
+  L.nkeys = 1;
+  for (int d = 0; d < 3; ++d) {
+    L.tile[d] = d < p.dim ? (p.tile[d] > 0 ? p.tile[d] : deft[d]) : 1;
+    L.ntile[d] = d < p.dim ? (L.M[d] + L.tile[d] - 1) / L.tile[d] : 1;
+    L.nkeys *= L.ntile[d] * L.tile[d];
+  }
+  L.nscan = (L.nkeys + 4095) / 4096;
+  L.diag_blocks = ((L.M[0] + 1 + 63) / 64) * ((L.M[1] + 1 + 3) / 4) * (p.dim == 3 ? L.M[2] + 1 : 1);
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  for (int a = 0; a < 15; ++a) L.off_field[a] = take(L.esz * (size_t)L.nelem);
+  L.off_tab = take(L.esz * 3 * T_NKIND * (size_t)L.ntab);
+  const size_t cap = (size_t)std::max<int64_t>(L.cap, 1);
+  for (int b = 0; b < 2; ++b) {
+    L.off_cell[b] = take(4 * cap);
+    for (int d = 0; d < 3; ++d) L.off_f[b][d] = d < p.dim ? take(L.esz * cap) : 0;
+    for (int d = 0; d < 3; ++d) L.off_u[b][d] = take(L.esz * cap);
+    L.off_w[b] = take(L.esz * cap);
+    L.off_id[b] = take(4 * cap);
+  }
+  L.off_oldcell = take(4 * cap);
+  for (int d = 0; d < 3; ++d) L.off_oldf[d] = d < p.dim ? take(L.esz * cap) : 0;
+  L.off_count = take(8);
+  L.off_pushes = take(8);
+  L.off_counts = take(4 * ((size_t)L.nkeys + 1));
+  L.off_rank = take(4 * cap);
+  L.off_blocksums = take(4 * ((size_t)L.nscan + 2));
+  L.off_rho = take(8 * (size_t)L.nelem);
+  L.off_rho_static = take(8 * (size_t)L.nelem);
+  L.off_partial = take(8 * (4 * (size_t)L.diag_blocks + 1024));
+  L.off_result = take(8 * 8);
+  L.off_flags = take(4 * 4);
+  L.total = off;
+}
+
+}  // namespace
+
+struct pml_pic_handle {
+  pml_pic_params p;
+  Layout L;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int cur = 0;               // active particle buffer
+  int64_t n_slots = 0;       // upper bound of used particle slots
+  int64_t n_added = 0;
+  int64_t step = 0;
+  int sort_interval = 8;
+  int since_sort = 0;
+  bool sort_pending = false;
+  // FP64 host copies of the per-axis tables: [axis][kind][ntab]
+  std::vector<double> tab64;
+
+  template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
+  double tab(int axis, int kind, int i) const { return tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G]; }
+
+  template <typename T> Grid<T> grid() const {
+    Grid<T> g;
+    g.dim = p.dim; g.order = p.shape_order;
+    for (int d = 0; d < 3; ++d) {
+      g.M[d] = L.M[d];
+      g.lo[d] = d < p.dim ? p.pml[d][0] : 0;
+      g.n[d] = d < p.dim ? p.n[d] : 0;
+      g.ext[d] = L.ext[d];
+      g.inv_dx[d] = (T)(1.0 / (d < p.dim ? p.dx[d] : 1.0));
+    }
+    g.sy = L.sy; g.sz = L.sz; g.base = L.base; g.nelem = L.nelem;
+    g.dt = (T)p.dt;
+    g.qdt_2m = (T)(p.charge * p.dt / (2.0 * p.mass));
+    g.charge = (T)p.charge;
+    g.tab = at<T>(L.off_tab);
+    g.ntab = L.ntab;
+    return g;
+  }
+  template <typename T> Fields<T> fields() const {
+    Fields<T> F;
+    for (int a = 0; a < 3; ++a) {
+      F.E[a] = at<T>(L.off_field[a]);
+      F.B[a] = at<T>(L.off_field[3 + a]);
+      F.Ea[a] = at<T>(L.off_field[6 + a]);
+      F.Ba[a] = at<T>(L.off_field[9 + a]);
+      F.J[a] = at<T>(L.off_field[12 + a]);
+    }
+    return F;
+  }
+  template <typename T> Parts<T> parts(int b) const {
+    Parts<T> P;
+    P.cell = at<uint32_t>(L.off_cell[b]);
+    for (int d = 0; d < 3; ++d) {
+      P.f[d] = d < p.dim ? at<T>(L.off_f[b][d]) : nullptr;
+      P.u[d] = at<T>(L.off_u[b][d]);
+    }
+    P.w = at<T>(L.off_w[b]);
+    P.id = at<int32_t>(L.off_id[b]);
+    return P;
+  }
+  template <typename T> Parts<T> old_parts() const {
+    Parts<T> P = parts<T>(0);
+    P.cell = at<uint32_t>(L.off_oldcell);
+    for (int d = 0; d < 3; ++d) P.f[d] = d < p.dim ? at<T>(L.off_oldf[d]) : nullptr;
+    return P;
+  }
+  StepCtl ctl() const {
+    StepCtl c;
+    c.count = at<int32_t>(L.off_count);
+    c.pushes = at<unsigned long long>(L.off_pushes);
+    return c;
+  }
+  SortWork sortwork() const {
+    SortWork s;
+    s.counts = at<uint32_t>(L.off_counts);
+    s.rank = at<uint32_t>(L.off_rank);
+    s.blocksums = at<uint32_t>(L.off_blocksums);
+    s.nkeys = L.nkeys;
+    for (int d = 0; d < 3; ++d) { s.tile[d] = L.tile[d]; s.ntile[d] = L.ntile[d]; }
+    return s;
+  }
+  DiagWork diagwork() const {
+    DiagWork w;
+    w.rho = at<double>(L.off_rho);
+    w.rho_static = at<double>(L.off_rho_static);
+    w.partial = at<double>(L.off_partial);
+    w.result = at<double>(L.off_result);
+    w.flags = at<int32_t>(L.off_flags);
+    w.max_blocks = L.diag_blocks;
+    return w;
+  }
+};
+
+#define HIPCHK(h, expr)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      (h)->err = std::string("HIP error in " #expr ": ") + hipGetErrorString(e_);            \
+      return PML_PIC_E_HIP;                                                                  \
+    }                                                                                        \
+  } while (0)
+
+namespace {
+
+void build_tables(pml_pic_handle *h) {
+  const pml_pic_params &p = h->p;
+  const Layout &L = h->L;
+  h->tab64.assign((size_t)3 * T_NKIND * L.ntab, 0.0);
+  auto put = [&](int axis, int kind, int i, double v) { h->tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G] = v; };
+  for (int d = 0; d < 3; ++d) {
+    for (int i = -G; i <= L.M[d] + G; ++i) {
+      for (int centre = 0; centre < 2; ++centre) {
+        const double X = i + 0.5 * centre;
+        const bool in_grid = d < p.dim && X >= 0.0 && X <= (double)L.M[d];
+        double sig = 0.0, phi = 0.0;
+        if (in_grid) profile(p, d, X, &sig, &phi);
+        double L_;
+        const double dep = (d < p.dim) ? pml_depth(p, d, X, &L_) : 0.0;
+        const double taus[2] = {p.dt, 0.5 * p.dt};
+        double ev[2], gv[2];
+        for (int t = 0; t < 2; ++t) {
+          if (sig > 0.0) { ev[t] = std::exp(-sig * taus[t]); gv[t] = -std::expm1(-sig * taus[t]) / sig; }
+          else { ev[t] = 1.0; gv[t] = taus[t]; }
+        }
+        double alpha = 1.0;
+        if (p.alpha_mode == PML_ALPHA_ZERO) alpha = dep > 0.0 ? 0.0 : 1.0;
+        else if (p.alpha_mode == PML_ALPHA_DAMPED) alpha = std::exp(-p.damping_scale * phi);
+        if (d < p.dim && !in_grid) alpha = 0.0;   // guard samples: no current
+        const int k0 = centre ? T_SIG_C : T_SIG_N;
+        const double inv_dx = 1.0 / (d < p.dim ? p.dx[d] : 1.0);
+        put(d, centre ? T_GHK_C : T_GK_N, i, (centre ? gv[1] : gv[0]) * inv_dx);
+        put(d, k0 + 0, i, sig);
+        put(d, k0 + 1, i, ev[0]);
+        put(d, k0 + 2, i, gv[0]);
+        put(d, k0 + 3, i, ev[1]);
+        put(d, k0 + 4, i, gv[1]);
+        put(d, k0 + 5, i, alpha);
+      }
+    }
+  }
+}
+
+template <typename T>
+int upload_tables(pml_pic_handle *h) {
+  std::vector<T> t(h->tab64.size());
+  for (size_t i = 0; i < t.size(); ++i) t[i] = (T)h->tab64[i];
+  HIPCHK(h, hipMemcpyAsync(h->at<T>(h->L.off_tab), t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PML_PIC_OK;
+}
+
+// storage rule of component c (0..5 = Ex..Bz): unsplit in-plane part index, or -1 if split
+int unsplit_part(const pml_pic_params &p, int c) {
+  const int a = c % 3, b = (a + 1) % 3, cc = (a + 2) % 3;
+  if (p.dim == 2 && (b == 2 || cc == 2)) return (b == 2) ? 1 : 0;
+  return -1;
+}
+
+// is the split of component c active at sample (i,j,k)?
+bool split_active(const pml_pic_handle *h, int c, const int id[3]) {
+  const int a = c % 3, b = (a + 1) % 3, cc = (a + 2) % 3;
+  const int kind = c < 3 ? T_SIG_N : T_SIG_C;
+  return h->tab(b, kind, id[b]) + h->tab(cc, kind, id[cc]) > 0.0;
+}
+
+template <typename T>
+int get_fields_t(pml_pic_handle *h, double *out) {
+  const Layout &L = h->L;
+  const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
+  std::vector<T> tot(L.nelem), aux(L.nelem);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int c = 0; c < 6; ++c) {
+    const int a = c % 3;
+    HIPCHK(h, hipMemcpy(tot.data(), h->at<T>(L.off_field[c < 3 ? a : 3 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
+    const int up = unsplit_part(h->p, c);
+    if (up < 0)
+      HIPCHK(h, hipMemcpy(aux.data(), h->at<T>(L.off_field[c < 3 ? 6 + a : 9 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
+    double *p0 = out + (size_t)(2 * c) * ns, *p1 = out + (size_t)(2 * c + 1) * ns;
+    for (int k = 0; k < L.nn[2]; ++k)
+      for (int j = 0; j < L.nn[1]; ++j)
+        for (int i = 0; i < L.nn[0]; ++i) {
+          const size_t o = ((size_t)k * L.nn[1] + j) * L.nn[0] + i;
+          const long q = L.base + i + j * L.sy + k * L.sz;
+          const int id[3] = {i, j, k};
+          const double t = (double)tot[q];
+          if (up == 0) { p0[o] = t; p1[o] = 0.0; }
+          else if (up == 1) { p0[o] = 0.0; p1[o] = t; }
+          else if (split_active(h, c, id)) { p0[o] = (double)aux[q]; p1[o] = t - (double)aux[q]; }
+          else { p0[o] = t; p1[o] = 0.0; }
+        }
+  }
+  return PML_PIC_OK;
+}
+
+template <typename T>
+int set_fields_t(pml_pic_handle *h, const double *in) {
+  const Layout &L = h->L;
+  const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
+  std::vector<T> tot(L.nelem), aux(L.nelem);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int c = 0; c < 6; ++c) {
+    const int a = c % 3;
+    std::fill(tot.begin(), tot.end(), T(0));
+    std::fill(aux.begin(), aux.end(), T(0));
+    const int up = unsplit_part(h->p, c);
+    const double *p0 = in + (size_t)(2 * c) * ns, *p1 = in + (size_t)(2 * c + 1) * ns;
+    for (int k = 0; k < L.nn[2]; ++k)
+      for (int j = 0; j < L.nn[1]; ++j)
+        for (int i = 0; i < L.nn[0]; ++i) {
+          const size_t o = ((size_t)k * L.nn[1] + j) * L.nn[0] + i;
+          const long q = L.base + i + j * L.sy + k * L.sz;
+          const int id[3] = {i, j, k};
+          tot[q] = (T)(p0[o] + p1[o]);
+          if (up < 0 && split_active(h, c, id)) aux[q] = (T)p0[o];
+        }
+    HIPCHK(h, hipMemcpy(h->at<T>(L.off_field[c < 3 ? a : 3 + a]), tot.data(), sizeof(T) * L.nelem, hipMemcpyHostToDevice));
+    if (up < 0)
+      HIPCHK(h, hipMemcpy(h->at<T>(L.off_field[c < 3 ? 6 + a : 9 + a]), aux.data(), sizeof(T) * L.nelem, hipMemcpyHostToDevice));
+  }
+  return PML_PIC_OK;
+}
+
+template <typename T>
+int get_current_t(pml_pic_handle *h, double *out) {
+  const Layout &L = h->L;
+  const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
+  std::vector<T> buf(L.nelem);
+  const bool alpha_in_update = !(h->p.flags & PML_PIC_FLAG_SEPARATE_DAMP) && h->p.alpha_mode != PML_ALPHA_ONE;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int a = 0; a < 3; ++a) {
+    HIPCHK(h, hipMemcpy(buf.data(), h->at<T>(L.off_field[12 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
+    for (int k = 0; k < L.nn[2]; ++k)
+      for (int j = 0; j < L.nn[1]; ++j)
+        for (int i = 0; i < L.nn[0]; ++i) {
+          const size_t o = ((size_t)k * L.nn[1] + j) * L.nn[0] + i;
+          const long q = L.base + i + j * L.sy + k * L.sz;
+          double v = (double)buf[q];
+          if (alpha_in_update) {
+            const int id[3] = {i, j, k};
+            for (int d = 0; d < h->p.dim; ++d) v *= h->tab(d, d == a ? T_A_C : T_A_N, id[d]);
+          }
+          out[(size_t)a * ns + o] = v;
+        }
+  }
+  return PML_PIC_OK;
+}
+
+// grid coordinate -> (cell, offset) in precision T; false if outside [0, M)
+template <typename T>
+bool to_cell(const Layout &L, int dim, const double *X, int id[3], T f[3]) {
+  for (int d = 0; d < 3; ++d) { id[d] = 0; f[d] = T(0); }
+  for (int d = 0; d < dim; ++d) {
+    if (!std::isfinite(X[d])) return false;
+    double fl = std::floor(X[d]);
+    int i = (int)fl;
+    T ff = (T)(X[d] - fl);
+    if (ff >= T(1)) { ff = T(0); i += 1; }
+    if (i < 0 || i >= L.M[d]) return false;
+    id[d] = i;
+    f[d] = ff;
+  }
+  return true;
+}
+
+template <typename T>
+int write_particles(pml_pic_handle *h, int64_t at_slot, int64_t n, const int64_t *ids, const double *X3,
+                    const double *xphys, const double *u, const double *w) {
+  const Layout &L = h->L;
+  const int dim = h->p.dim;
+  std::vector<uint32_t> cell(n);
+  std::vector<T> f[3], uu[3], ww(n);
+  std::vector<int32_t> id(n);
+  for (int d = 0; d < 3; ++d) { f[d].resize(n); uu[d].resize(n); }
+  for (int64_t t = 0; t < n; ++t) {
+    double X[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d)
+      X[d] = X3 ? X3[3 * t + d] : xphys[dim * t + d] / h->p.dx[d] + h->p.pml[d][0];
+    int ic[3];
+    T ff[3];
+    if (!to_cell<T>(L, dim, X, ic, ff)) {
+      h->err = "particle " + std::to_string(t) + " lies outside the PEC box";
+      return PML_PIC_E_INVALID_ARG;
+    }
+    if (!std::isfinite(u[3 * t]) || !std::isfinite(u[3 * t + 1]) || !std::isfinite(u[3 * t + 2]) || !std::isfinite(w[t])) {
+      h->err = "particle " + std::to_string(t) + " has a non-finite momentum or weight";
+      return PML_PIC_E_INVALID_ARG;
+    }
+    cell[t] = pack_cell(dim, ic[0], ic[1], ic[2]);
+    for (int d = 0; d < 3; ++d) { f[d][t] = ff[d]; uu[d][t] = (T)u[3 * t + d]; }
+    ww[t] = (T)w[t];
+    id[t] = ids ? (int32_t)ids[t] : (int32_t)(h->n_added + t);
+  }
+  const int b = h->cur;
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(h->at<uint32_t>(L.off_cell[b]) + at_slot, cell.data(), 4 * n, hipMemcpyHostToDevice, s));
+  for (int d = 0; d < dim; ++d)
+    HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_f[b][d]) + at_slot, f[d].data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  for (int d = 0; d < 3; ++d)
+    HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_u[b][d]) + at_slot, uu[d].data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_w[b]) + at_slot, ww.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->at<int32_t>(L.off_id[b]) + at_slot, id.data(), 4 * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return PML_PIC_OK;
+}
+
+int read_count(pml_pic_handle *h, int32_t *n) {
+  HIPCHK(h, hipMemcpyAsync(n, h->at<int32_t>(h->L.off_count), 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PML_PIC_OK;
+}
+
+int write_count(pml_pic_handle *h, int32_t n) {
+  HIPCHK(h, hipMemcpyAsync(h->at<int32_t>(h->L.off_count), &n, 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PML_PIC_OK;
+}
+
+// Timing hooks around each phase (no-ops unless profiling).
+struct PhaseTimer {
+  pml_pic_handle *h = nullptr;
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  hipError_t err = hipSuccess;
+  void begin(hipStream_t s) {
+    if (!on) return;
+    hipEvent_t e;
+    if (err == hipSuccess) err = hipEventCreate(&e);
+    if (err == hipSuccess) err = hipEventRecord(e, s);
+    if (err == hipSuccess) ev.push_back(e);
+  }
+  void end(hipStream_t s, int p) {
+    if (!on) return;
+    begin(s);
+    phase.push_back(p);
+  }
+};
+
+template <typename T>
+int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
+  const Grid<T> g = h->grid<T>();
+  const Fields<T> F = h->fields<T>();
+  const StepCtl ctl = h->ctl();
+  const int fl = h->p.flags;
+  const bool use_sort = !(fl & PML_PIC_FLAG_NO_SORT);
+  const bool fused = !(fl & PML_PIC_FLAG_UNFUSED);
+  const bool sep_damp = (fl & PML_PIC_FLAG_SEPARATE_DAMP) != 0;
+  const int ns = (int)h->n_slots;
+  hipStream_t s = h->stream;
+  const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
+  for (int it = 0; it < nsteps; ++it) {
+    if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
+      pt.begin(s);
+      launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
+      pt.end(s, PML_PIC_PHASE_SORT);
+      h->cur = 1 - h->cur;
+      h->since_sort = 0;
+      h->sort_pending = false;
+    }
+    pt.begin(s);
+    for (int a = 0; a < 3; ++a) HIPCHK(h, hipMemsetAsync(F.J[a], 0, jbytes, s));
+    pt.end(s, PML_PIC_PHASE_CLEAR_J);
+    const Parts<T> P = h->parts<T>(h->cur);
+    pt.begin(s);
+    launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
+    pt.end(s, PML_PIC_PHASE_PUSH);
+    if (!fused) {
+      pt.begin(s);
+      launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, s);
+      pt.end(s, PML_PIC_PHASE_DEPOSIT);
+    }
+    if (sep_damp && h->p.alpha_mode != PML_ALPHA_ONE) {
+      pt.begin(s);
+      launch_damp_current<T>(g, F, s);
+      pt.end(s, PML_PIC_PHASE_DAMP);
+    }
+    pt.begin(s);
+    launch_update_B<T>(g, F, true, s);
+    pt.end(s, PML_PIC_PHASE_UPDATE_B);
+    pt.begin(s);
+    launch_update_E<T>(g, F, !sep_damp, h->p.alpha_mode, s);
+    pt.end(s, PML_PIC_PHASE_UPDATE_E);
+    pt.begin(s);
+    launch_update_B<T>(g, F, true, s);
+    pt.end(s, PML_PIC_PHASE_UPDATE_B);
+    h->step++;
+    h->since_sort++;
+  }
+  HIPCHK(h, hipGetLastError());
+  if (pt.err != hipSuccess) {
+    h->err = std::string("HIP event error: ") + hipGetErrorString(pt.err);
+    return PML_PIC_E_HIP;
+  }
+  return PML_PIC_OK;
+}
+
+template <typename T>
+int diagnose_t(pml_pic_handle *h, pml_pic_diag *out) {
+  const Grid<T> g = h->grid<T>();
+  const DiagWork dw = h->diagwork();
+  launch_diag<T>(g, h->fields<T>(), h->parts<T>(h->cur), h->ctl(), (int)h->n_slots, dw, h->stream);
+  HIPCHK(h, hipGetLastError());
+  double res[8];
+  int32_t flags[2];
+  unsigned long long pushes = 0;
+  HIPCHK(h, hipMemcpyAsync(res, dw.result, sizeof(double) * 5, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(flags, dw.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&pushes, h->ctl().pushes, sizeof(pushes), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  long inner = 1;
+  for (int d = 0; d < h->p.dim; ++d) inner *= std::max(0, h->p.n[d] - 1);
+  out->u_interior = res[0];
+  out->u_pml = res[1];
+  out->gauss_max = res[2];
+  out->gauss_l2 = inner > 0 ? std::sqrt(res[3] / (double)inner) : 0.0;
+  out->rho_max = res[4];
+  out->n_particles = flags[1];
+  out->step = h->step;
+  out->n_pushes = (int64_t)pushes;
+  out->nonfinite = flags[0];
+  if (flags[0]) { h->err = "non-finite value in the fields"; return PML_PIC_E_NONFINITE; }
+  return PML_PIC_OK;
+}
+
+template <typename T>
+int get_particles_t(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, double *u, double *w, int64_t *n_out) {
+  int32_t cnt;
+  int rc = read_count(h, &cnt);
+  if (rc) return rc;
+  const int64_t n = std::min<int64_t>(cnt, h->n_slots);
+  const Layout &L = h->L;
+  const int b = h->cur, dim = h->p.dim;
+  std::vector<uint32_t> cell(n);
+  std::vector<T> f[3], uu[3], ww(n);
+  std::vector<int32_t> id(n);
+  for (int d = 0; d < 3; ++d) { f[d].resize(n); uu[d].resize(n); }
+  if (n > 0) {
+    HIPCHK(h, hipMemcpy(cell.data(), h->at<uint32_t>(L.off_cell[b]), 4 * n, hipMemcpyDeviceToHost));
+    for (int d = 0; d < dim; ++d) HIPCHK(h, hipMemcpy(f[d].data(), h->at<T>(L.off_f[b][d]), sizeof(T) * n, hipMemcpyDeviceToHost));
+    for (int d = 0; d < 3; ++d) HIPCHK(h, hipMemcpy(uu[d].data(), h->at<T>(L.off_u[b][d]), sizeof(T) * n, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(ww.data(), h->at<T>(L.off_w[b]), sizeof(T) * n, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(id.data(), h->at<int32_t>(L.off_id[b]), 4 * n, hipMemcpyDeviceToHost));
+  }
+  int64_t m = 0;
+  for (int64_t t = 0; t < n; ++t) {
+    if (cell[t] == DEAD) continue;
+    if (m >= cap) { h->err = "particle output capacity too small"; return PML_PIC_E_CAPACITY; }
+    int ic[3];
+    unpack_cell(dim, cell[t], ic[0], ic[1], ic[2]);
+    ids[m] = id[t];
+    for (int d = 0; d < 3; ++d) {
+      X[3 * m + d] = d < dim ? (double)ic[d] + (double)f[d][t] : 0.0;
+      u[3 * m + d] = (double)uu[d][t];
+    }
+    w[m] = (double)ww[t];
+    ++m;
+  }
+  *n_out = m;
+  return PML_PIC_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes) {
+  if (!bytes) return PML_PIC_E_INVALID_ARG;
+  const int rc = validate(params, &g_create_error);
+  if (rc) return rc;
+  Layout L;
+  make_layout(*params, L);
+  *bytes = L.total;
+  return PML_PIC_OK;
+}
+
+int pml_pic_create(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream,
+                   pml_pic_handle **out) {
+  if (!out) return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(params, &g_create_error);
+  if (rc) return rc;
+  Layout L;
+  make_layout(*params, L);
+  if (!device_workspace || bytes < L.total)
+    return fail(&g_create_error, PML_PIC_E_WORKSPACE, "workspace smaller than pml_pic_workspace_size()");
+  if (((uintptr_t)device_workspace) % 256 != 0)
+    return fail(&g_create_error, PML_PIC_E_WORKSPACE, "workspace must be 256-byte aligned");
+  pml_pic_handle *h = new pml_pic_handle();
+  h->p = *params;
+  h->L = L;
+  h->ws = (char *)device_workspace;
+  h->stream = (hipStream_t)stream;
+  h->sort_interval = params->sort_interval > 0 ? params->sort_interval : 8;
+  build_tables(h);
+  hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    g_create_error = std::string("HIP error while clearing the workspace: ") + hipGetErrorString(e);
+    delete h;
+    return PML_PIC_E_HIP;
+  }
+  rc = params->precision == 64 ? upload_tables<double>(h) : upload_tables<float>(h);
+  if (rc) {
+    g_create_error = h->err;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return PML_PIC_OK;
+}
+
+int pml_pic_add_particles(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!x || !u || !w))) return fail(&h->err, PML_PIC_E_INVALID_ARG, "bad particle arrays");
+  if (n == 0) return PML_PIC_OK;
+  int32_t cnt;
+  int rc = read_count(h, &cnt);
+  if (rc) return rc;
+  const int64_t first = h->sort_pending ? h->n_slots : std::min<int64_t>(cnt, h->n_slots);
+  if (first + n > h->L.cap) return fail(&h->err, PML_PIC_E_CAPACITY, "max_particles exceeded");
+  rc = h->p.precision == 64 ? write_particles<double>(h, first, n, nullptr, nullptr, x, u, w)
+                            : write_particles<float>(h, first, n, nullptr, nullptr, x, u, w);
+  if (rc) return rc;
+  h->n_added += n;
+  h->n_slots = first + n;
+  rc = write_count(h, (int32_t)h->n_slots);
+  if (rc) return rc;
+  double *rs = h->at<double>(h->L.off_rho_static);
+  if (h->p.precision == 64)
+    launch_rho<double>(h->grid<double>(), h->parts<double>(h->cur), h->ctl(), (int)first, (int)h->n_slots, rs, -1.0, h->stream);
+  else
+    launch_rho<float>(h->grid<float>(), h->parts<float>(h->cur), h->ctl(), (int)first, (int)h->n_slots, rs, -1.0, h->stream);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->sort_pending = true;
+  return PML_PIC_OK;
+}
+
+int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X, const double *u,
+                          const double *w) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!ids || !X || !u || !w))) return fail(&h->err, PML_PIC_E_INVALID_ARG, "bad particle arrays");
+  if (n > h->L.cap) return fail(&h->err, PML_PIC_E_CAPACITY, "max_particles exceeded");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int rc = n == 0 ? 0
+                  : (h->p.precision == 64 ? write_particles<double>(h, 0, n, ids, X, nullptr, u, w)
+                                          : write_particles<float>(h, 0, n, ids, X, nullptr, u, w));
+  if (rc) return rc;
+  h->n_slots = n;
+  for (int64_t t = 0; t < n; ++t) h->n_added = std::max<int64_t>(h->n_added, ids[t] + 1);
+  rc = write_count(h, (int32_t)n);
+  if (rc) return rc;
+  h->sort_pending = true;
+  return PML_PIC_OK;
+}
+
+int pml_pic_step(pml_pic_handle *h, int32_t n_steps) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  if (n_steps < 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
+  PhaseTimer pt;
+  return h->p.precision == 64 ? step_t<double>(h, n_steps, pt) : step_t<float>(h, n_steps, pt);
+}
+
+int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
+  if (!h || !phase_ms || !phase_calls) return PML_PIC_E_INVALID_ARG;
+  if (n_steps < 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
+  PhaseTimer pt;
+  pt.h = h;
+  pt.on = true;
+  int rc = h->p.precision == 64 ? step_t<double>(h, n_steps, pt) : step_t<float>(h, n_steps, pt);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (rc == PML_PIC_OK && e != hipSuccess) {
+    h->err = std::string("HIP error: ") + hipGetErrorString(e);
+    rc = PML_PIC_E_HIP;
+  }
+  for (size_t k = 0; k < pt.phase.size() && 2 * k + 1 < pt.ev.size(); ++k) {
+    float ms = 0.f;
+    if (rc == PML_PIC_OK && hipEventElapsedTime(&ms, pt.ev[2 * k], pt.ev[2 * k + 1]) == hipSuccess) {
+      phase_ms[pt.phase[k]] += ms;
+      phase_calls[pt.phase[k]] += 1;
+    }
+  }
+  for (hipEvent_t ev : pt.ev) (void)hipEventDestroy(ev);
+  return rc;
+}
+
+int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out) {
+  if (!h || !out) return PML_PIC_E_INVALID_ARG;
+  return h->p.precision == 64 ? diagnose_t<double>(h, out) : diagnose_t<float>(h, out);
+}
+
+int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples) {
+  if (!h || !nn || !n_samples) return PML_PIC_E_INVALID_ARG;
+  for (int d = 0; d < 3; ++d) nn[d] = h->L.nn[d];
+  *n_samples = (int64_t)h->L.nn[0] * h->L.nn[1] * h->L.nn[2];
+  return PML_PIC_OK;
+}
+
+static int64_t n_samples_of(const pml_pic_handle *h) { return (int64_t)h->L.nn[0] * h->L.nn[1] * h->L.nn[2]; }
+
+int pml_pic_get_fields(pml_pic_handle *h, double *host, int64_t count) {
+  if (!h || !host) return PML_PIC_E_INVALID_ARG;
+  if (count < 12 * n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "field buffer too small");
+  return h->p.precision == 64 ? get_fields_t<double>(h, host) : get_fields_t<float>(h, host);
+}
+
+int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count) {
+  if (!h || !host) return PML_PIC_E_INVALID_ARG;
+  if (count < 12 * n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "field buffer too small");
+  return h->p.precision == 64 ? set_fields_t<double>(h, host) : set_fields_t<float>(h, host);
+}
+
+int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count) {
+  if (!h || !host) return PML_PIC_E_INVALID_ARG;
+  if (count < 3 * n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "current buffer too small");
+  return h->p.precision == 64 ? get_current_t<double>(h, host) : get_current_t<float>(h, host);
+}
+
+int pml_pic_get_rho_static(pml_pic_handle *h, double *host, int64_t count) {
+  if (!h || !host) return PML_PIC_E_INVALID_ARG;
+  const Layout &L = h->L;
+  if (count < n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "buffer too small");
+  std::vector<double> buf(L.nelem);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpy(buf.data(), h->at<double>(L.off_rho_static), 8 * L.nelem, hipMemcpyDeviceToHost));
+  for (int k = 0; k < L.nn[2]; ++k)
+    for (int j = 0; j < L.nn[1]; ++j)
+      for (int i = 0; i < L.nn[0]; ++i)
+        host[((size_t)k * L.nn[1] + j) * L.nn[0] + i] = buf[L.base + i + j * L.sy + k * L.sz];
+  return PML_PIC_OK;
+}
+
+int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count) {
+  if (!h || !host) return PML_PIC_E_INVALID_ARG;
+  const Layout &L = h->L;
+  if (count < n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "buffer too small");
+  std::vector<double> buf(L.nelem, 0.0);
+  for (int k = 0; k < L.nn[2]; ++k)
+    for (int j = 0; j < L.nn[1]; ++j)
+      for (int i = 0; i < L.nn[0]; ++i)
+        buf[L.base + i + j * L.sy + k * L.sz] = host[((size_t)k * L.nn[1] + j) * L.nn[0] + i];
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpy(h->at<double>(L.off_rho_static), buf.data(), 8 * L.nelem, hipMemcpyHostToDevice));
+  return PML_PIC_OK;
+}
+
+int pml_pic_num_particles(pml_pic_handle *h, int64_t *n) {
+  if (!h || !n) return PML_PIC_E_INVALID_ARG;
+  pml_pic_diag d;
+  const int rc = pml_pic_diagnose(h, &d);
+  if (rc && rc != PML_PIC_E_NONFINITE) return rc;
+  *n = d.n_particles;
+  return PML_PIC_OK;
+}
+
+int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, double *u, double *w,
+                          int64_t *n_out) {
+  if (!h || !n_out || (cap > 0 && (!ids || !X || !u || !w))) return PML_PIC_E_INVALID_ARG;
+  return h->p.precision == 64 ? get_particles_t<double>(h, cap, ids, X, u, w, n_out)
+                              : get_particles_t<float>(h, cap, ids, X, u, w, n_out);
+}
+
+const char *pml_pic_last_error(const pml_pic_handle *h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+void pml_pic_destroy(pml_pic_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Device-side views and helpers shared by the HIP kernels of the PML PIC library.
+//
+// Layout in HBM (all arrays live in one caller-owned workspace):
+//   * field arrays (E, B totals, one split part per component, J) are 3D blocks with
+//     G guard layers on every side of every in-plane axis, x fastest, row pitch padded
+//     to a multiple of 64 elements; sample (i,j,k) of a component is at
+//     base + i + j*sy + k*sz.  Guard and out-of-extent samples hold 0 and are never
+//     updated, so stencils near the PEC walls read zeros without bounds checks;
+//   * per-axis 1D coefficient tables (sigma, exponential factors, alpha) at nodes and
+//     cell centres, built in FP64 on the host;
+//   * particles as structure-of-arrays: packed cell index (int per axis, +1 offset),
+//     offsets in [0,1) within the cell, u = gamma v, weight, id.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmlpic {
+
+constexpr int G = 4;                 // guard layers per side
+constexpr uint32_t DEAD = 0xFFFFFFFFu;
+
+// kinds of per-axis table entries; node tables then centre tables
+// (T_GK_N = g * (1/dx) of that axis at nodes for a full step; T_GHK_C = the same at
+// centres for a half step: the factors that multiply a raw neighbour difference)
+enum TabKind {
+  T_SIG_N = 0, T_E_N, T_G_N, T_EH_N, T_GH_N, T_A_N,
+  T_SIG_C, T_E_C, T_G_C, T_EH_C, T_GH_C, T_A_C,
+  T_GK_N, T_GHK_C,
+  T_NKIND
+};
+
+template <typename T>
+struct Grid {
+  int dim, order;
+  int M[3];            // cells per axis including the PML (0 on the invariant axis)
+  int lo[3], n[3];     // PML cells on the low side, physical cells
+  long sy, sz;         // strides of y and z (x stride is 1)
+  long base;           // offset of sample (0,0,0)
+  long nelem;          // elements per field array
+  int ext[3];          // allocated extent per axis (incl. guards)
+  T dt;
+  T inv_dx[3];
+  T qdt_2m;            // charge dt / (2 mass)
+  T charge;
+  const T *tab;        // [3][T_NKIND][ntab], entry i + G for index i in [-G, M+G]
+  int ntab;
+
+  __host__ __device__ long at(int i, int j, int k) const { return base + i + j * sy + k * sz; }
+  __device__ T tb(int axis, int kind, int i) const {
+    return tab[(axis * T_NKIND + kind) * ntab + i + G];
+  }
+};
+
+template <typename T>
+struct Fields {
+  T *E[3];
+  T *B[3];
+  T *Ea[3];   // split part E_ab, b = a+1 (valid where the component is split)
+  T *Ba[3];   // split part B_ab, b = a+1
+  T *J[3];
+};
+
+template <typename T>
+struct Parts {
+  uint32_t *cell;     // packed (i+1) per axis; DEAD for removed particles
+  T *f[3];            // offsets in [0,1)
+  T *u[3];            // gamma v
+  T *w;               // weight
+  int32_t *id;
+};
+
+// --------------------------------------------------------------- packed cells
+// 2D: 16 bits per axis; 3D: 11 / 11 / 10 bits.  Stored value is index + 1, so a
+// particle one cell outside the grid (just before removal) is representable.
+__host__ __device__ inline uint32_t pack_cell(int dim, int i, int j, int k) {
+  if (dim == 2) return (uint32_t)(i + 1) | ((uint32_t)(j + 1) << 16);
+  return (uint32_t)(i + 1) | ((uint32_t)(j + 1) << 11) | ((uint32_t)(k + 1) << 22);
+}
+__host__ __device__ inline void unpack_cell(int dim, uint32_t c, int &i, int &j, int &k) {
+  if (dim == 2) { i = (int)(c & 0xFFFFu) - 1; j = (int)(c >> 16) - 1; k = 0; return; }
+  i = (int)(c & 0x7FFu) - 1; j = (int)((c >> 11) & 0x7FFu) - 1; k = (int)(c >> 22) - 1;
+}
+
+// --------------------------------------------------------------- shapes
+// Centred B-spline weights of order ORDER (1 linear, 2 quadratic, 3 cubic) for a point
+// at offset f in [0,1) from node i: the stencil is nodes i+start .. i+start+ORDER.
+template <int ORDER, typename T>
+__device__ __forceinline__ int shape_weights(T f, T (&w)[ORDER + 1]) {
+  if constexpr (ORDER == 1) {
+    w[0] = T(1) - f;
+    w[1] = f;
+    return 0;
+  } else if constexpr (ORDER == 2) {
+    const int up = f >= T(0.5);
+    const T d = f - T(up);                 // distance to the nearest node, [-1/2, 1/2)
+    const T a = T(0.5) - d, b = T(0.5) + d;
+    w[0] = T(0.5) * a * a;
+    w[1] = T(0.75) - d * d;
+    w[2] = T(0.5) * b * b;
+    return up - 1;
+  } else {
+    const T g = T(1) - f;
+    const T f2 = f * f, g2 = g * g;
+    w[0] = g2 * g * T(1.0 / 6.0);
+    w[1] = (T(4) - T(6) * f2 + T(3) * f2 * f) * T(1.0 / 6.0);
+    w[2] = (T(4) - T(6) * g2 + T(3) * g2 * g) * T(1.0 / 6.0);
+    w[3] = f2 * f * T(1.0 / 6.0);
+    return -1;
+  }
+}
+
+// Same for the half-integer sample positions (index s refers to s + 1/2).
+template <int ORDER, typename T>
+__device__ __forceinline__ int shape_weights_stag(int i, T f, T (&w)[ORDER + 1]) {
+  int ii;
+  T ff;
+  if (f >= T(0.5)) { ii = i; ff = f - T(0.5); }
+  else { ii = i - 1; ff = f + T(0.5); if (ff >= T(1)) { ff = T(0); ii = i; } }
+  return ii + shape_weights<ORDER>(ff, w);
+}
+
+// --------------------------------------------------------------- atomics
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// --------------------------------------------------------------- launch wrappers
+struct StepCtl {
+  int32_t *count;          // device: live particle slots in use
+  unsigned long long *pushes;
+};
+
+template <typename T>
+void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool half, hipStream_t s);
+template <typename T>
+void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode,
+                     hipStream_t s);
+template <typename T>
+void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
+template <typename T>
+void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
+                        StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s);
+template <typename T>
+void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
+                    StepCtl ctl, int n_slots, hipStream_t s);
+
+struct SortWork {
+  uint32_t *counts;      // nkeys + 1
+  uint32_t *rank;        // per particle
+  uint32_t *blocksums;   // scan scratch
+  int nkeys;
+  int tile[3];
+  int ntile[3];
+};
+template <typename T>
+void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, SortWork sw,
+                 StepCtl ctl, int n_slots, hipStream_t s);
+
+struct DiagWork {
+  double *rho;           // nelem
+  const double *rho_static;
+  double *partial;       // per block scratch
+  double *result;        // 8 doubles
+  int32_t *flags;        // [0] nonfinite, [1] live count
+  int max_blocks;
+};
+template <typename T>
+void launch_diag(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+                 int n_slots, DiagWork dw, hipStream_t s);
+template <typename T>
+void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int n_slots, double *rho,
+                double sign, hipStream_t s);
+
+}  // namespace pmlpic

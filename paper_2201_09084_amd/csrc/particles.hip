@@ -1,0 +1,442 @@
+// gather_push, deposit_current and sort_particles.
+//
+// gather_push: the six total field components (sum of the split parts, Eq. MaxwellSum)
+// are interpolated at the particle with the same-order B-spline at each component's
+// staggered Yee position, then the relativistic Boris rotation advances u = gamma v,
+// and the particle moves by dt u/gamma.  Positions are an integer cell per axis plus
+// an offset in [0,1); the offset is re-based when it leaves [0,1).
+//
+// deposit_current: Esirkepov's charge-conserving scheme (used in App. A) for the move
+// x^n -> x^{n+1} on the (order+2)-node window that covers both shapes; the running
+// sums along each axis give J at E's staggered samples.  Accumulated with hardware
+// float atomics (order-nondeterministic).  Particles that end outside the PEC box
+// deposit this step and are then marked DEAD.
+//
+// The fused kernel does both for one particle in registers, so x^n and x^{n+1} are
+// exactly the stored positions of consecutive steps (exact discrete continuity).
+#include "common.h"
+
+namespace pmlpic {
+
+template <int ORDER, typename T>
+struct Shape3 {
+  T wn[3][ORDER + 1];
+  T wc[3][ORDER + 1];
+  int sn[3], sc[3];
+};
+
+template <typename T, int DIM, int ORDER>
+__device__ __forceinline__ void shape_all(const int (&id)[3], const T (&f)[3], Shape3<ORDER, T> &S) {
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    S.sn[d] = id[d] + shape_weights<ORDER>(f[d], S.wn[d]);
+    S.sc[d] = shape_weights_stag<ORDER>(id[d], f[d], S.wc[d]);
+  }
+}
+
+// interpolate one component whose stagger bits are MASK (bit d: half-integer along d)
+template <typename T, int DIM, int ORDER, int MASK>
+__device__ __forceinline__ T gather_comp(const Grid<T> &g, const T *__restrict__ arr,
+                                         const Shape3<ORDER, T> &S) {
+  constexpr bool hx = MASK & 1, hy = MASK & 2, hz = MASK & 4;
+  const int x0 = hx ? S.sc[0] : S.sn[0];
+  const int y0 = hy ? S.sc[1] : S.sn[1];
+  T acc = T(0);
+  if constexpr (DIM == 2) {
+    const long q0 = g.at(x0, y0, 0);
+#pragma unroll
+    for (int b = 0; b <= ORDER; ++b) {
+      T row = T(0);
+#pragma unroll
+      for (int a = 0; a <= ORDER; ++a) row += (hx ? S.wc[0][a] : S.wn[0][a]) * arr[q0 + b * g.sy + a];
+      acc += (hy ? S.wc[1][b] : S.wn[1][b]) * row;
+    }
+  } else {
+    const int z0 = hz ? S.sc[2] : S.sn[2];
+    const long q0 = g.at(x0, y0, z0);
+#pragma unroll
+    for (int c = 0; c <= ORDER; ++c) {
+      T pl = T(0);
+#pragma unroll
+      for (int b = 0; b <= ORDER; ++b) {
+        T row = T(0);
+#pragma unroll
+        for (int a = 0; a <= ORDER; ++a)
+          row += (hx ? S.wc[0][a] : S.wn[0][a]) * arr[q0 + c * g.sz + b * g.sy + a];
+        pl += (hy ? S.wc[1][b] : S.wn[1][b]) * row;
+      }
+      acc += (hz ? S.wc[2][c] : S.wn[2][c]) * pl;
+    }
+  }
+  return acc;
+}
+
+template <typename T, int DIM, int ORDER>
+__device__ __forceinline__ void gather(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
+                                       const T (&f)[3], T (&EB)[6]) {
+  Shape3<ORDER, T> S;
+  shape_all<T, DIM, ORDER>(id, f, S);
+  EB[0] = gather_comp<T, DIM, ORDER, 1>(g, F.E[0], S);
+  EB[1] = gather_comp<T, DIM, ORDER, 2>(g, F.E[1], S);
+  EB[2] = gather_comp<T, DIM, ORDER, 4>(g, F.E[2], S);
+  EB[3] = gather_comp<T, DIM, ORDER, 6>(g, F.B[0], S);
+  EB[4] = gather_comp<T, DIM, ORDER, 5>(g, F.B[1], S);
+  EB[5] = gather_comp<T, DIM, ORDER, 3>(g, F.B[2], S);
+}
+
+// relativistic Boris rotation (Boris 1970)
+template <typename T>
+__device__ __forceinline__ void boris(T k, const T (&EB)[6], T (&u)[3]) {
+  const T mx = u[0] + k * EB[0], my = u[1] + k * EB[1], mz = u[2] + k * EB[2];
+  const T ig = T(1) / sqrt(T(1) + mx * mx + my * my + mz * mz);
+  const T tx = k * EB[3] * ig, ty = k * EB[4] * ig, tz = k * EB[5] * ig;
+  const T s = T(2) / (T(1) + tx * tx + ty * ty + tz * tz);
+  const T px = mx + (my * tz - mz * ty);
+  const T py = my + (mz * tx - mx * tz);
+  const T pz = mz + (mx * ty - my * tx);
+  u[0] = mx + s * (py * tz - pz * ty) + k * EB[0];
+  u[1] = my + s * (pz * tx - px * tz) + k * EB[1];
+  u[2] = mz + s * (px * ty - py * tx) + k * EB[2];
+}
+
+// x^{n+1} = x^n + dt u/gamma; returns true if the particle is still inside the PEC box
+template <typename T, int DIM>
+__device__ __forceinline__ bool move(const Grid<T> &g, int (&id)[3], T (&f)[3], const T (&u)[3], T &inv_gamma) {
+  inv_gamma = T(1) / sqrt(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const T disp = (g.dt * g.inv_dx[d]) * (u[d] * inv_gamma);
+    T nf = f[d] + disp;
+    if (nf >= T(1)) { nf -= T(1); id[d] += 1; }
+    else if (nf < T(0)) {
+      nf += T(1); id[d] -= 1;
+      if (nf >= T(1)) { nf = T(0); id[d] += 1; }
+    }
+    f[d] = nf;
+    inside = inside && id[d] >= 0 && id[d] < g.M[d];
+  }
+  return inside;
+}
+
+// Esirkepov deposit of charge qw moving (i0,f0) -> (i1,f1); vz used in 2D only
+template <typename T, int DIM, int ORDER>
+__device__ __forceinline__ void deposit(const Grid<T> &g, const Fields<T> &F, const int (&i0)[3],
+                                        const T (&f0)[3], const int (&i1)[3], const T (&f1)[3],
+                                        T vz, T qw) {
+  constexpr int W = ORDER + 2;
+  T S0[3][W], S1[3][W];
+  int ws[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    T w0[ORDER + 1], w1[ORDER + 1];
+    const int s0 = i0[d] + shape_weights<ORDER>(f0[d], w0);
+    const int s1 = i1[d] + shape_weights<ORDER>(f1[d], w1);
+    const int st = s0 < s1 ? s0 : s1;
+    ws[d] = st;
+    const bool o0 = s0 != st, o1 = s1 != st;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      S0[d][k] = o0 ? (k >= 1 ? w0[k - 1 < ORDER ? k - 1 : ORDER] : T(0)) : (k <= ORDER ? w0[k <= ORDER ? k : ORDER] : T(0));
+      S1[d][k] = o1 ? (k >= 1 ? w1[k - 1 < ORDER ? k - 1 : ORDER] : T(0)) : (k <= ORDER ? w1[k <= ORDER ? k : ORDER] : T(0));
+    }
+  }
+  if constexpr (DIM == 2) {
+    const long q0 = g.at(ws[0], ws[1], 0);
+    const T cx = qw * g.inv_dx[1] / g.dt;
+    const T cy = qw * g.inv_dx[0] / g.dt;
+    const T cz = qw * vz * g.inv_dx[0] * g.inv_dx[1];
+#pragma unroll
+    for (int b = 0; b < W; ++b) {            // J_x: running sum along x
+      const T sy = S0[1][b] + S1[1][b];
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < W - 1; ++a) {
+        acc -= cx * T(0.5) * (S1[0][a] - S0[0][a]) * sy;
+        if (acc != T(0)) atomic_add(&F.J[0][q0 + b * g.sy + a], acc);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < W; ++a) {            // J_y: running sum along y
+      const T sx = S0[0][a] + S1[0][a];
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < W - 1; ++b) {
+        acc -= cy * T(0.5) * (S1[1][b] - S0[1][b]) * sx;
+        if (acc != T(0)) atomic_add(&F.J[1][q0 + b * g.sy + a], acc);
+      }
+    }
+    if (cz != T(0)) {
+#pragma unroll
+      for (int b = 0; b < W; ++b)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+          const T wz = (S0[0][a] * S0[1][b] + S1[0][a] * S1[1][b]) * T(1.0 / 3.0) +
+                       (S1[0][a] * S0[1][b] + S0[0][a] * S1[1][b]) * T(1.0 / 6.0);
+          if (wz != T(0)) atomic_add(&F.J[2][q0 + b * g.sy + a], cz * wz);
+        }
+    }
+  } else {
+    const long q0 = g.at(ws[0], ws[1], ws[2]);
+    const long st[3] = {1L, g.sy, g.sz};
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+      const int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
+      const T coef = qw * g.inv_dx[Bx] * g.inv_dx[Cx] / g.dt;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+          const T avg = (S0[Bx][b] * S0[Cx][c] + S1[Bx][b] * S1[Cx][c]) * T(1.0 / 3.0) +
+                        (S1[Bx][b] * S0[Cx][c] + S0[Bx][b] * S1[Cx][c]) * T(1.0 / 6.0);
+          if (avg == T(0)) continue;
+          T acc = T(0);
+#pragma unroll
+          for (int a = 0; a < W - 1; ++a) {
+            acc -= coef * (S1[A][a] - S0[A][a]) * avg;
+            if (acc != T(0)) atomic_add(&F.J[A][q0 + a * st[A] + b * st[Bx] + c * st[Cx]], acc);
+          }
+        }
+    }
+  }
+}
+
+__device__ __forceinline__ void count_pushes(unsigned long long *pushes, bool active) {
+  const unsigned long long m = __ballot(active);
+  if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1))
+    atomicAdd(pushes, (unsigned long long)__popcll(m));
+}
+
+// fused (fused = true) or first half (fused = false) of the particle step
+template <typename T, int DIM, int ORDER>
+__global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Parts<T> P, Parts<T> old,
+                                                      StepCtl ctl, int n_slots, int push, bool fused) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int count = *ctl.count;
+  bool active = false;
+  if (p < n_slots && p < count) {
+    const uint32_t c = P.cell[p];
+    if (c != DEAD) {
+      active = true;
+      int id[3];
+      unpack_cell(DIM, c, id[0], id[1], id[2]);
+      T f[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
+      T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+      if (push) {
+        T EB[6];
+        gather<T, DIM, ORDER>(g, F, id, f, EB);
+        boris(g.qdt_2m, EB, u);
+      }
+      const int id0[3] = {id[0], id[1], id[2]};
+      const T f0[3] = {f[0], f[1], f[2]};
+      T ig;
+      const bool inside = move<T, DIM>(g, id, f, u, ig);
+      P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
+      if (fused) {
+        deposit<T, DIM, ORDER>(g, F, id0, f0, id, f, u[2] * ig, g.charge * P.w[p]);
+        P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
+      } else {
+        old.cell[p] = c;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) old.f[d][p] = f0[d];
+        P.cell[p] = pack_cell(DIM, id[0], id[1], id[2]);
+      }
+    }
+  }
+  count_pushes(ctl.pushes, active);
+}
+
+// second half of the unfused particle step: deposit from the saved x^n to x^{n+1}
+template <typename T, int DIM, int ORDER>
+__global__ void __launch_bounds__(256) k_deposit(Grid<T> g, Fields<T> F, Parts<T> P, Parts<T> old,
+                                                  StepCtl ctl, int n_slots) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots || p >= *ctl.count) return;
+  const uint32_t c = P.cell[p];
+  if (c == DEAD) return;
+  int i1[3], i0[3];
+  unpack_cell(DIM, c, i1[0], i1[1], i1[2]);
+  unpack_cell(DIM, old.cell[p], i0[0], i0[1], i0[2]);
+  const T f1[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
+  const T f0[3] = {old.f[0][p], old.f[1][p], DIM == 3 ? old.f[2][p] : T(0)};
+  const T ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
+  const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
+  deposit<T, DIM, ORDER>(g, F, i0, f0, i1, f1, uz * ig, g.charge * P.w[p]);
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) inside = inside && i1[d] >= 0 && i1[d] < g.M[d];
+  if (!inside) P.cell[p] = DEAD;
+}
+
+#define PMLPIC_DISPATCH_ORDER(DIMV, KERNEL, ...)                                         \
+  switch (g.order) {                                                                    \
+    case 1: hipLaunchKernelGGL((KERNEL<T, DIMV, 1>), grd, blk, 0, s, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<T, DIMV, 2>), grd, blk, 0, s, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<T, DIMV, 3>), grd, blk, 0, s, __VA_ARGS__); break; \
+  }
+
+template <typename T>
+void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
+                        StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s) {
+  if (n_slots <= 0) return;
+  dim3 blk(256), grd((n_slots + 255) / 256);
+  if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
+  else { PMLPIC_DISPATCH_ORDER(3, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
+}
+
+template <typename T>
+void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
+                    StepCtl ctl, int n_slots, hipStream_t s) {
+  if (n_slots <= 0) return;
+  dim3 blk(256), grd((n_slots + 255) / 256);
+  if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_deposit, g, F, P, old, ctl, n_slots) }
+  else { PMLPIC_DISPATCH_ORDER(3, k_deposit, g, F, P, old, ctl, n_slots) }
+}
+
+// ------------------------------------------------------------------ sort_particles
+// Counting sort by a tile-major cell key: cells of one tile are contiguous in key
+// space, so each tile's particles form one contiguous range, ordered by cell.
+// Removed particles get no key and are dropped (compaction).
+
+__device__ __forceinline__ uint32_t cell_key(int dim, const SortWork &sw, int i, int j, int k) {
+  const int tx = i / sw.tile[0], lx = i - tx * sw.tile[0];
+  const int ty = j / sw.tile[1], ly = j - ty * sw.tile[1];
+  const int tz = k / sw.tile[2], lz = k - tz * sw.tile[2];
+  const uint32_t tile = ((uint32_t)tz * sw.ntile[1] + ty) * sw.ntile[0] + tx;
+  const uint32_t local = ((uint32_t)lz * sw.tile[1] + ly) * sw.tile[0] + lx;
+  return tile * (uint32_t)(sw.tile[0] * sw.tile[1] * sw.tile[2]) + local;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_hist(int dim, Parts<T> P, SortWork sw, StepCtl ctl, int n_slots) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots || p >= *ctl.count) return;
+  const uint32_t c = P.cell[p];
+  if (c == DEAD) return;
+  int i, j, k;
+  unpack_cell(dim, c, i, j, k);
+  const uint32_t key = cell_key(dim, sw, i, j, k);
+  sw.rank[p] = atomicAdd(&sw.counts[key], 1u);
+}
+
+constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+// block-wide exclusive scan of SCAN_TILE counts; block totals to blocksums
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_local(uint32_t *counts, int n, uint32_t *blocksums) {
+  __shared__ uint32_t sh[SCAN_BLOCK];
+  const int t = threadIdx.x;
+  const long base = (long)blockIdx.x * SCAN_TILE + (long)t * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int e = 0; e < SCAN_ITEMS; ++e) {
+    v[e] = (base + e < n) ? counts[base + e] : 0u;
+    sum += v[e];
+  }
+  sh[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+    const uint32_t add = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  uint32_t run = sh[t] - sum;   // exclusive prefix of this thread
+#pragma unroll
+  for (int e = 0; e < SCAN_ITEMS; ++e) {
+    if (base + e < n) counts[base + e] = run;
+    run += v[e];
+  }
+  if (t == SCAN_BLOCK - 1) blocksums[blockIdx.x] = sh[t];
+}
+
+// exclusive scan of the block totals in one block; writes the grand total to *total
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_blocks(uint32_t *blocksums, int nb, int32_t *total) {
+  __shared__ uint32_t sh[SCAN_BLOCK];
+  __shared__ uint32_t carry;
+  const int t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int start = 0; start < nb; start += SCAN_BLOCK) {
+    const uint32_t v = (start + t < nb) ? blocksums[start + t] : 0u;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+      const uint32_t add = t >= off ? sh[t - off] : 0u;
+      __syncthreads();
+      sh[t] += add;
+      __syncthreads();
+    }
+    if (start + t < nb) blocksums[start + t] = carry + sh[t] - v;
+    __syncthreads();
+    if (t == SCAN_BLOCK - 1) carry += sh[t];
+    __syncthreads();
+  }
+  if (t == 0) *total = (int32_t)carry;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_add(uint32_t *counts, int n, const uint32_t *blocksums) {
+  const long base = (long)blockIdx.x * SCAN_TILE + (long)threadIdx.x * SCAN_ITEMS;
+  const uint32_t add = blocksums[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < SCAN_ITEMS; ++e)
+    if (base + e < n) counts[base + e] += add;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_scatter(int dim, Parts<T> src, Parts<T> dst, SortWork sw,
+                                                      const int32_t *old_count, int n_slots) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots || p >= *old_count) return;
+  const uint32_t c = src.cell[p];
+  if (c == DEAD) return;
+  int i, j, k;
+  unpack_cell(dim, c, i, j, k);
+  const uint32_t key = cell_key(dim, sw, i, j, k);
+  const uint32_t q = sw.counts[key] + sw.rank[p];
+  dst.cell[q] = c;
+  for (int d = 0; d < dim; ++d) dst.f[d][q] = src.f[d][p];
+  dst.u[0][q] = src.u[0][p];
+  dst.u[1][q] = src.u[1][p];
+  dst.u[2][q] = src.u[2][p];
+  dst.w[q] = src.w[p];
+  dst.id[q] = src.id[p];
+}
+
+__global__ void k_copy_count(const int32_t *src, int32_t *dst) { *dst = *src; }
+
+template <typename T>
+void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, SortWork sw,
+                 StepCtl ctl, int n_slots, hipStream_t s) {
+  if (n_slots <= 0) return;
+  const int nb = (sw.nkeys + SCAN_TILE - 1) / SCAN_TILE;
+  hipMemsetAsync(sw.counts, 0, sizeof(uint32_t) * (size_t)sw.nkeys, s);
+  dim3 blk(256), grd((n_slots + 255) / 256);
+  hipLaunchKernelGGL((k_sort_hist<T>), grd, blk, 0, s, g.dim, src, sw, ctl, n_slots);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, sw.counts, sw.nkeys, sw.blocksums);
+  // the new count goes to a scratch slot first: the scatter still needs the old one
+  int32_t *new_count = (int32_t *)(sw.blocksums + nb);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, sw.blocksums, nb, new_count);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, sw.counts, sw.nkeys, sw.blocksums);
+  hipLaunchKernelGGL((k_sort_scatter<T>), grd, blk, 0, s, g.dim, src, dst, sw, ctl.count, n_slots);
+  hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, new_count, ctl.count);
+}
+
+template void launch_gather_push<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
+                                        Parts<float>, StepCtl, int, int, bool, hipStream_t);
+template void launch_gather_push<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
+                                         Parts<double>, StepCtl, int, int, bool, hipStream_t);
+template void launch_deposit<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
+                                    Parts<float>, StepCtl, int, hipStream_t);
+template void launch_deposit<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
+                                     Parts<double>, StepCtl, int, hipStream_t);
+template void launch_sort<float>(const Grid<float> &, const Parts<float> &, const Parts<float> &, SortWork,
+                                 StepCtl, int, hipStream_t);
+template void launch_sort<double>(const Grid<double> &, const Parts<double> &, const Parts<double> &, SortWork,
+                                  StepCtl, int, hipStream_t);
+
+}  // namespace pmlpic

@@ -224,10 +224,11 @@ def batch_runs(n_runs: int = 256, seed: int = 1003, steps_to_cross: int = 300,
 def random_particles(cfg: SimConfig, n: int, seed: int, margin: float = 3.0,
                      umax: float = 3.0, region=None) -> Particles:
     """Uniformly placed particles over the whole grid including the PML (kept
-    `margin` cells away from the outer walls), momenta uniform in [-umax, umax]^3."""
+    `margin` cells away from the outer walls), momenta uniform in [-umax, umax]^3.
+    Positions are physical (cells times dx)."""
     rng = np.random.default_rng(seed)
-    lo = np.array([-cfg.pml[d][0] + margin for d in range(cfg.dim)])
-    hi = np.array([cfg.n[d] + cfg.pml[d][1] - margin for d in range(cfg.dim)])
+    lo = np.array([(-cfg.pml[d][0] + margin) * cfg.dx[d] for d in range(cfg.dim)])
+    hi = np.array([(cfg.n[d] + cfg.pml[d][1] - margin) * cfg.dx[d] for d in range(cfg.dim)])
     if region is not None:
         lo, hi = np.asarray(region[0], float), np.asarray(region[1], float)
     x = lo + (hi - lo) * rng.uniform(0.0, 1.0, (n, cfg.dim))

@@ -1,0 +1,82 @@
+"""Host-only checks of the C ABI: the library loads, exports every function that
+include/pml_pic.h declares, and rejects bad parameters with the documented status
+codes (pml_pic_workspace_size validates without touching a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2201_09084_amd import binding as B
+from paper_2201_09084_amd import workloads as W
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pml_pic.h")
+
+
+def _declared_functions():
+    text = open(HDR).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pml_pic_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return B.load_library()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(B.EXPORTED) == set(names)
+
+
+def _size(cfg, **kw):
+    p = B.make_params(cfg, max_particles=kw.pop("max_particles", 16))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    n = C.c_size_t(0)
+    rc = B.load_library().pml_pic_workspace_size(C.byref(p), C.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_valid_configs(lib):
+    rc, n = _size(W.single_particle_config())
+    assert rc == 0 and n > 0
+    rc2, n2 = _size(W.single_particle_config(precision=32))
+    assert rc2 == 0 and n2 < n
+    rc3, n3 = _size(W.beam3d_config(), max_particles=17 << 20)
+    assert rc3 == 0 and n3 > 3e9
+
+
+def test_parameter_validation_codes(lib):
+    cfg = W.single_particle_config()
+    assert _size(cfg, dt=0.71)[0] == -2                  # beyond the 2D Yee CFL limit 1/sqrt(2)
+    assert _size(cfg, dim=4)[0] == -1
+    assert _size(cfg, shape_order=4)[0] == -1
+    assert _size(cfg, alpha_mode=3)[0] == -1
+    assert _size(cfg, precision=16)[0] == -1
+    assert _size(cfg, max_particles=-1)[0] == -1
+    p = B.make_params(cfg)
+    p.pml[0][1] = 200                                     # thicker than the 128-cell box
+    n = C.c_size_t()
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
+    p = B.make_params(cfg)
+    p.sigma_coef[0][3] = -1.0                             # negative conductivity
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
+    assert b"negative" in lib.pml_pic_last_error(None)
+    p = B.make_params(cfg)
+    p.dx[0] = 0.0
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
+
+
+def test_create_rejects_small_or_missing_workspace(lib):
+    p = B.make_params(W.single_particle_config(), max_particles=4)
+    h = C.c_void_p()
+    assert lib.pml_pic_create(C.byref(p), None, C.c_size_t(0), None, C.byref(h)) == -3
+    assert lib.pml_pic_create(C.byref(p), C.c_void_p(256), C.c_size_t(10), None, C.byref(h)) == -3
+    assert not h.value
