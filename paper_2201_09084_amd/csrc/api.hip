@@ -154,7 +154,7 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_oldcell = take(4 * cap);
   for (int d = 0; d < 3; ++d) L.off_oldf[d] = d < p.dim ? take(L.esz * cap) : 0;
   L.off_count = take(8);
-  L.off_pushes = take(8);
+  L.off_pushes = take(8 * N_PUSH_COUNTERS);
   L.off_counts = take(4 * ((size_t)L.nkeys + 1));
   L.off_rank = take(4 * cap);
   L.off_blocksums = take(4 * ((size_t)L.nscan + 2));
@@ -531,7 +531,8 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     pt.end(s, PML_PIC_PHASE_CLEAR_J);
     const Parts<T> P = h->parts<T>(h->cur);
     pt.begin(s);
-    launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
+    if (fused && use_sort) launch_push_deposit_tiled<T>(g, F, P, ctl, ns, h->p.push, s);
+    else launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
     pt.end(s, PML_PIC_PHASE_PUSH);
     if (!fused) {
       pt.begin(s);
@@ -571,11 +572,13 @@ int diagnose_t(pml_pic_handle *h, pml_pic_diag *out) {
   HIPCHK(h, hipGetLastError());
   double res[8];
   int32_t flags[2];
+  unsigned long long pushv[N_PUSH_COUNTERS];
   unsigned long long pushes = 0;
   HIPCHK(h, hipMemcpyAsync(res, dw.result, sizeof(double) * 5, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(flags, dw.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(&pushes, h->ctl().pushes, sizeof(pushes), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(pushv, h->ctl().pushes, sizeof(pushv), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int k = 0; k < N_PUSH_COUNTERS; ++k) pushes += pushv[k];
   long inner = 1;
   for (int d = 0; d < h->p.dim; ++d) inner *= std::max(0, h->p.n[d] - 1);
   out->u_interior = res[0];

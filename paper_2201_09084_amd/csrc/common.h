@@ -125,9 +125,11 @@ __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // --------------------------------------------------------------- launch wrappers
+constexpr int N_PUSH_COUNTERS = 256;   // push tallies are spread over this many words
+
 struct StepCtl {
-  int32_t *count;          // device: live particle slots in use
-  unsigned long long *pushes;
+  int32_t *count;                 // device: live particle slots in use
+  unsigned long long *pushes;     // N_PUSH_COUNTERS partial push counts
 };
 
 template <typename T>
@@ -140,6 +142,9 @@ void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
 template <typename T>
 void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                         StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s);
+template <typename T>
+void launch_push_deposit_tiled(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, int n_slots,
+                               int push, hipStream_t s);
 template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                     StepCtl ctl, int n_slots, hipStream_t s);

@@ -119,30 +119,72 @@ __device__ __forceinline__ bool move(const Grid<T> &g, int (&id)[3], T (&f)[3], 
   return inside;
 }
 
-// Esirkepov deposit of charge qw moving (i0,f0) -> (i1,f1); vz used in 2D only
-template <typename T, int DIM, int ORDER>
-__device__ __forceinline__ void deposit(const Grid<T> &g, const Fields<T> &F, const int (&i0)[3],
-                                        const T (&f0)[3], const int (&i1)[3], const T (&f1)[3],
-                                        T vz, T qw) {
+// Where deposited current goes: straight to the global J arrays (hardware float
+// atomics at L2), or to a workgroup's LDS copy of a box of nodes that is flushed to
+// global memory once at the end.
+template <typename T>
+struct GlobalSink {
+  T *J[3];
+  long q0, sy, sz;
+  __device__ __forceinline__ void origin(const Grid<T> &g, const int (&ws)[3]) {
+    q0 = g.at(ws[0], ws[1], ws[2]);
+    sy = g.sy;
+    sz = g.sz;
+  }
+  __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) {
+    atomic_add(&J[comp][q0 + a + b * sy + c * sz], v);
+  }
+};
+
+// The LDS box is replicated: lane L adds into copy L mod R, so lanes of a wave that
+// hit the same node (dense beams: whole waves share a cell) meet in R different words
+// and banks (the copy stride is odd).  The flush sums the copies.
+template <typename T>
+struct LdsSink {
+  T *lds;
+  int lo[3];
+  int e0, e01, total;
+  int q0;
+  __device__ __forceinline__ void origin(const Grid<T> &, const int (&ws)[3]) {
+    q0 = (ws[0] - lo[0]) + (ws[1] - lo[1]) * e0 + (ws[2] - lo[2]) * e01;
+  }
+  __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) {
+    atomicAdd(&lds[comp * total + q0 + a + b * e0 + c * e01], v);
+  }
+};
+
+// the (ORDER+2)-node window holding both shapes of a move, per axis: S0, S1 and start
+template <typename T, int ORDER>
+__device__ __forceinline__ int move_window(int i0, T f0, int i1, T f1, T (&S0)[ORDER + 2], T (&S1)[ORDER + 2]) {
+  T w0[ORDER + 1], w1[ORDER + 1];
+  const int s0 = i0 + shape_weights<ORDER>(f0, w0);
+  const int s1 = i1 + shape_weights<ORDER>(f1, w1);
+  const int st = s0 < s1 ? s0 : s1;
+  const bool sh0 = s0 != st, sh1 = s1 != st;     // shape shifted one node up in the window
+#pragma unroll
+  for (int k = 0; k < ORDER + 2; ++k) {
+    const T a0 = k <= ORDER ? w0[k <= ORDER ? k : 0] : T(0);
+    const T b0 = k >= 1 ? w0[k >= 1 ? k - 1 : 0] : T(0);
+    const T a1 = k <= ORDER ? w1[k <= ORDER ? k : 0] : T(0);
+    const T b1 = k >= 1 ? w1[k >= 1 ? k - 1 : 0] : T(0);
+    S0[k] = sh0 ? b0 : a0;
+    S1[k] = sh1 ? b1 : a1;
+  }
+  return st;
+}
+
+// Esirkepov deposit of charge qw moving (i0,f0) -> (i1,f1) into `sink`; vz is used in
+// 2D only (current along the invariant axis)
+template <typename T, int DIM, int ORDER, class Sink>
+__device__ __forceinline__ void deposit(const Grid<T> &g, Sink &sink, const int (&i0)[3], const T (&f0)[3],
+                                        const int (&i1)[3], const T (&f1)[3], T vz, T qw) {
   constexpr int W = ORDER + 2;
   T S0[3][W], S1[3][W];
   int ws[3] = {0, 0, 0};
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    T w0[ORDER + 1], w1[ORDER + 1];
-    const int s0 = i0[d] + shape_weights<ORDER>(f0[d], w0);
-    const int s1 = i1[d] + shape_weights<ORDER>(f1[d], w1);
-    const int st = s0 < s1 ? s0 : s1;
-    ws[d] = st;
-    const bool o0 = s0 != st, o1 = s1 != st;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      S0[d][k] = o0 ? (k >= 1 ? w0[k - 1 < ORDER ? k - 1 : ORDER] : T(0)) : (k <= ORDER ? w0[k <= ORDER ? k : ORDER] : T(0));
-      S1[d][k] = o1 ? (k >= 1 ? w1[k - 1 < ORDER ? k - 1 : ORDER] : T(0)) : (k <= ORDER ? w1[k <= ORDER ? k : ORDER] : T(0));
-    }
-  }
+  for (int d = 0; d < DIM; ++d) ws[d] = move_window<T, ORDER>(i0[d], f0[d], i1[d], f1[d], S0[d], S1[d]);
+  sink.origin(g, ws);
   if constexpr (DIM == 2) {
-    const long q0 = g.at(ws[0], ws[1], 0);
     const T cx = qw * g.inv_dx[1] / g.dt;
     const T cy = qw * g.inv_dx[0] / g.dt;
     const T cz = qw * vz * g.inv_dx[0] * g.inv_dx[1];
@@ -153,7 +195,7 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, const Fields<T> &F, co
 #pragma unroll
       for (int a = 0; a < W - 1; ++a) {
         acc -= cx * T(0.5) * (S1[0][a] - S0[0][a]) * sy;
-        if (acc != T(0)) atomic_add(&F.J[0][q0 + b * g.sy + a], acc);
+        if (acc != T(0)) sink.add(0, a, b, 0, acc);
       }
     }
 #pragma unroll
@@ -163,7 +205,7 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, const Fields<T> &F, co
 #pragma unroll
       for (int b = 0; b < W - 1; ++b) {
         acc -= cy * T(0.5) * (S1[1][b] - S0[1][b]) * sx;
-        if (acc != T(0)) atomic_add(&F.J[1][q0 + b * g.sy + a], acc);
+        if (acc != T(0)) sink.add(1, a, b, 0, acc);
       }
     }
     if (cz != T(0)) {
@@ -173,12 +215,10 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, const Fields<T> &F, co
         for (int a = 0; a < W; ++a) {
           const T wz = (S0[0][a] * S0[1][b] + S1[0][a] * S1[1][b]) * T(1.0 / 3.0) +
                        (S1[0][a] * S0[1][b] + S0[0][a] * S1[1][b]) * T(1.0 / 6.0);
-          if (wz != T(0)) atomic_add(&F.J[2][q0 + b * g.sy + a], cz * wz);
+          if (wz != T(0)) sink.add(2, a, b, 0, cz * wz);
         }
     }
   } else {
-    const long q0 = g.at(ws[0], ws[1], ws[2]);
-    const long st[3] = {1L, g.sy, g.sz};
 #pragma unroll
     for (int A = 0; A < 3; ++A) {
       const int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
@@ -194,17 +234,25 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, const Fields<T> &F, co
 #pragma unroll
           for (int a = 0; a < W - 1; ++a) {
             acc -= coef * (S1[A][a] - S0[A][a]) * avg;
-            if (acc != T(0)) atomic_add(&F.J[A][q0 + a * st[A] + b * st[Bx] + c * st[Cx]], acc);
+            if (acc != T(0)) {
+              int ii[3];
+              ii[A] = a; ii[Bx] = b; ii[Cx] = c;
+              sink.add(A, ii[0], ii[1], ii[2], acc);
+            }
           }
         }
     }
   }
 }
 
+// Push tally of a wavefront, added to one of N_PUSH_COUNTERS words chosen by the
+// wavefront (a single shared counter would serialise every wavefront of the grid).
 __device__ __forceinline__ void count_pushes(unsigned long long *pushes, bool active) {
   const unsigned long long m = __ballot(active);
-  if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1))
-    atomicAdd(pushes, (unsigned long long)__popcll(m));
+  if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1)) {
+    const unsigned slot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % N_PUSH_COUNTERS;
+    atomicAdd(&pushes[slot], (unsigned long long)__popcll(m));
+  }
 }
 
 // fused (fused = true) or first half (fused = false) of the particle step
@@ -235,7 +283,8 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
 #pragma unroll
       for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
       if (fused) {
-        deposit<T, DIM, ORDER>(g, F, id0, f0, id, f, u[2] * ig, g.charge * P.w[p]);
+        GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+        deposit<T, DIM, ORDER>(g, sink, id0, f0, id, f, u[2] * ig, g.charge * P.w[p]);
         P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
       } else {
         old.cell[p] = c;
@@ -246,6 +295,131 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
     }
   }
   count_pushes(ctl.pushes, active);
+}
+
+// Tiled form of the fused step for cell-sorted particles.  A workgroup takes a
+// contiguous chunk of TPB*PPT particles; their old cells bound the nodes the chunk can
+// deposit to (the move window spans [i0 + WLO, i0 + WHI] per axis).  If that box fits
+// in LDS the chunk accumulates its current there with LDS atomics and then adds every
+// non-zero LDS entry to global J once; otherwise it falls back to global atomics.
+constexpr int TPB = 256;
+template <typename T> struct TileCfg;
+template <> struct TileCfg<float> { static constexpr int NODES = 2048; };
+template <> struct TileCfg<double> { static constexpr int NODES = 2048; };
+
+template <typename T, int DIM, int ORDER, int PPT>
+__global__ void __launch_bounds__(TPB) k_push_deposit_tiled(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl,
+                                                            int n_slots, int push) {
+  constexpr int WLO = ORDER == 1 ? -1 : -2;
+  constexpr int WHI = ORDER == 1 ? 2 : 3;
+  constexpr int NODES = TileCfg<T>::NODES;
+  __shared__ T lds[3 * NODES];
+  __shared__ int sbox[6];
+  __shared__ unsigned int n_pushed;
+  const int tid = threadIdx.x;
+  if (tid == 0) n_pushed = 0u;
+  const int count = min(*ctl.count, n_slots);
+  const int base = blockIdx.x * (TPB * PPT);
+  if (tid < 3) { sbox[tid] = 0x7FFFFFFF; sbox[3 + tid] = -0x7FFFFFFF; }
+  __syncthreads();
+  // bounding box of the chunk's old cells
+  int mn[3] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF}, mx[3] = {-0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF};
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int p = base + k * TPB + tid;
+    if (p < count) {
+      const uint32_t c = P.cell[p];
+      if (c != DEAD) {
+        int id[3];
+        unpack_cell(DIM, c, id[0], id[1], id[2]);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) { mn[d] = min(mn[d], id[d]); mx[d] = max(mx[d], id[d]); }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    if (mn[d] <= mx[d]) { atomicMin(&sbox[d], mn[d]); atomicMax(&sbox[3 + d], mx[d]); }
+  }
+  __syncthreads();
+  LdsSink<T> lsink;
+  lsink.lds = lds;
+  int ext[3] = {1, 1, 1};
+  bool any = sbox[0] <= sbox[3];
+  int total = 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < DIM) {
+      lsink.lo[d] = sbox[d] + WLO;
+      ext[d] = any ? sbox[3 + d] - sbox[d] + (WHI - WLO) + 1 : 1;
+    } else {
+      lsink.lo[d] = 0;
+    }
+    total *= ext[d];
+  }
+  // replicas of the box that fit: R in {1, 2, 4, 8, 16}, odd stride between copies
+  const int stride = (3 * total) | 1;
+  const bool use_lds = any && stride <= 3 * NODES;
+  int R = 1;
+  while (R < 16 && 2 * R * stride <= 3 * NODES) R *= 2;
+  lsink.e0 = ext[0];
+  lsink.e01 = ext[0] * ext[1];
+  lsink.total = total;
+  if (use_lds) {
+    for (int e = tid; e < R * stride; e += TPB) lds[e] = T(0);
+  }
+  lsink.lds = lds + (tid % R) * stride;
+  __syncthreads();
+  GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+#pragma unroll 1
+  for (int k = 0; k < PPT; ++k) {
+    const int p = base + k * TPB + tid;
+    bool active = false;
+    if (p < count) {
+      const uint32_t c = P.cell[p];
+      if (c != DEAD) {
+        active = true;
+        int id[3];
+        unpack_cell(DIM, c, id[0], id[1], id[2]);
+        T f[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
+        T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+        if (push) {
+          T EB[6];
+          gather<T, DIM, ORDER>(g, F, id, f, EB);
+          boris(g.qdt_2m, EB, u);
+        }
+        const int id0[3] = {id[0], id[1], id[2]};
+        const T f0[3] = {f[0], f[1], f[2]};
+        T ig;
+        const bool inside = move<T, DIM>(g, id, f, u, ig);
+        P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
+        const T qw = g.charge * P.w[p];
+        if (use_lds) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
+        else deposit<T, DIM, ORDER>(g, gsink, id0, f0, id, f, u[2] * ig, qw);
+        P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
+      }
+    }
+    const unsigned long long m = __ballot(active);
+    if ((tid & 63) == 0 && m) atomicAdd(&n_pushed, (unsigned int)__popcll(m));
+  }
+  __syncthreads();
+  if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
+  if (use_lds) {
+    for (int e = tid; e < 3 * total; e += TPB) {
+      T v = lds[e];
+      for (int r = 1; r < R; ++r) v += lds[r * stride + e];
+      if (v == T(0)) continue;
+      const int comp = e / total;
+      int r = e - comp * total;
+      const int i = r % ext[0];
+      r /= ext[0];
+      const int j = r % ext[1];
+      const int kk = r / ext[1];
+      atomic_add(&F.J[comp][g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk)], v);
+    }
+  }
 }
 
 // second half of the unfused particle step: deposit from the saved x^n to x^{n+1}
@@ -263,7 +437,8 @@ __global__ void __launch_bounds__(256) k_deposit(Grid<T> g, Fields<T> F, Parts<T
   const T f0[3] = {old.f[0][p], old.f[1][p], DIM == 3 ? old.f[2][p] : T(0)};
   const T ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
   const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
-  deposit<T, DIM, ORDER>(g, F, i0, f0, i1, f1, uz * ig, g.charge * P.w[p]);
+  GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+  deposit<T, DIM, ORDER>(g, sink, i0, f0, i1, f1, uz * ig, g.charge * P.w[p]);
   bool inside = true;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) inside = inside && i1[d] >= 0 && i1[d] < g.M[d];
@@ -284,6 +459,23 @@ void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P,
   dim3 blk(256), grd((n_slots + 255) / 256);
   if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
   else { PMLPIC_DISPATCH_ORDER(3, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
+}
+
+constexpr int PPT_DEFAULT = 4;
+
+template <typename T>
+void launch_push_deposit_tiled(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, int n_slots,
+                               int push, hipStream_t s) {
+  if (n_slots <= 0) return;
+  dim3 blk(TPB), grd((n_slots + TPB * PPT_DEFAULT - 1) / (TPB * PPT_DEFAULT));
+#define PMLPIC_TILED(DIMV, ORD) \
+  hipLaunchKernelGGL((k_push_deposit_tiled<T, DIMV, ORD, PPT_DEFAULT>), grd, blk, 0, s, g, F, P, ctl, n_slots, push)
+  if (g.dim == 2) {
+    if (g.order == 1) PMLPIC_TILED(2, 1); else if (g.order == 2) PMLPIC_TILED(2, 2); else PMLPIC_TILED(2, 3);
+  } else {
+    if (g.order == 1) PMLPIC_TILED(3, 1); else if (g.order == 2) PMLPIC_TILED(3, 2); else PMLPIC_TILED(3, 3);
+  }
+#undef PMLPIC_TILED
 }
 
 template <typename T>
@@ -309,16 +501,87 @@ __device__ __forceinline__ uint32_t cell_key(int dim, const SortWork &sw, int i,
   return tile * (uint32_t)(sw.tile[0] * sw.tile[1] * sw.tile[2]) + local;
 }
 
+// Runs of equal keys inside a wavefront (particles are nearly sorted from the previous
+// sort): the first lane of my run and the first lane after it.
+__device__ __forceinline__ void key_run(uint32_t key, int lane, int &first, int &next) {
+  const uint32_t prev = __shfl_up(key, 1);
+  const bool start = lane == 0 || prev != key;
+  const unsigned long long starts = __ballot(start);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  first = 63 - __clzll((long long)(starts & upto));
+  const unsigned long long after = starts & ~upto;
+  next = after ? (__ffsll((long long)after) - 1) : 64;
+}
+
+// Histogram of the sort keys with the rank of every particle among equal keys.
+// A workgroup takes a chunk of HIST_TPB*HIST_PPT consecutive particles; runs of equal
+// keys in a wavefront take one counter update; if the chunk's key range fits, the
+// counters live in LDS and each distinct key costs one global atomic per chunk.
+constexpr int HIST_TPB = 256;
+constexpr int HIST_PPT = 4;
+constexpr int HIST_LDS = 4096;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_sort_hist(int dim, Parts<T> P, SortWork sw, StepCtl ctl, int n_slots) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_slots || p >= *ctl.count) return;
-  const uint32_t c = P.cell[p];
-  if (c == DEAD) return;
-  int i, j, k;
-  unpack_cell(dim, c, i, j, k);
-  const uint32_t key = cell_key(dim, sw, i, j, k);
-  sw.rank[p] = atomicAdd(&sw.counts[key], 1u);
+__global__ void __launch_bounds__(HIST_TPB) k_sort_hist(int dim, Parts<T> P, SortWork sw, StepCtl ctl, int n_slots) {
+  __shared__ uint32_t cnt[HIST_LDS];
+  __shared__ uint32_t kmin_s, kmax_s;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int count = min(*ctl.count, n_slots);
+  const int base = blockIdx.x * (HIST_TPB * HIST_PPT);
+  uint32_t key[HIST_PPT];
+  if (tid == 0) { kmin_s = 0xFFFFFFFFu; kmax_s = 0u; }
+  __syncthreads();
+  uint32_t lmin = 0xFFFFFFFFu, lmax = 0u;
+#pragma unroll
+  for (int k = 0; k < HIST_PPT; ++k) {
+    const int p = base + k * HIST_TPB + tid;
+    key[k] = 0xFFFFFFFFu;
+    if (p < count) {
+      const uint32_t c = P.cell[p];
+      if (c != DEAD) {
+        int i, j, kk;
+        unpack_cell(dim, c, i, j, kk);
+        key[k] = cell_key(dim, sw, i, j, kk);
+        lmin = min(lmin, key[k]);
+        lmax = max(lmax, key[k]);
+      }
+    }
+  }
+  if (lmin <= lmax) { atomicMin(&kmin_s, lmin); atomicMax(&kmax_s, lmax); }
+  __syncthreads();
+  const uint32_t kmin = kmin_s, kmax = kmax_s;
+  const bool any = kmin <= kmax;
+  const bool local = any && (kmax - kmin) < (uint32_t)HIST_LDS;
+  if (local) {
+    for (uint32_t e = tid; e <= kmax - kmin; e += HIST_TPB) cnt[e] = 0u;
+  }
+  __syncthreads();
+  uint32_t r[HIST_PPT];
+#pragma unroll
+  for (int k = 0; k < HIST_PPT; ++k) {
+    int first, next;
+    key_run(key[k], lane, first, next);
+    uint32_t b = 0;
+    if (lane == first && key[k] != 0xFFFFFFFFu) {
+      const uint32_t n = (uint32_t)(next - lane);
+      b = local ? atomicAdd(&cnt[key[k] - kmin], n) : atomicAdd(&sw.counts[key[k]], n);
+    }
+    b = __shfl(b, first);
+    r[k] = b + (uint32_t)(lane - first);
+  }
+  if (local) {
+    __syncthreads();
+    for (uint32_t e = tid; e <= kmax - kmin; e += HIST_TPB) {
+      const uint32_t c = cnt[e];
+      if (c) cnt[e] = atomicAdd(&sw.counts[kmin + e], c);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < HIST_PPT; ++k) {
+    const int p = base + k * HIST_TPB + tid;
+    if (key[k] != 0xFFFFFFFFu) sw.rank[p] = local ? cnt[key[k] - kmin] + r[k] : r[k];
+  }
 }
 
 constexpr int SCAN_BLOCK = 1024;
@@ -416,7 +679,8 @@ void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, Sor
   const int nb = (sw.nkeys + SCAN_TILE - 1) / SCAN_TILE;
   hipMemsetAsync(sw.counts, 0, sizeof(uint32_t) * (size_t)sw.nkeys, s);
   dim3 blk(256), grd((n_slots + 255) / 256);
-  hipLaunchKernelGGL((k_sort_hist<T>), grd, blk, 0, s, g.dim, src, sw, ctl, n_slots);
+  const int hist_blocks = (n_slots + HIST_TPB * HIST_PPT - 1) / (HIST_TPB * HIST_PPT);
+  hipLaunchKernelGGL((k_sort_hist<T>), dim3(hist_blocks), dim3(HIST_TPB), 0, s, g.dim, src, sw, ctl, n_slots);
   hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, sw.counts, sw.nkeys, sw.blocksums);
   // the new count goes to a scratch slot first: the scatter still needs the old one
   int32_t *new_count = (int32_t *)(sw.blocksums + nb);
@@ -430,6 +694,10 @@ template void launch_gather_push<float>(const Grid<float> &, const Fields<float>
                                         Parts<float>, StepCtl, int, int, bool, hipStream_t);
 template void launch_gather_push<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
                                          Parts<double>, StepCtl, int, int, bool, hipStream_t);
+template void launch_push_deposit_tiled<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
+                                               StepCtl, int, int, hipStream_t);
+template void launch_push_deposit_tiled<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
+                                                StepCtl, int, int, hipStream_t);
 template void launch_deposit<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
                                     Parts<float>, StepCtl, int, hipStream_t);
 template void launch_deposit<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
