@@ -56,7 +56,9 @@ enum { PML_ALPHA_ZERO = 0, PML_ALPHA_ONE = 1, PML_ALPHA_DAMPED = 2 };
 enum {
     PML_PIC_FLAG_UNFUSED = 1,      /* gather_push and deposit_current as separate launches */
     PML_PIC_FLAG_NO_SORT = 2,      /* never sort; deposit with global atomics only */
-    PML_PIC_FLAG_SEPARATE_DAMP = 4 /* damp_pml_current as its own pass over the PML */
+    PML_PIC_FLAG_SEPARATE_DAMP = 4,/* damp_pml_current as its own pass over the PML */
+    PML_PIC_FLAG_KEEP_CURRENT = 8  /* keep J after the step (for pml_pic_get_current); by
+                                      default the E update consumes J and zeroes it */
 };
 
 typedef struct {
@@ -152,7 +154,8 @@ int pml_pic_get_fields(pml_pic_handle *h, double *host, int64_t count);
 int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count);
 
 /* The current J_x J_y J_z (3 x n_samples doubles) deposited and damped by the last
- * step, at E's sample positions.  Synchronises. */
+ * step, at E's sample positions; needs PML_PIC_FLAG_KEEP_CURRENT (without it the
+ * arrays are zero after every step).  Synchronises. */
 int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count);
 
 /* Static partner charge density at the nodes (n_samples doubles). */

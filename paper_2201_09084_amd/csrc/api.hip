@@ -514,6 +514,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const bool use_sort = !(fl & PML_PIC_FLAG_NO_SORT);
   const bool fused = !(fl & PML_PIC_FLAG_UNFUSED);
   const bool sep_damp = (fl & PML_PIC_FLAG_SEPARATE_DAMP) != 0;
+  const bool keep_j = (fl & PML_PIC_FLAG_KEEP_CURRENT) != 0;
   const int ns = (int)h->n_slots;
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
@@ -526,9 +527,11 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       h->since_sort = 0;
       h->sort_pending = false;
     }
-    pt.begin(s);
-    for (int a = 0; a < 3; ++a) HIPCHK(h, hipMemsetAsync(F.J[a], 0, jbytes, s));
-    pt.end(s, PML_PIC_PHASE_CLEAR_J);
+    if (keep_j) {   // J survives the step for inspection; clear it before depositing
+      pt.begin(s);
+      for (int a = 0; a < 3; ++a) HIPCHK(h, hipMemsetAsync(F.J[a], 0, jbytes, s));
+      pt.end(s, PML_PIC_PHASE_CLEAR_J);
+    }
     const Parts<T> P = h->parts<T>(h->cur);
     pt.begin(s);
     if (fused && use_sort) launch_push_deposit_tiled<T>(g, F, P, ctl, ns, h->p.push, s);
@@ -548,7 +551,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     launch_update_B<T>(g, F, true, s);
     pt.end(s, PML_PIC_PHASE_UPDATE_B);
     pt.begin(s);
-    launch_update_E<T>(g, F, !sep_damp, h->p.alpha_mode, s);
+    launch_update_E<T>(g, F, !sep_damp, h->p.alpha_mode, !keep_j, s);
     pt.end(s, PML_PIC_PHASE_UPDATE_E);
     pt.begin(s);
     launch_update_B<T>(g, F, true, s);

@@ -135,7 +135,7 @@ struct StepCtl {
 template <typename T>
 void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool half, hipStream_t s);
 template <typename T>
-void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode,
+void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode, bool consume,
                      hipStream_t s);
 template <typename T>
 void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);

@@ -68,7 +68,7 @@ __device__ __forceinline__ T alpha_at(const Grid<T> &g, const int (&id)[3]) {
 
 template <typename T, int DIM, int A>
 __device__ __forceinline__ void update_E_comp(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
-                                              long q, bool fuse_alpha) {
+                                              long q, bool fuse_alpha, bool consume) {
   constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
   if (A < DIM && id[A] > g.M[A] - 1) return;
   if (Bx < DIM && (id[Bx] < 1 || id[Bx] > g.M[Bx] - 1)) return;   // PEC: tangential E = 0
@@ -78,6 +78,7 @@ __device__ __forceinline__ void update_E_comp(const Grid<T> &g, const Fields<T> 
   if (Bx < DIM) Db = F.B[Cx][q] - F.B[Cx][q - stride_of<T, DIM>(g, Bx)];
   if (Cx < DIM) Dc = F.B[Bx][q] - F.B[Bx][q - stride_of<T, DIM>(g, Cx)];
   T j = F.J[A][q];
+  if (consume && j != T(0)) F.J[A][q] = T(0);   // leaves J zero for the next deposit
   if (fuse_alpha) j *= alpha_at<T, DIM, A>(g, id);
   if constexpr (DIM == 2 && (Bx == 2 || Cx == 2)) {
     constexpr int P = (Bx == 2) ? Cx : Bx;
@@ -116,16 +117,16 @@ __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_update_E(Grid<T> g, Fields<T> F, bool fuse_alpha) {
+__global__ void __launch_bounds__(256) k_update_E(Grid<T> g, Fields<T> F, bool fuse_alpha, bool consume) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = (DIM == 3) ? (int)blockIdx.z : 0;
   if (i > g.M[0] || j > g.M[1]) return;
   const int id[3] = {i, j, k};
   const long q = g.at(i, j, k);
-  update_E_comp<T, DIM, 0>(g, F, id, q, fuse_alpha);
-  update_E_comp<T, DIM, 1>(g, F, id, q, fuse_alpha);
-  update_E_comp<T, DIM, 2>(g, F, id, q, fuse_alpha);
+  update_E_comp<T, DIM, 0>(g, F, id, q, fuse_alpha, consume);
+  update_E_comp<T, DIM, 1>(g, F, id, q, fuse_alpha, consume);
+  update_E_comp<T, DIM, 2>(g, F, id, q, fuse_alpha, consume);
 }
 
 // damp_pml_current: J_A <- alpha J_A at every sample where alpha != 1 (the PML).
@@ -160,11 +161,12 @@ void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool /*half*/, hipStr
 }
 
 template <typename T>
-void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode, hipStream_t s) {
+void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode, bool consume,
+                     hipStream_t s) {
   dim3 blk, grd = node_grid(g, blk);
   const bool fa = fuse_alpha && alpha_mode != 1;
-  if (g.dim == 2) hipLaunchKernelGGL((k_update_E<T, 2>), grd, blk, 0, s, g, F, fa);
-  else hipLaunchKernelGGL((k_update_E<T, 3>), grd, blk, 0, s, g, F, fa);
+  if (g.dim == 2) hipLaunchKernelGGL((k_update_E<T, 2>), grd, blk, 0, s, g, F, fa, consume);
+  else hipLaunchKernelGGL((k_update_E<T, 3>), grd, blk, 0, s, g, F, fa, consume);
 }
 
 template <typename T>
@@ -176,8 +178,8 @@ void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s) {
 
 template void launch_update_B<float>(const Grid<float> &, const Fields<float> &, bool, hipStream_t);
 template void launch_update_B<double>(const Grid<double> &, const Fields<double> &, bool, hipStream_t);
-template void launch_update_E<float>(const Grid<float> &, const Fields<float> &, bool, int, hipStream_t);
-template void launch_update_E<double>(const Grid<double> &, const Fields<double> &, bool, int, hipStream_t);
+template void launch_update_E<float>(const Grid<float> &, const Fields<float> &, bool, int, bool, hipStream_t);
+template void launch_update_E<double>(const Grid<double> &, const Fields<double> &, bool, int, bool, hipStream_t);
 template void launch_damp_current<float>(const Grid<float> &, const Fields<float> &, hipStream_t);
 template void launch_damp_current<double>(const Grid<double> &, const Fields<double> &, hipStream_t);
 

@@ -303,16 +303,18 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
 // in LDS the chunk accumulates its current there with LDS atomics and then adds every
 // non-zero LDS entry to global J once; otherwise it falls back to global atomics.
 constexpr int TPB = 256;
-template <typename T> struct TileCfg;
-template <> struct TileCfg<float> { static constexpr int NODES = 2048; };
-template <> struct TileCfg<double> { static constexpr int NODES = 2048; };
+// LDS nodes per current component (2D: ~24 KB of FP32; 3D holds a box around two 8^3
+// tiles at 1 particle per cell, 19 x 11 x 11 nodes) and particles per thread
+template <int DIM> struct TileCfg;
+template <> struct TileCfg<2> { static constexpr int NODES = 2048; static constexpr int PPT = 4; };
+template <> struct TileCfg<3> { static constexpr int NODES = 2560; static constexpr int PPT = 2; };
 
 template <typename T, int DIM, int ORDER, int PPT>
 __global__ void __launch_bounds__(TPB) k_push_deposit_tiled(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl,
                                                             int n_slots, int push) {
   constexpr int WLO = ORDER == 1 ? -1 : -2;
   constexpr int WHI = ORDER == 1 ? 2 : 3;
-  constexpr int NODES = TileCfg<T>::NODES;
+  constexpr int NODES = TileCfg<DIM>::NODES;
   __shared__ T lds[3 * NODES];
   __shared__ int sbox[6];
   __shared__ unsigned int n_pushed;
@@ -461,15 +463,14 @@ void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P,
   else { PMLPIC_DISPATCH_ORDER(3, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
 }
 
-constexpr int PPT_DEFAULT = 4;
-
 template <typename T>
 void launch_push_deposit_tiled(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, int n_slots,
                                int push, hipStream_t s) {
   if (n_slots <= 0) return;
-  dim3 blk(TPB), grd((n_slots + TPB * PPT_DEFAULT - 1) / (TPB * PPT_DEFAULT));
+  const int ppt = g.dim == 2 ? TileCfg<2>::PPT : TileCfg<3>::PPT;
+  dim3 blk(TPB), grd((n_slots + TPB * ppt - 1) / (TPB * ppt));
 #define PMLPIC_TILED(DIMV, ORD) \
-  hipLaunchKernelGGL((k_push_deposit_tiled<T, DIMV, ORD, PPT_DEFAULT>), grd, blk, 0, s, g, F, P, ctl, n_slots, push)
+  hipLaunchKernelGGL((k_push_deposit_tiled<T, DIMV, ORD, TileCfg<DIMV>::PPT>), grd, blk, 0, s, g, F, P, ctl, n_slots, push)
   if (g.dim == 2) {
     if (g.order == 1) PMLPIC_TILED(2, 1); else if (g.order == 2) PMLPIC_TILED(2, 2); else PMLPIC_TILED(2, 3);
   } else {

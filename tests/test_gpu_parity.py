@@ -115,7 +115,7 @@ def test_random_state_steps_fp64(dim, order):
     particles over box and PML; several steps, fields, current and particles."""
     cfg, parts, fields = _random_case(dim, order, seed=100 + 10 * dim + order, n_particles=300)
     say("case", dim, order)
-    g, o = both(cfg, parts, fields)
+    g, o = both(cfg, parts, fields, flags=B.FLAG_KEEP_CURRENT)
     for k in range(3):
         g.step(1)
         o.step(1)
@@ -131,8 +131,8 @@ def test_random_state_steps_fp64(dim, order):
     compare_particles(g, o, 1e-9, 1e-9, "after 7 steps")
 
 
-@pytest.mark.parametrize("flags", [B.FLAG_UNFUSED, B.FLAG_NO_SORT, B.FLAG_SEPARATE_DAMP,
-                                   B.FLAG_UNFUSED | B.FLAG_SEPARATE_DAMP | B.FLAG_NO_SORT])
+@pytest.mark.parametrize("flags", [B.FLAG_UNFUSED, B.FLAG_NO_SORT, B.FLAG_SEPARATE_DAMP, B.FLAG_KEEP_CURRENT,
+                                   B.FLAG_UNFUSED | B.FLAG_SEPARATE_DAMP | B.FLAG_NO_SORT | B.FLAG_KEEP_CURRENT])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_kernel_variants_match_oracle(flags, dim):
     """Unfused gather_push + deposit_current, no sorting, separate damp pass."""
