@@ -69,6 +69,63 @@ def run_gpu(args, cfg, parts):
     return sim, elapsed, pushes, phases, d0, d1
 
 
+def run_batch(args):
+    """Workload 3: 256 independent 2D single-particle exit runs (N ~ U{64..512}, PML ~
+    U{8..32}, angle ~ U[0, 60] deg, ln gamma ~ U[ln 1.1, ln 20]), FP32, stepped as one
+    batch whose step is a replayed HIP graph, launch shape from the autotuner."""
+    import torch
+    from paper_2201_09084_amd import autotune
+    from paper_2201_09084_amd import binding as B
+    from paper_2201_09084_amd import workloads as W
+    runs = W.batch_runs(256)
+    cfgs = [r.cfg for r in runs]
+    cells = sum(c.total_cells() for c in cfgs)
+    print("bench: batch of %d runs, %d cells in total, fp32; warmup %d, timed %d"
+          % (len(runs), cells, args.warmup, args.steps), file=sys.stderr, flush=True)
+    bx, grid = autotune.tune_batch(cfgs, cache_path=args.tune_cache)
+    b = B.PmlPicBatch(cfgs, particles_per_run=1, use_graph=True)
+    b.set_launch(bx, grid)
+    for k, r in enumerate(runs):
+        b.runs[k].add_particles(r.particles.x, r.particles.u, r.particles.w)
+    if args.warmup:
+        b.step(args.warmup)
+    b.synchronize()
+    p0 = sum(r.diagnose()["n_pushes"] for r in b.runs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    b.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pushes = sum(r.diagnose()["n_pushes"] for r in b.runs) - p0
+    n_prof = max(10, min(50, args.steps // 10))
+    phases = b.step_profiled(n_prof)
+    dom = max(phases.items(), key=lambda kv: kv[1][0])
+    name, (ms_total, launches) = dom
+    avg_s = ms_total / 1e3 / launches
+    pml = sum(c.pml_cells() for c in cfgs)
+    per = {"update_yee_pml_B": cells * 9 * 4 + pml * 2 * 4, "update_yee_pml_E": cells * 12 * 4 + pml * 2 * 4}
+    roof = None
+    if name in per:
+        ach = per[name] / avg_s / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": int(per[name]),
+                "timing": "HIP events around each kernel in %d eager steps after the timed graph replays" % n_prof}
+    out = {
+        "metric": "PIC particle-pushes/s & Yee+PML cell-updates/s; FP32 vs FP64 at stated err",
+        "value": cells * args.steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch", "runs": len(runs), "cells": cells, "launch": [bx, grid],
+                   "graph": True},
+        "particle_pushes_per_s": pushes / elapsed,
+        "phases_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in phases.items()},
+        "roofline": roof, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(cfg, parts, n_steps):
     import oracle
     oracle.build.build(force=False)
@@ -83,9 +140,11 @@ def cpu_baseline(cfg, parts, n_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 2000 beam2d, 100 beam3d, 600 batch)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["beam2d", "beam3d"], default="beam2d")
+    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch"], default="beam2d")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,6 +170,10 @@ def main():
     from paper_2201_09084_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.steps is None:
+        args.steps = {"beam2d": 2000, "beam3d": 100, "batch": 600}[args.workload]
+    if args.workload == "batch":
+        return run_batch(args)
     if args.workload == "beam2d":
         cfg = W.beam2d_config(precision=args.precision)
         parts = W.beam2d_particles(cfg)

@@ -176,6 +176,47 @@ int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *
 int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X,
                           const double *u, const double *w);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent runs advanced together: each run has its own grid, PML, profile,
+ * alpha mode and particles (all runs share dim, shape_order and precision).  One
+ * step of every run is a fixed set of launches (particles, then B, E, B over a work
+ * list of (run, block) items walked by a persistent grid); with use_graph the step is
+ * captured once as a HIP graph and replayed.  Batched runs deposit with global atomics
+ * (no sorting), the form meant for few particles per run, as in single-particle exit
+ * studies (Sec. III). */
+typedef struct pml_pic_batch pml_pic_batch;
+
+/* Workspace bytes for n_runs runs with the given parameters (validated as for one run). */
+int pml_pic_batch_workspace_size(const pml_pic_params *runs, int32_t n_runs, size_t *bytes);
+
+/* Creates the batch in one caller-owned, 256-byte aligned device workspace.  stream
+ * must be a non-default hipStream_t when use_graph is 1 (graphs cannot be captured on
+ * the legacy default stream). */
+int pml_pic_batch_create(const pml_pic_params *runs, int32_t n_runs, void *device_workspace, size_t bytes,
+                         void *stream, int32_t use_graph, pml_pic_batch **out);
+
+/* Handle of run `run`, owned by the batch (valid until pml_pic_batch_destroy; never
+ * pass it to pml_pic_destroy).  Every single-run call works on it: add particles,
+ * diagnose, get/set fields; pml_pic_step on it advances that run alone. */
+pml_pic_handle *pml_pic_batch_run(pml_pic_batch *b, int32_t run);
+
+/* Launch shape of the batched field kernels: 256-thread blocks of block_x x
+ * (256/block_x) nodes (block_x in 32, 64, 128, 256) and grid_blocks persistent
+ * workgroups (0 = 8 per compute unit).  Drops the captured graph. */
+int pml_pic_batch_set_launch(pml_pic_batch *b, int32_t block_x, int32_t grid_blocks);
+
+/* Advances every run by n_steps, asynchronously on the batch's stream. */
+int pml_pic_batch_step(pml_pic_batch *b, int32_t n_steps);
+
+/* Same work launched eagerly (no graph) with HIP events around every kernel; adds
+ * milliseconds and launch counts per phase as pml_pic_step_profiled does
+ * (PUSH = particles of all runs, UPDATE_B = both B half steps, UPDATE_E).
+ * Synchronises the stream. */
+int pml_pic_batch_step_profiled(pml_pic_batch *b, int32_t n_steps, double *phase_ms, int64_t *phase_calls);
+
+const char *pml_pic_batch_last_error(const pml_pic_batch *b);
+void pml_pic_batch_destroy(pml_pic_batch *b);
+
 /* Message of the last failed call on h (or of the last failed create if h is NULL). */
 const char *pml_pic_last_error(const pml_pic_handle *h);
 

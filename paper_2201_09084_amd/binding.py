@@ -26,6 +26,9 @@ EXPORTED = [
     "pml_pic_get_current", "pml_pic_get_rho_static", "pml_pic_set_rho_static",
     "pml_pic_num_particles", "pml_pic_get_particles", "pml_pic_set_particles",
     "pml_pic_last_error", "pml_pic_destroy", "pml_pic_step_profiled",
+    "pml_pic_batch_workspace_size", "pml_pic_batch_create", "pml_pic_batch_run",
+    "pml_pic_batch_set_launch", "pml_pic_batch_step", "pml_pic_batch_last_error",
+    "pml_pic_batch_destroy", "pml_pic_batch_step_profiled",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "unused"]
@@ -86,6 +89,14 @@ def load_library():
             "pml_pic_set_particles": (C.c_int, [vp, i64, P(C.c_int64), dp, dp, dp]),
             "pml_pic_last_error": (C.c_char_p, [vp]),
             "pml_pic_destroy": (None, [vp]),
+            "pml_pic_batch_workspace_size": (C.c_int, [P(Params), i32, P(C.c_size_t)]),
+            "pml_pic_batch_create": (C.c_int, [P(Params), i32, vp, C.c_size_t, vp, i32, P(vp)]),
+            "pml_pic_batch_run": (vp, [vp, i32]),
+            "pml_pic_batch_set_launch": (C.c_int, [vp, i32, i32]),
+            "pml_pic_batch_step": (C.c_int, [vp, i32]),
+            "pml_pic_batch_step_profiled": (C.c_int, [vp, i32, dp, P(C.c_int64)]),
+            "pml_pic_batch_last_error": (C.c_char_p, [vp]),
+            "pml_pic_batch_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -143,13 +154,18 @@ def workspace_size(params: Params) -> int:
 class PmlPic:
     """One simulation on the current GPU (names follow the C ABI)."""
 
-    def __init__(self, cfg, max_particles=None, flags=0, stream=None):
+    def __init__(self, cfg, max_particles=None, flags=0, stream=None, _borrowed=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("PmlPic needs a ROCm GPU; there is no CPU fallback")
         L = load_library()
         self.cfg = cfg
         self.params = make_params(cfg, max_particles, flags)
+        if _borrowed is not None:        # a run owned by a PmlPicBatch
+            self._h, self._owned, self.stream = C.c_void_p(_borrowed), False, stream
+            self._init_shape()
+            return
+        self._owned = True
         nbytes = workspace_size(self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
@@ -161,6 +177,10 @@ class PmlPic:
         if rc != PML_PIC_OK:
             raise PmlPicError(rc, L.pml_pic_last_error(None).decode())
         self._h = h
+        self._init_shape()
+
+    def _init_shape(self):
+        L = load_library()
         nn = (C.c_int32 * 3)()
         ns = C.c_int64()
         self._check(L.pml_pic_grid_shape(self._h, nn, C.byref(ns)))
@@ -173,7 +193,8 @@ class PmlPic:
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().pml_pic_destroy(self._h)
+            if getattr(self, "_owned", True):
+                load_library().pml_pic_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -265,3 +286,87 @@ class PmlPic:
     def set_rho_static(self, r):
         r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
         self._check(load_library().pml_pic_set_rho_static(self._h, _dp(r), r.size))
+
+
+def batch_workspace_size(params_list) -> int:
+    arr = (Params * len(params_list))(*params_list)
+    n = C.c_size_t(0)
+    rc = load_library().pml_pic_batch_workspace_size(arr, len(params_list), C.byref(n))
+    if rc != PML_PIC_OK:
+        raise PmlPicError(rc, load_library().pml_pic_batch_last_error(None).decode())
+    return int(n.value)
+
+
+class PmlPicBatch:
+    """Many independent runs stepped together (pml_pic_batch_*).  ``runs[r]`` is a PmlPic
+    view of run r (owned by the batch).  Uses its own torch stream so that the step can
+    be captured as a HIP graph."""
+
+    def __init__(self, cfgs, particles_per_run=1, use_graph=True, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("PmlPicBatch needs a ROCm GPU; there is no CPU fallback")
+        L = load_library()
+        self.cfgs = list(cfgs)
+        caps = particles_per_run if isinstance(particles_per_run, (list, tuple)) else [particles_per_run] * len(cfgs)
+        self.params = [make_params(c, max_particles=m) for c, m in zip(self.cfgs, caps)]
+        arr = (Params * len(self.params))(*self.params)
+        nbytes = batch_workspace_size(self.params)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = C.c_void_p()
+        rc = L.pml_pic_batch_create(arr, len(self.params), C.c_void_p(aligned), C.c_size_t(nbytes),
+                                    C.c_void_p(self.stream.cuda_stream), int(bool(use_graph)), C.byref(h))
+        if rc != PML_PIC_OK:
+            raise PmlPicError(rc, L.pml_pic_batch_last_error(None).decode())
+        self._h = h
+        self.runs = [PmlPic(c, max_particles=m, stream=self.stream,
+                            _borrowed=L.pml_pic_batch_run(self._h, r))
+                     for r, (c, m) in enumerate(zip(self.cfgs, caps))]
+        self.launch = (64, 0)
+
+    def _check(self, rc):
+        if rc != PML_PIC_OK:
+            raise PmlPicError(rc, load_library().pml_pic_batch_last_error(self._h).decode())
+
+    def step(self, n: int = 1):
+        self._check(load_library().pml_pic_batch_step(self._h, int(n)))
+
+    def step_profiled(self, n: int = 1):
+        """Eager steps with HIP events around every kernel: {phase: (total ms, launches)}."""
+        ms = np.zeros(8)
+        calls = np.zeros(8, np.int64)
+        self._check(load_library().pml_pic_batch_step_profiled(self._h, int(n), _dp(ms), _lp(calls)))
+        return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(8) if calls[k] > 0}
+
+    def set_launch(self, block_x: int, grid_blocks: int = 0):
+        self._check(load_library().pml_pic_batch_set_launch(self._h, int(block_x), int(grid_blocks)))
+        self.launch = (block_x, grid_blocks)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def timed_steps(self, n: int) -> float:
+        """Seconds for n steps, from HIP events recorded on the batch's stream."""
+        import torch
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        self.step(n)
+        b.record(self.stream)
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for r in self.runs:
+                r._h = None
+            load_library().pml_pic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -636,6 +636,318 @@ int get_particles_t(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, dou
 
 }  // namespace
 
+static int create_handle(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream,
+                         pml_pic_handle **out, std::string *err) {
+  if (!out) return fail(err, PML_PIC_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(params, err);
+  if (rc) return rc;
+  Layout L;
+  make_layout(*params, L);
+  if (!device_workspace || bytes < L.total)
+    return fail(err, PML_PIC_E_WORKSPACE, "workspace smaller than pml_pic_workspace_size()");
+  if (((uintptr_t)device_workspace) % 256 != 0)
+    return fail(err, PML_PIC_E_WORKSPACE, "workspace must be 256-byte aligned");
+  pml_pic_handle *h = new pml_pic_handle();
+  h->p = *params;
+  h->L = L;
+  h->ws = (char *)device_workspace;
+  h->stream = (hipStream_t)stream;
+  h->sort_interval = params->sort_interval > 0 ? params->sort_interval : 8;
+  build_tables(h);
+  hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    *err = std::string("HIP error while clearing the workspace: ") + hipGetErrorString(e);
+    delete h;
+    return PML_PIC_E_HIP;
+  }
+  rc = params->precision == 64 ? upload_tables<double>(h) : upload_tables<float>(h);
+  if (rc) {
+    *err = h->err;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return PML_PIC_OK;
+}
+
+// ===================================================================== batches
+struct pml_pic_batch {
+  std::vector<pml_pic_handle *> runs;
+  std::vector<int64_t> slots_seen;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int dim = 2, order = 1, prec = 32;
+  size_t off_desc = 0, off_items = 0, max_items = 0;
+  int n_items = 0, bdx = 64, grid_blocks = 0;
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+const int BATCH_BDX[4] = {32, 64, 128, 256};
+
+size_t batch_items(const std::vector<Layout> &Ls, int dim, int bdx) {
+  const int bdy = 256 / bdx;
+  size_t n = 0;
+  for (const Layout &L : Ls)
+    n += (size_t)((L.M[0] + bdx) / bdx) * ((L.M[1] + bdy) / bdy) * (dim == 3 ? L.M[2] + 1 : 1);
+  return n;
+}
+
+int batch_layout(const pml_pic_params *runs, int32_t n, std::vector<Layout> &Ls, std::vector<size_t> &offs,
+                 size_t &off_desc, size_t &off_items, size_t &max_items, size_t &total, std::string *err) {
+  if (!runs || n < 1) return fail(err, PML_PIC_E_INVALID_ARG, "need at least one run");
+  Ls.assign(n, Layout());
+  for (int r = 0; r < n; ++r) {
+    const int rc = validate(&runs[r], err);
+    if (rc) {
+      if (err) *err = "run " + std::to_string(r) + ": " + *err;
+      return rc;
+    }
+    if (runs[r].dim != runs[0].dim || runs[r].shape_order != runs[0].shape_order ||
+        runs[r].precision != runs[0].precision)
+      return fail(err, PML_PIC_E_INVALID_ARG, "all runs of a batch need the same dim, shape_order and precision");
+    make_layout(runs[r], Ls[r]);
+  }
+  max_items = 0;
+  for (int k = 0; k < 4; ++k) max_items = std::max(max_items, batch_items(Ls, runs[0].dim, BATCH_BDX[k]));
+  const size_t dsz = runs[0].precision == 64 ? sizeof(RunDesc<double>) : sizeof(RunDesc<float>);
+  off_desc = 0;
+  off_items = align_up(dsz * n, 256);
+  size_t off = align_up(off_items + sizeof(int4) * max_items, 256);
+  offs.resize(n);
+  for (int r = 0; r < n; ++r) {
+    offs[r] = off;
+    off = align_up(off + Ls[r].total, 256);
+  }
+  total = off;
+  return PML_PIC_OK;
+}
+
+template <typename T>
+int batch_upload_descs(pml_pic_batch *b) {
+  std::vector<RunDesc<T>> d(b->runs.size());
+  for (size_t r = 0; r < b->runs.size(); ++r) {
+    pml_pic_handle *h = b->runs[r];
+    d[r].g = h->grid<T>();
+    d[r].F = h->fields<T>();
+    d[r].P = h->parts<T>(h->cur);
+    d[r].ctl = h->ctl();
+    d[r].n_slots = (int)h->n_slots;
+    d[r].push = h->p.push;
+    d[r].alpha_mode = h->p.alpha_mode;
+    d[r].pad = 0;
+    b->slots_seen[r] = h->n_slots;
+  }
+  HIPCHK(b, hipMemcpyAsync(b->ws + b->off_desc, d.data(), sizeof(RunDesc<T>) * d.size(), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return PML_PIC_OK;
+}
+
+int batch_build_items(pml_pic_batch *b, int bdx) {
+  const int bdy = 256 / bdx;
+  std::vector<int4> it;
+  it.reserve(b->max_items);
+  for (size_t r = 0; r < b->runs.size(); ++r) {
+    const Layout &L = b->runs[r]->L;
+    const int nbx = (L.M[0] + bdx) / bdx, nby = (L.M[1] + bdy) / bdy, nbz = b->dim == 3 ? L.M[2] + 1 : 1;
+    for (int bz = 0; bz < nbz; ++bz)
+      for (int by = 0; by < nby; ++by)
+        for (int bx = 0; bx < nbx; ++bx) it.push_back(make_int4((int)r, bx, by, bz));
+  }
+  if (it.size() > b->max_items) return fail(&b->err, PML_PIC_E_INVALID_ARG, "work list overflow");
+  HIPCHK(b, hipMemcpyAsync(b->ws + b->off_items, it.data(), sizeof(int4) * it.size(), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->n_items = (int)it.size();
+  b->bdx = bdx;
+  return PML_PIC_OK;
+}
+
+void batch_drop_graph(pml_pic_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// particles, B half step, E step, B half step (the order of the single-run step)
+template <typename T>
+void batch_launch(pml_pic_batch *b, PhaseTimer *pt = nullptr) {
+  static const int order_of_phases[4] = {0, 1, 2, 1};
+  static const int timer_phase[3] = {PML_PIC_PHASE_PUSH, PML_PIC_PHASE_UPDATE_B, PML_PIC_PHASE_UPDATE_E};
+  for (int k = 0; k < 4; ++k) {
+    const int ph = order_of_phases[k];
+    if (pt) pt->begin(b->stream);
+    launch_batch_phase<T>(ph, b->dim, b->order, (const RunDesc<T> *)(b->ws + b->off_desc), (int)b->runs.size(),
+                          (const int4 *)(b->ws + b->off_items), b->n_items, b->bdx, b->grid_blocks, b->stream);
+    if (pt) pt->end(b->stream, timer_phase[ph]);
+  }
+}
+
+template <typename T>
+int batch_step_t(pml_pic_batch *b, int n, PhaseTimer *pt = nullptr) {
+  bool changed = false;
+  for (size_t r = 0; r < b->runs.size(); ++r) changed = changed || b->runs[r]->n_slots != b->slots_seen[r];
+  if (changed) {
+    const int rc = batch_upload_descs<T>(b);
+    if (rc) return rc;
+  }
+  if (pt) {
+    for (int it = 0; it < n; ++it) batch_launch<T>(b, pt);
+    HIPCHK(b, hipGetLastError());
+  } else if (b->use_graph) {
+    if (!b->exec) {
+      HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      batch_launch<T>(b);
+      hipGraph_t g = nullptr;
+      HIPCHK(b, hipStreamEndCapture(b->stream, &g));
+      b->graph = g;
+      HIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    for (int it = 0; it < n; ++it) HIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+  } else {
+    for (int it = 0; it < n; ++it) batch_launch<T>(b);
+    HIPCHK(b, hipGetLastError());
+  }
+  for (pml_pic_handle *h : b->runs) h->step += n;
+  return PML_PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pml_pic_batch_workspace_size(const pml_pic_params *runs, int32_t n_runs, size_t *bytes) {
+  if (!bytes) return PML_PIC_E_INVALID_ARG;
+  std::vector<Layout> Ls;
+  std::vector<size_t> offs;
+  size_t od, oi, mi, total;
+  const int rc = batch_layout(runs, n_runs, Ls, offs, od, oi, mi, total, &g_create_error);
+  if (rc) return rc;
+  *bytes = total;
+  return PML_PIC_OK;
+}
+
+int pml_pic_batch_create(const pml_pic_params *runs, int32_t n_runs, void *device_workspace, size_t bytes,
+                         void *stream, int32_t use_graph, pml_pic_batch **out) {
+  if (!out) return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::vector<Layout> Ls;
+  std::vector<size_t> offs;
+  size_t od, oi, mi, total;
+  int rc = batch_layout(runs, n_runs, Ls, offs, od, oi, mi, total, &g_create_error);
+  if (rc) return rc;
+  if (!device_workspace || bytes < total || ((uintptr_t)device_workspace) % 256 != 0)
+    return fail(&g_create_error, PML_PIC_E_WORKSPACE, "batch workspace too small or misaligned");
+  if (use_graph && !stream)
+    return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "graphs need a non-default stream");
+  pml_pic_batch *b = new pml_pic_batch();
+  b->ws = (char *)device_workspace;
+  b->stream = (hipStream_t)stream;
+  b->dim = runs[0].dim;
+  b->order = runs[0].shape_order;
+  b->prec = runs[0].precision;
+  b->off_desc = od;
+  b->off_items = oi;
+  b->max_items = mi;
+  b->use_graph = use_graph != 0;
+  for (int r = 0; r < n_runs; ++r) {
+    pml_pic_params pr = runs[r];
+    pr.flags |= PML_PIC_FLAG_NO_SORT;     // batched particles deposit with global atomics
+    pr.flags &= ~(PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_SEPARATE_DAMP | PML_PIC_FLAG_KEEP_CURRENT);
+    pml_pic_handle *h = nullptr;
+    rc = create_handle(&pr, b->ws + offs[r], Ls[r].total, stream, &h, &g_create_error);
+    if (rc) {
+      for (pml_pic_handle *x : b->runs) delete x;
+      delete b;
+      return rc;
+    }
+    b->runs.push_back(h);
+  }
+  b->slots_seen.assign(n_runs, -1);
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) n_cu = prop.multiProcessorCount;
+  }
+  b->grid_blocks = 8 * n_cu;
+  rc = b->prec == 64 ? batch_upload_descs<double>(b) : batch_upload_descs<float>(b);
+  if (rc == PML_PIC_OK) rc = batch_build_items(b, 64);
+  if (rc) {
+    g_create_error = b->err;
+    for (pml_pic_handle *x : b->runs) delete x;
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return PML_PIC_OK;
+}
+
+pml_pic_handle *pml_pic_batch_run(pml_pic_batch *b, int32_t run) {
+  if (!b || run < 0 || run >= (int32_t)b->runs.size()) return nullptr;
+  return b->runs[run];
+}
+
+int pml_pic_batch_set_launch(pml_pic_batch *b, int32_t block_x, int32_t grid_blocks) {
+  if (!b) return PML_PIC_E_INVALID_ARG;
+  if (block_x != 32 && block_x != 64 && block_x != 128 && block_x != 256)
+    return fail(&b->err, PML_PIC_E_INVALID_ARG, "block_x must be 32, 64, 128 or 256");
+  if (grid_blocks < 0) return fail(&b->err, PML_PIC_E_INVALID_ARG, "grid_blocks must be >= 0");
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  batch_drop_graph(b);
+  if (grid_blocks > 0) b->grid_blocks = grid_blocks;
+  return batch_build_items(b, block_x);
+}
+
+int pml_pic_batch_step(pml_pic_batch *b, int32_t n_steps) {
+  if (!b) return PML_PIC_E_INVALID_ARG;
+  if (n_steps < 0) return fail(&b->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
+  return b->prec == 64 ? batch_step_t<double>(b, n_steps) : batch_step_t<float>(b, n_steps);
+}
+
+int pml_pic_batch_step_profiled(pml_pic_batch *b, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
+  if (!b || !phase_ms || !phase_calls) return PML_PIC_E_INVALID_ARG;
+  if (n_steps < 0) return fail(&b->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
+  PhaseTimer pt;
+  pt.on = true;
+  int rc = b->prec == 64 ? batch_step_t<double>(b, n_steps, &pt) : batch_step_t<float>(b, n_steps, &pt);
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (rc == PML_PIC_OK && (e != hipSuccess || pt.err != hipSuccess)) {
+    b->err = std::string("HIP error: ") + hipGetErrorString(e != hipSuccess ? e : pt.err);
+    rc = PML_PIC_E_HIP;
+  }
+  for (size_t k = 0; k < pt.phase.size() && 2 * k + 1 < pt.ev.size(); ++k) {
+    float ms = 0.f;
+    if (rc == PML_PIC_OK && hipEventElapsedTime(&ms, pt.ev[2 * k], pt.ev[2 * k + 1]) == hipSuccess) {
+      phase_ms[pt.phase[k]] += ms;
+      phase_calls[pt.phase[k]] += 1;
+    }
+  }
+  for (hipEvent_t ev : pt.ev) (void)hipEventDestroy(ev);
+  return rc;
+}
+
+const char *pml_pic_batch_last_error(const pml_pic_batch *b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+void pml_pic_batch_destroy(pml_pic_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  batch_drop_graph(b);
+  for (pml_pic_handle *h : b->runs) delete h;
+  delete b;
+}
+
+}  // extern "C"
+
+namespace {
+}  // namespace
+
 // ===================================================================== C ABI
 extern "C" {
 
@@ -651,38 +963,7 @@ int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes) {
 
 int pml_pic_create(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream,
                    pml_pic_handle **out) {
-  if (!out) return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  int rc = validate(params, &g_create_error);
-  if (rc) return rc;
-  Layout L;
-  make_layout(*params, L);
-  if (!device_workspace || bytes < L.total)
-    return fail(&g_create_error, PML_PIC_E_WORKSPACE, "workspace smaller than pml_pic_workspace_size()");
-  if (((uintptr_t)device_workspace) % 256 != 0)
-    return fail(&g_create_error, PML_PIC_E_WORKSPACE, "workspace must be 256-byte aligned");
-  pml_pic_handle *h = new pml_pic_handle();
-  h->p = *params;
-  h->L = L;
-  h->ws = (char *)device_workspace;
-  h->stream = (hipStream_t)stream;
-  h->sort_interval = params->sort_interval > 0 ? params->sort_interval : 8;
-  build_tables(h);
-  hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) {
-    g_create_error = std::string("HIP error while clearing the workspace: ") + hipGetErrorString(e);
-    delete h;
-    return PML_PIC_E_HIP;
-  }
-  rc = params->precision == 64 ? upload_tables<double>(h) : upload_tables<float>(h);
-  if (rc) {
-    g_create_error = h->err;
-    delete h;
-    return rc;
-  }
-  *out = h;
-  return PML_PIC_OK;
+  return create_handle(params, device_workspace, bytes, stream, out, &g_create_error);
 }
 
 int pml_pic_add_particles(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w) {

@@ -176,4 +176,22 @@ template <typename T>
 void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int n_slots, double *rho,
                 double sign, hipStream_t s);
 
+// one run of a batch: everything its kernels need, in device memory
+template <typename T>
+struct RunDesc {
+  Grid<T> g;
+  Fields<T> F;
+  Parts<T> P;
+  StepCtl ctl;
+  int n_slots;
+  int push;
+  int alpha_mode;
+  int pad;
+};
+
+// one phase of a batched step: 0 particles, 1 B half step, 2 E step
+template <typename T>
+void launch_batch_phase(int phase, int dim, int order, const RunDesc<T> *runs, int n_runs, const int4 *items,
+                        int n_items, int bdx, int grid_blocks, hipStream_t s);
+
 }  // namespace pmlpic
