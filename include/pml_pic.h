@@ -79,6 +79,8 @@ typedef struct {
     int64_t max_particles;      /* particle capacity of the workspace */
     double charge, mass;        /* species charge and mass per unit weight */
     int32_t flags;              /* PML_PIC_FLAG_* */
+    int32_t adjoint_segment;    /* steps per checkpoint segment of the adjoint; 0 = no adjoint storage */
+    int32_t adjoint_checkpoints;/* checkpoints kept by pml_pic_forward_ckpt (segments per run) */
 } pml_pic_params;
 
 typedef struct {
@@ -175,6 +177,30 @@ int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *
  * partner density is left as it is. */
 int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X,
                           const double *u, const double *w);
+
+/* ------------------------------------------------------------------ adjoint
+ * Gradient of the interior field energy U = 1/2 sum (E^2 + B^2) dV (samples inside the
+ * physical box) after n steps with respect to the PML profile parameters
+ * theta = (sigma_coef[d][k] for d < dim, k < 16; then damping_scale; entries with
+ * k >= n_sigma_coef are not part of the profile and get 0), by a hand-written
+ * reverse-mode pass through update_yee_pml and the alpha damping.  Ballistic runs only
+ * (push = 0): the particles' paths, and so the undamped current, do not depend on the
+ * fields; alpha_mode must be PML_ALPHA_ONE or PML_ALPHA_DAMPED.  Needs
+ * params.adjoint_segment > 0 and adjoint_checkpoints * adjoint_segment >= n_steps. */
+
+/* Runs n_steps from the current state, keeping the state every adjoint_segment steps
+ * and the final state; writes U (FP64 reduction) to *U.  Synchronises. */
+int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U);
+
+/* Reverse pass of the last pml_pic_forward_ckpt: restores each checkpoint, recomputes
+ * its segment, and runs the transposed step.  seed: NULL for dU/dfields of the
+ * interior energy, else a 12-part field array (as pml_pic_get_fields) used as the
+ * adjoint of the final state.  lambda_out (12 parts, may be NULL) receives the adjoint
+ * of the initial state (for split samples per part; elsewhere the same value in both
+ * parts).  grad_theta (n_theta = 16 dim + 1 doubles) receives d(seed . state)/d(theta).
+ * The final state of the forward run is restored afterwards.  Synchronises. */
+int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out,
+                     double *grad_theta, int32_t n_theta);
 
 /* ------------------------------------------------------------------ batches
  * Many independent runs advanced together: each run has its own grid, PML, profile,

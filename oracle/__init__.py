@@ -284,3 +284,59 @@ class OracleSim:
         return {"u_interior": out[0], "u_pml": out[1], "gauss_max": out[2],
                 "gauss_l2": out[3], "rho_max": out[4], "n_particles": int(out[5]),
                 "step": int(out[6])}
+
+
+# ---------------------------------------------------------------- reference gradient
+# Parameters of the PML: the per-axis conductivity polynomial sigma/eps0 = sum_k
+# a_{d,k} (depth/L)^k (16 coefficients per axis, Sec. II.C and Sec. III) and the scale s
+# of the current damping alpha = exp(-s Phi) (Sec. II.C), packed as
+# (a_{0,0..15}, ..., a_{dim-1,0..15}, s).
+
+def theta_vector(cfg) -> np.ndarray:
+    th = np.zeros(16 * cfg.dim + 1)
+    for d in range(cfg.dim):
+        row = list(cfg.sigma_coef[d])
+        th[16 * d:16 * d + len(row)] = row
+    th[-1] = cfg.damping_scale
+    return th
+
+
+def with_theta(cfg, theta):
+    import dataclasses
+    th = np.asarray(theta, dtype=np.float64)
+    rows = [tuple(th[16 * d:16 * d + 16]) for d in range(cfg.dim)]
+    rows += [tuple(cfg.sigma_coef[d]) for d in range(cfg.dim, 3)]
+    return dataclasses.replace(cfg, sigma_coef=tuple(rows), damping_scale=float(th[-1]))
+
+
+def interior_energy(cfg, x, u, w, n_steps: int, fields=None) -> float:
+    """Field energy inside the physical box after n_steps (the energy norm of Sec. III)."""
+    o = OracleSim(cfg)
+    if fields is not None:
+        o.set_split_fields(fields)
+    if len(w):
+        o.add_particles(x, u, w)
+    o.step(n_steps)
+    return o.diagnose()["u_interior"]
+
+
+def fd_gradient(cfg, x, u, w, n_steps: int, idx=None, rel_h: float = 1e-3) -> np.ndarray:
+    """dU/dtheta by central differences, Richardson-extrapolated from steps h and h/2
+    (truncation O(h^4)); h = rel_h * max(|theta_i|, 0.1).  Entries not in idx are NaN."""
+    th0 = theta_vector(cfg)
+    idx = range(th0.size) if idx is None else idx
+    g = np.full(th0.size, np.nan)
+
+    def U(th):
+        return interior_energy(with_theta(cfg, th), x, u, w, n_steps)
+
+    for i in idx:
+        h = rel_h * max(abs(th0[i]), 0.1)
+        D = []
+        for hh in (h, 0.5 * h):
+            tp, tm = th0.copy(), th0.copy()
+            tp[i] += hh
+            tm[i] -= hh
+            D.append((U(tp) - U(tm)) / (2.0 * hh))
+        g[i] = (4.0 * D[1] - D[0]) / 3.0
+    return g

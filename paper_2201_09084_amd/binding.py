@@ -28,7 +28,8 @@ EXPORTED = [
     "pml_pic_last_error", "pml_pic_destroy", "pml_pic_step_profiled",
     "pml_pic_batch_workspace_size", "pml_pic_batch_create", "pml_pic_batch_run",
     "pml_pic_batch_set_launch", "pml_pic_batch_step", "pml_pic_batch_last_error",
-    "pml_pic_batch_destroy", "pml_pic_batch_step_profiled",
+    "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
+    "pml_pic_backward",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "unused"]
@@ -42,6 +43,7 @@ class Params(C.Structure):
         ("sigma_coef", (C.c_double * 16) * 3), ("precision", C.c_int32), ("push", C.c_int32),
         ("sort_interval", C.c_int32), ("tile", C.c_int32 * 3), ("max_particles", C.c_int64),
         ("charge", C.c_double), ("mass", C.c_double), ("flags", C.c_int32),
+        ("adjoint_segment", C.c_int32), ("adjoint_checkpoints", C.c_int32),
     ]
 
 
@@ -97,6 +99,8 @@ def load_library():
             "pml_pic_batch_step_profiled": (C.c_int, [vp, i32, dp, P(C.c_int64)]),
             "pml_pic_batch_last_error": (C.c_char_p, [vp]),
             "pml_pic_batch_destroy": (None, [vp]),
+            "pml_pic_forward_ckpt": (C.c_int, [vp, i32, dp]),
+            "pml_pic_backward": (C.c_int, [vp, dp, i64, dp, dp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -106,7 +110,7 @@ def load_library():
     return _lib
 
 
-def make_params(cfg, max_particles=None, flags=0) -> Params:
+def make_params(cfg, max_particles=None, flags=0, adjoint=(0, 0)) -> Params:
     """C parameter block from a workloads.SimConfig-like object."""
     p = Params()
     p.dim = int(cfg.dim)
@@ -132,6 +136,8 @@ def make_params(cfg, max_particles=None, flags=0) -> Params:
     p.charge = float(cfg.charge)
     p.mass = float(cfg.mass)
     p.flags = int(flags)
+    p.adjoint_segment = int(adjoint[0])
+    p.adjoint_checkpoints = int(adjoint[1])
     return p
 
 
@@ -154,13 +160,13 @@ def workspace_size(params: Params) -> int:
 class PmlPic:
     """One simulation on the current GPU (names follow the C ABI)."""
 
-    def __init__(self, cfg, max_particles=None, flags=0, stream=None, _borrowed=None):
+    def __init__(self, cfg, max_particles=None, flags=0, stream=None, _borrowed=None, adjoint=(0, 0)):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("PmlPic needs a ROCm GPU; there is no CPU fallback")
         L = load_library()
         self.cfg = cfg
-        self.params = make_params(cfg, max_particles, flags)
+        self.params = make_params(cfg, max_particles, flags, adjoint)
         if _borrowed is not None:        # a run owned by a PmlPicBatch
             self._h, self._owned, self.stream = C.c_void_p(_borrowed), False, stream
             self._init_shape()
@@ -248,6 +254,29 @@ class PmlPic:
         calls = np.zeros(8, np.int64)
         self._check(load_library().pml_pic_step_profiled(self._h, int(n), _dp(ms), _lp(calls)))
         return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(8) if calls[k] > 0}
+
+    # ---------------------------------------------------------------- adjoint
+    def forward_ckpt(self, n: int) -> float:
+        """n steps keeping checkpoints; returns the interior field energy after them."""
+        U = C.c_double()
+        self._check(load_library().pml_pic_forward_ckpt(self._h, int(n), C.byref(U)))
+        return float(U.value)
+
+    def backward(self, seed=None, want_lambda=False):
+        """Reverse pass of the last forward_ckpt.  seed: None (interior energy) or a
+        12-part array shaped like split_fields().  Returns (grad_theta, lambda or None)."""
+        L = load_library()
+        n_theta = 16 * int(self.params.dim) + 1
+        grad = np.zeros(n_theta)
+        lam = np.zeros(12 * self.nsamp) if want_lambda else None
+        if seed is not None:
+            seed = np.ascontiguousarray(seed, dtype=np.float64).reshape(-1)
+            sp, sc = _dp(seed), seed.size
+        else:
+            sp, sc = None, 0
+        self._check(L.pml_pic_backward(self._h, sp, sc, _dp(lam) if lam is not None else None, _dp(grad),
+                                       n_theta))
+        return grad, (lam.reshape((12,) + self._shape()) if lam is not None else None)
 
     def diagnose(self, allow_nonfinite=False) -> dict:
         d = Diag()

@@ -33,6 +33,13 @@ struct Layout {
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0;
   size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
   int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
+  // adjoint storage (present when adjoint_segment > 0)
+  int seg = 0, nckpt = 0;            // segment length, checkpoint slots (incl. the final state)
+  size_t fields_bytes = 0;           // the 12 E/B arrays (totals and split parts), contiguous
+  size_t parts_bytes = 0;            // one particle buffer (cell .. id), contiguous
+  size_t off_ckpt = 0, ckpt_stride = 0;
+  size_t off_seg_state = 0, off_seg_J = 0, J_bytes = 0;
+  size_t off_adj = 0, off_bh = 0, off_grad = 0;
   size_t total = 0;
 };
 
@@ -163,6 +170,21 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_partial = take(8 * (4 * (size_t)L.diag_blocks + 1024));
   L.off_result = take(8 * 8);
   L.off_flags = take(4 * 4);
+  if (p.adjoint_segment > 0) {
+    const size_t fb = L.esz * (size_t)L.nelem;          // one field array (multiple of 256 bytes)
+    L.seg = p.adjoint_segment;
+    L.nckpt = std::max(p.adjoint_checkpoints, 1) + 1;
+    L.fields_bytes = 12 * fb;
+    L.parts_bytes = L.off_id[0] + align_up(4 * cap, 256) - L.off_cell[0];
+    L.ckpt_stride = align_up(L.fields_bytes + L.parts_bytes + 256 + 8 * N_PUSH_COUNTERS, 256);
+    L.off_ckpt = take(L.ckpt_stride * L.nckpt);
+    L.off_seg_state = take(L.fields_bytes * (size_t)(L.seg + 1));
+    L.J_bytes = 3 * fb;
+    L.off_seg_J = take(L.J_bytes * (size_t)L.seg);
+    L.off_adj = take(12 * fb);
+    L.off_bh = take(6 * fb);
+    L.off_grad = take(8 * 3 * 8 * (size_t)L.ntab);
+  }
   L.total = off;
 }
 
@@ -183,6 +205,13 @@ struct pml_pic_handle {
   bool sort_pending = false;
   // FP64 host copies of the per-axis tables: [axis][kind][ntab]
   std::vector<double> tab64;
+  // adjoint bookkeeping: host metadata of each checkpoint, steps of the last forward
+  struct CkptMeta { int cur; int64_t n_slots, n_added, step; int since_sort; bool sort_pending; };
+  std::vector<CkptMeta> ckpt_meta;
+  int64_t fwd_steps = -1;
+  // while set, step k of step_t copies the 12 field arrays before the step to
+  // snap_state[k] and the undamped current after the deposit to snap_J[k]
+  std::vector<char *> snap_state, snap_J;
 
   template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
   double tab(int axis, int kind, int i) const { return tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G]; }
@@ -519,6 +548,8 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
   for (int it = 0; it < nsteps; ++it) {
+    if (it < (int)h->snap_state.size())
+      HIPCHK(h, hipMemcpyAsync(h->snap_state[it], F.E[0], h->L.fields_bytes, hipMemcpyDeviceToDevice, s));
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
       pt.begin(s);
       launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
@@ -542,6 +573,8 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, s);
       pt.end(s, PML_PIC_PHASE_DEPOSIT);
     }
+    if (it < (int)h->snap_J.size())
+      HIPCHK(h, hipMemcpyAsync(h->snap_J[it], F.J[0], h->L.J_bytes, hipMemcpyDeviceToDevice, s));
     if (sep_damp && h->p.alpha_mode != PML_ALPHA_ONE) {
       pt.begin(s);
       launch_damp_current<T>(g, F, s);
@@ -1126,6 +1159,265 @@ void pml_pic_destroy(pml_pic_handle *h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   delete h;
+}
+
+}  // extern "C"
+
+// ===================================================================== adjoint (host side)
+namespace {
+
+template <typename T>
+Fields<T> fields_at(const pml_pic_handle *h, char *base) {
+  const size_t fb = sizeof(T) * (size_t)h->L.nelem;
+  Fields<T> F;
+  for (int a = 0; a < 3; ++a) {
+    F.E[a] = (T *)(base + a * fb);
+    F.B[a] = (T *)(base + (3 + a) * fb);
+    F.Ea[a] = (T *)(base + (6 + a) * fb);
+    F.Ba[a] = (T *)(base + (9 + a) * fb);
+    F.J[a] = nullptr;
+  }
+  return F;
+}
+
+char *ckpt_ptr(pml_pic_handle *h, int c) { return h->ws + h->L.off_ckpt + (size_t)c * h->L.ckpt_stride; }
+
+int save_ckpt(pml_pic_handle *h, int c) {
+  const Layout &L = h->L;
+  char *dst = ckpt_ptr(h, c);
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(dst, h->ws + L.off_field[0], L.fields_bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(dst + L.fields_bytes, h->ws + L.off_cell[h->cur], L.parts_bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(dst + L.fields_bytes + L.parts_bytes, h->ws + L.off_count, 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(dst + L.fields_bytes + L.parts_bytes + 256, h->ws + L.off_pushes, 8 * N_PUSH_COUNTERS,
+                           hipMemcpyDeviceToDevice, s));
+  if ((int)h->ckpt_meta.size() < L.nckpt) h->ckpt_meta.resize(L.nckpt);
+  h->ckpt_meta[c] = {h->cur, h->n_slots, h->n_added, h->step, h->since_sort, h->sort_pending};
+  return PML_PIC_OK;
+}
+
+int restore_ckpt(pml_pic_handle *h, int c) {
+  const Layout &L = h->L;
+  const pml_pic_handle::CkptMeta m = h->ckpt_meta[c];
+  h->cur = m.cur; h->n_slots = m.n_slots; h->n_added = m.n_added; h->step = m.step;
+  h->since_sort = m.since_sort; h->sort_pending = m.sort_pending;
+  const char *src = ckpt_ptr(h, c);
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(h->ws + L.off_field[0], src, L.fields_bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->ws + L.off_cell[h->cur], src + L.fields_bytes, L.parts_bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->ws + L.off_count, src + L.fields_bytes + L.parts_bytes, 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->ws + L.off_pushes, src + L.fields_bytes + L.parts_bytes + 256, 8 * N_PUSH_COUNTERS,
+                           hipMemcpyDeviceToDevice, s));
+  return PML_PIC_OK;
+}
+
+int check_adjoint(pml_pic_handle *h) {
+  if (h->L.seg <= 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "created without adjoint_segment");
+  if (h->p.push != 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint covers ballistic runs (push = 0)");
+  if (h->p.alpha_mode == PML_ALPHA_ZERO)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "alpha_mode 0 is not differentiable in the profile");
+  return PML_PIC_OK;
+}
+
+template <typename T>
+int forward_ckpt_t(pml_pic_handle *h, int n, double *U) {
+  int rc = check_adjoint(h);
+  if (rc) return rc;
+  const int seg = h->L.seg;
+  if (n < 1 || (n + seg - 1) / seg > h->L.nckpt - 1)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_steps exceeds adjoint_checkpoints * adjoint_segment");
+  PhaseTimer pt;
+  for (int c = 0; c * seg < n; ++c) {
+    if ((rc = save_ckpt(h, c))) return rc;
+    if ((rc = step_t<T>(h, std::min(seg, n - c * seg), pt))) return rc;
+  }
+  if ((rc = save_ckpt(h, h->L.nckpt - 1))) return rc;
+  h->fwd_steps = n;
+  pml_pic_diag d;
+  rc = diagnose_t<T>(h, &d);
+  if (rc && rc != PML_PIC_E_NONFINITE) return rc;
+  *U = d.u_interior;
+  return rc;
+}
+
+// dg/dsigma for g = (1 - exp(-sigma tau))/sigma, stable for small sigma tau
+double dg_dsigma(double sig, double tau) {
+  const double x = sig * tau;
+  if (x < 1e-3) return tau * tau * (-0.5 + x / 3.0 - x * x / 8.0 + x * x * x / 30.0);
+  const double e = std::exp(-x);
+  return (tau * e - (-std::expm1(-x)) / sig) / sig;
+}
+
+void chain_rule(const pml_pic_handle *h, const std::vector<double> &Gv, double *grad) {
+  const pml_pic_params &p = h->p;
+  const Layout &L = h->L;
+  const int NK = 8;   // gradient kinds, in the order of adjoint.hip
+  auto Gat = [&](int axis, int kind, int i) { return Gv[((size_t)axis * NK + kind) * L.ntab + i + G]; };
+  for (int k = 0; k < 16 * p.dim + 1; ++k) grad[k] = 0.0;
+  for (int d = 0; d < p.dim; ++d) {
+    for (int i = -G; i <= L.M[d] + G; ++i) {
+      for (int centre = 0; centre < 2; ++centre) {
+        const double X = i + 0.5 * centre;
+        if (X < 0.0 || X > (double)L.M[d]) continue;
+        double thick;
+        const double dep = pml_depth(p, d, X, &thick);
+        if (dep <= 0.0 || thick <= 0.0) continue;
+        double sig, phi;
+        profile(p, d, X, &sig, &phi);
+        const double r = dep / thick;
+        double dUdsig, dUdalpha;
+        if (!centre) {
+          const double tau = p.dt, e = std::exp(-sig * tau);
+          const double dg = dg_dsigma(sig, tau);
+          dUdsig = Gat(d, 0, i) * (-tau * e) + Gat(d, 1, i) * dg + Gat(d, 2, i) * dg / p.dx[d] + Gat(d, 7, i);
+          dUdalpha = Gat(d, 5, i);
+        } else {
+          const double tau = 0.5 * p.dt, e = std::exp(-sig * tau);
+          const double dg = dg_dsigma(sig, tau);
+          dUdsig = Gat(d, 3, i) * (-tau * e) + Gat(d, 4, i) * dg / p.dx[d];
+          dUdalpha = Gat(d, 6, i);
+        }
+        double alpha = 1.0;
+        if (p.alpha_mode == PML_ALPHA_DAMPED) alpha = std::exp(-p.damping_scale * phi);
+        else dUdalpha = 0.0;
+        double rk = 1.0;
+        for (int k = 0; k < p.n_sigma_coef; ++k) {
+          const double dphi = thick * rk * r / (k + 1);
+          grad[16 * d + k] += dUdsig * rk + dUdalpha * (-p.damping_scale * alpha * dphi);
+          rk *= r;
+        }
+        grad[16 * p.dim] += dUdalpha * (-phi * alpha);
+      }
+    }
+  }
+}
+
+template <typename T>
+int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double *grad) {
+  int rc = check_adjoint(h);
+  if (rc) return rc;
+  if (h->fwd_steps < 1) return fail(&h->err, PML_PIC_E_INVALID_ARG, "no pml_pic_forward_ckpt run to reverse");
+  const Layout &L = h->L;
+  const Grid<T> g = h->grid<T>();
+  hipStream_t s = h->stream;
+  const size_t fb = sizeof(T) * (size_t)L.nelem;
+  const int n = (int)h->fwd_steps, seg = L.seg;
+  double *Gacc = h->at<double>(L.off_grad);
+  HIPCHK(h, hipMemsetAsync(Gacc, 0, 8 * 3 * 8 * (size_t)L.ntab, s));
+  AdjFields<T> A;
+  for (int c = 0; c < 6; ++c) {
+    A.LT[c] = (T *)(h->ws + L.off_adj + c * fb);
+    A.LA[c] = (T *)(h->ws + L.off_adj + (6 + c) * fb);
+  }
+  HIPCHK(h, hipMemsetAsync(h->ws + L.off_adj, 0, 12 * fb, s));
+  if ((rc = restore_ckpt(h, L.nckpt - 1))) return rc;
+  const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
+  if (!seed) {
+    launch_adj_seed_energy<T>(g, h->fields<T>(), A, s);
+  } else {   // 12-part seed -> LT / LA
+    std::vector<T> lt(L.nelem), la(L.nelem);
+    for (int c = 0; c < 6; ++c) {
+      std::fill(lt.begin(), lt.end(), T(0));
+      std::fill(la.begin(), la.end(), T(0));
+      const int up = unsplit_part(h->p, c);
+      const double *s0 = seed + (size_t)(2 * c) * ns, *s1 = seed + (size_t)(2 * c + 1) * ns;
+      for (int k = 0; k < L.nn[2]; ++k)
+        for (int j = 0; j < L.nn[1]; ++j)
+          for (int i = 0; i < L.nn[0]; ++i) {
+            const size_t o = ((size_t)k * L.nn[1] + j) * L.nn[0] + i;
+            const long q = L.base + i + j * L.sy + k * L.sz;
+            const int id[3] = {i, j, k};
+            if (up < 0 && split_active(h, c, id)) { lt[q] = (T)s1[o]; la[q] = (T)(s0[o] - s1[o]); }
+            else lt[q] = (T)(up == 1 ? s1[o] : s0[o]);
+          }
+      HIPCHK(h, hipMemcpyAsync(A.LT[c], lt.data(), fb, hipMemcpyHostToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(A.LA[c], la.data(), fb, hipMemcpyHostToDevice, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+    }
+  }
+  char *seg_state = h->ws + L.off_seg_state;
+  char *seg_J = h->ws + L.off_seg_J;
+  char *bh = h->ws + L.off_bh;
+  const int nseg = (n + seg - 1) / seg;
+  PhaseTimer pt;
+  for (int c = nseg - 1; c >= 0; --c) {
+    if ((rc = restore_ckpt(h, c))) return rc;
+    const int len = std::min(seg, n - c * seg);
+    h->snap_state.clear();
+    h->snap_J.clear();
+    for (int k = 0; k < len; ++k) {
+      h->snap_state.push_back(seg_state + (size_t)k * L.fields_bytes);
+      h->snap_J.push_back(seg_J + (size_t)k * L.J_bytes);
+    }
+    rc = step_t<T>(h, len, pt);
+    h->snap_state.clear();
+    h->snap_J.clear();
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(seg_state + (size_t)len * L.fields_bytes, h->ws + L.off_field[0], L.fields_bytes,
+                             hipMemcpyDeviceToDevice, s));
+    for (int k = len - 1; k >= 0; --k) {
+      const Fields<T> Fn = fields_at<T>(h, seg_state + (size_t)k * L.fields_bytes);
+      const Fields<T> Fn1 = fields_at<T>(h, seg_state + (size_t)(k + 1) * L.fields_bytes);
+      // B^{n+1/2} from the stored B^n, E^n
+      HIPCHK(h, hipMemcpyAsync(bh, Fn.B[0], 3 * fb, hipMemcpyDeviceToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(bh + 3 * fb, Fn.Ba[0], 3 * fb, hipMemcpyDeviceToDevice, s));
+      Fields<T> FH = Fn;
+      for (int a = 0; a < 3; ++a) { FH.B[a] = (T *)(bh + a * fb); FH.Ba[a] = (T *)(bh + (3 + a) * fb); }
+      launch_update_B<T>(g, FH, true, s);
+      T *J[3];
+      for (int a = 0; a < 3; ++a) J[a] = (T *)(seg_J + (size_t)k * L.J_bytes + a * fb);
+      Fields<T> F3 = FH;        // second B half step: B^{n+1/2} -> B^{n+1} with E^{n+1}
+      for (int a = 0; a < 3; ++a) F3.E[a] = Fn1.E[a];
+      launch_adj_B_half<T>(g, A, F3, Gacc, s);
+      launch_adj_E<T>(g, A, FH, J, h->p.alpha_mode, Gacc, s);   // E^n -> E^{n+1} with B^{n+1/2}
+      launch_adj_B_half<T>(g, A, Fn, Gacc, s);                 // first half step: B^n, E^n
+    }
+    HIPCHK(h, hipGetLastError());
+  }
+  if ((rc = restore_ckpt(h, L.nckpt - 1))) return rc;
+  std::vector<double> Gv((size_t)3 * 8 * L.ntab);
+  HIPCHK(h, hipMemcpyAsync(Gv.data(), Gacc, 8 * Gv.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  chain_rule(h, Gv, grad);
+  if (lambda_out) {
+    std::vector<T> lt(L.nelem), la(L.nelem);
+    for (int c = 0; c < 6; ++c) {
+      HIPCHK(h, hipMemcpy(lt.data(), A.LT[c], fb, hipMemcpyDeviceToHost));
+      HIPCHK(h, hipMemcpy(la.data(), A.LA[c], fb, hipMemcpyDeviceToHost));
+      const int up = unsplit_part(h->p, c);
+      double *o0 = lambda_out + (size_t)(2 * c) * ns, *o1 = lambda_out + (size_t)(2 * c + 1) * ns;
+      for (int k = 0; k < L.nn[2]; ++k)
+        for (int j = 0; j < L.nn[1]; ++j)
+          for (int i = 0; i < L.nn[0]; ++i) {
+            const size_t o = ((size_t)k * L.nn[1] + j) * L.nn[0] + i;
+            const long q = L.base + i + j * L.sy + k * L.sz;
+            const int id[3] = {i, j, k};
+            const double vt = (double)lt[q];
+            if (up < 0 && split_active(h, c, id)) { o0[o] = vt + (double)la[q]; o1[o] = vt; }
+            else { o0[o] = vt; o1[o] = vt; }
+          }
+    }
+  }
+  return PML_PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U) {
+  if (!h || !U) return PML_PIC_E_INVALID_ARG;
+  return h->p.precision == 64 ? forward_ckpt_t<double>(h, n_steps, U) : forward_ckpt_t<float>(h, n_steps, U);
+}
+
+int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out,
+                     double *grad_theta, int32_t n_theta) {
+  if (!h || !grad_theta) return PML_PIC_E_INVALID_ARG;
+  if (n_theta != 16 * h->p.dim + 1) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_theta must be 16 dim + 1");
+  const int64_t ns = (int64_t)h->L.nn[0] * h->L.nn[1] * h->L.nn[2];
+  if (seed && seed_count < 12 * ns) return fail(&h->err, PML_PIC_E_INVALID_ARG, "seed buffer too small");
+  return h->p.precision == 64 ? backward_t<double>(h, seed, lambda_out, grad_theta)
+                              : backward_t<float>(h, seed, lambda_out, grad_theta);
 }
 
 }  // extern "C"

@@ -176,6 +176,21 @@ template <typename T>
 void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int n_slots, double *rho,
                 double sign, hipStream_t s);
 
+// adjoint of the fields: LT[c] (part driven along a+2, or the whole component where it
+// is not split), LA[c] (part driven along a+1 minus LT), c = E_x .. B_z
+template <typename T>
+struct AdjFields {
+  T *LT[6];
+  T *LA[6];
+};
+template <typename T>
+void launch_adj_seed_energy(const Grid<T> &g, const Fields<T> &F, const AdjFields<T> &L, hipStream_t s);
+template <typename T>
+void launch_adj_B_half(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> &Fb, double *Gacc, hipStream_t s);
+template <typename T>
+void launch_adj_E(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> &Fe, T *const J[3], int alpha_mode,
+                  double *Gacc, hipStream_t s);
+
 // one run of a batch: everything its kernels need, in device memory
 template <typename T>
 struct RunDesc {

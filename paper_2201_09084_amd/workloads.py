@@ -169,10 +169,49 @@ def beam3d_particles(cfg: SimConfig, seed: int = 1004, background_ppc: float = 1
 
 # ---------------------------------------------------------------- workload 5
 def adjoint_config(precision: int = 32, n: int = 512, pml: int = 16) -> SimConfig:
-    """2D 512x512 grid, 16-cell PML, quadratic shape, c dt = 0.7."""
+    """2D 512x512 grid, 16-cell PML, quadratic shape, c dt = 0.7, ballistic particles
+    (the current does not depend on the fields, so the adjoint is that of the field
+    update and of the damping)."""
     return SimConfig(dim=2, n=(n, n, 1), pml=((pml, pml), (pml, pml), (0, 0)), dt=0.7,
                      shape_order=2, alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
-                     sigma_coef=cubic_profile(3.2), push=1, precision=precision)
+                     sigma_coef=cubic_profile(3.2), push=0, precision=precision)
+
+
+def positive_profile(scale: float = 1.0) -> tuple:
+    """A 16-term profile with every coefficient positive (sigma > 0 throughout the
+    layer for small changes of any coefficient), close to the cubic 3.2 r^3."""
+    row = (0.05, 0.1, 0.3, 2.5) + (0.02,) * 12
+    return (tuple(scale * a for a in row),) * 3
+
+
+def adjoint_small_config(precision: int = 64, n: int = 40, pml: int = 8, dim: int = 2) -> SimConfig:
+    """Small ballistic case for gradient checks against the oracle."""
+    nz = n if dim == 3 else 1
+    pz = (pml, pml) if dim == 3 else (0, 0)
+    return SimConfig(dim=dim, n=(n, n, nz), pml=((pml, pml), (pml, pml), pz), dt=0.5 if dim == 3 else 0.7,
+                     shape_order=2, alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
+                     sigma_coef=positive_profile(), push=0, precision=precision)
+
+
+def adjoint_small_particles(cfg: SimConfig, n_particles: int = 6, seed: int = 1006,
+                            diagonal: bool = False) -> Particles:
+    """A few particles (gamma 3) a quarter box before the +x face, 10 degrees from +x;
+    with diagonal=True they start on the line x = y and move along (1, 1)."""
+    rng = np.random.default_rng(seed)
+    x = np.empty((n_particles, cfg.dim))
+    if diagonal:
+        t = rng.uniform(0.6, 0.7, n_particles) * cfg.n[0]
+        x[:, 0] = t
+        x[:, 1] = t
+        ang = np.full(n_particles, math.radians(45.0))
+    else:
+        x[:, 0] = rng.uniform(0.70, 0.78, n_particles) * cfg.n[0]
+        x[:, 1] = rng.uniform(0.40, 0.60, n_particles) * cfg.n[1]
+        ang = np.full(n_particles, math.radians(10.0))
+    if cfg.dim == 3:
+        x[:, 2] = rng.uniform(0.40, 0.60, n_particles) * cfg.n[2]
+    x *= np.asarray(cfg.dx[:cfg.dim])
+    return Particles(x=x, u=_momentum(np.full(n_particles, 3.0), ang), w=np.full(n_particles, 1.0 / n_particles))
 
 
 def adjoint_particles(cfg: SimConfig, n_particles: int = 4096, seed: int = 1005) -> Particles:
