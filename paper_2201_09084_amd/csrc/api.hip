@@ -30,7 +30,9 @@ struct Layout {
   size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_id[2] = {};
   size_t off_oldcell = 0, off_oldf[3] = {};
   size_t off_count = 0, off_pushes = 0;
-  size_t off_counts = 0, off_rank = 0, off_blocksums = 0;
+  size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
+  int ntiles = 1;
+  size_t off_items = 0, max_items = 0;
   size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
   int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
   // adjoint storage (present when adjoint_segment > 0)
@@ -165,6 +167,13 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_counts = take(4 * ((size_t)L.nkeys + 1));
   L.off_rank = take(4 * cap);
   L.off_blocksums = take(4 * ((size_t)L.nscan + 2));
+  L.ntiles = L.ntile[0] * L.ntile[1] * L.ntile[2];
+  L.off_tprefix = take(4 * ((size_t)L.ntiles + 1));
+  L.off_tpartial = take(4 * ((size_t)L.ntiles + 1));
+  L.off_tblocks = take(4 * ((size_t)(L.ntiles + 4095) / 4096 + 2));
+  // chunks of the tiled step: at most one partial chunk per tile beyond cap / chunk
+  L.max_items = (size_t)L.ntiles + (cap + tiled_chunk(p.dim) - 1) / tiled_chunk(p.dim);
+  L.off_items = take(16 * L.max_items);
   L.off_rho = take(8 * (size_t)L.nelem);
   L.off_rho_static = take(8 * (size_t)L.nelem);
   L.off_partial = take(8 * (4 * (size_t)L.diag_blocks + 1024));
@@ -276,6 +285,33 @@ struct pml_pic_handle {
     s.nkeys = L.nkeys;
     for (int d = 0; d < 3; ++d) { s.tile[d] = L.tile[d]; s.ntile[d] = L.ntile[d]; }
     return s;
+  }
+  TileWork tilework() const {
+    TileWork w;
+    w.key_start = at<uint32_t>(L.off_counts);
+    w.prefix = at<uint32_t>(L.off_tprefix);
+    w.pprefix = at<uint32_t>(L.off_tpartial);
+    w.blocksums = at<uint32_t>(L.off_tblocks);
+    w.items = at<int4>(L.off_items);
+    w.ntiles = L.ntiles;
+    w.tilecells = L.tile[0] * L.tile[1] * L.tile[2];
+    w.chunk = tiled_chunk(p.dim);
+    for (int d = 0; d < 3; ++d) { w.tile[d] = L.tile[d]; w.ntile[d] = L.ntile[d]; }
+    // 3D: a fixed range of the sorted array straddles tiles whose joint box is too big
+    // for LDS, so chunks follow the tiles; 2D: fixed ranges keep every chunk full
+    w.by_tile = p.dim == 3 ? 1 : 0;
+    // widest margin (<= 2 cells) whose box (tile + 2 margin + deposit window per axis)
+    // fits in LDS twice (two replicas), else once
+    const int win = p.shape_order == 1 ? 4 : 6;
+    w.margin = 0;
+    bool found = false;
+    for (int copies = 2; copies >= 1 && !found; --copies)
+      for (int m = 2; m >= 0; --m) {
+        long nodes = 1;
+        for (int d = 0; d < p.dim; ++d) nodes *= L.tile[d] + 2 * m + win - 1;
+        if (copies * ((3 * nodes) | 1) <= 3L * tiled_nodes(p.dim)) { w.margin = m; found = true; break; }
+      }
+    return w;
   }
   DiagWork diagwork() const {
     DiagWork w;
@@ -553,6 +589,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
       pt.begin(s);
       launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
+      if (fused && h->p.dim == 3) launch_tile_chunks(h->tilework(), ctl.count, s);
       pt.end(s, PML_PIC_PHASE_SORT);
       h->cur = 1 - h->cur;
       h->since_sort = 0;
@@ -565,7 +602,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     const Parts<T> P = h->parts<T>(h->cur);
     pt.begin(s);
-    if (fused && use_sort) launch_push_deposit_tiled<T>(g, F, P, ctl, ns, h->p.push, s);
+    if (fused && use_sort) launch_push_deposit_tiles<T>(g, F, P, ctl, h->tilework(), ns, h->p.push, s);
     else launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
     pt.end(s, PML_PIC_PHASE_PUSH);
     if (!fused) {
@@ -1200,7 +1237,8 @@ int restore_ckpt(pml_pic_handle *h, int c) {
   const Layout &L = h->L;
   const pml_pic_handle::CkptMeta m = h->ckpt_meta[c];
   h->cur = m.cur; h->n_slots = m.n_slots; h->n_added = m.n_added; h->step = m.step;
-  h->since_sort = m.since_sort; h->sort_pending = m.sort_pending;
+  // the tiled step needs the key ranges of the sort that ordered the restored buffer
+  h->since_sort = m.since_sort; h->sort_pending = true;
   const char *src = ckpt_ptr(h, c);
   hipStream_t s = h->stream;
   HIPCHK(h, hipMemcpyAsync(h->ws + L.off_field[0], src, L.fields_bytes, hipMemcpyDeviceToDevice, s));

@@ -142,9 +142,25 @@ void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
 template <typename T>
 void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                         StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s);
+// Work decomposition of the tiled particle step: after every sort, each tile's range
+// of cell-sorted particles is cut into chunks of at most `chunk` particles, listed as
+// work items (full chunks first, then each tile's partial chunk).
+struct TileWork {
+  const uint32_t *key_start;   // sort counts: first slot of every cell key at the last sort
+  uint32_t *prefix;            // ntiles + 1: exclusive prefix of full chunks per tile, total last
+  uint32_t *pprefix;           // ntiles + 1: the same for the partial last chunk of each tile
+  uint32_t *blocksums;         // scan scratch
+  int4 *items;                 // per chunk: first slot, end slot, tile
+  int ntiles, tilecells, chunk, margin;
+  int tile[3], ntile[3];
+  int by_tile;                 // 1: tile items; 0: fixed ranges of the sorted array
+};
+void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s);
+int tiled_chunk(int dim);   // particles per chunk of the tiled step
+int tiled_nodes(int dim);   // LDS nodes per current component of one chunk's box
 template <typename T>
-void launch_push_deposit_tiled(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, int n_slots,
-                               int push, hipStream_t s);
+void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+                               const TileWork &tw, int n_slots, int push, hipStream_t s);
 template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                     StepCtl ctl, int n_slots, hipStream_t s);

@@ -30,69 +30,133 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
   count_pushes(ctl.pushes, active);
 }
 
-// Tiled form of the fused step for cell-sorted particles.  A workgroup takes a
-// contiguous chunk of TPB*PPT particles; their old cells bound the nodes the chunk can
-// deposit to (the move window spans [i0 + WLO, i0 + WHI] per axis).  If that box fits
-// in LDS the chunk accumulates its current there with LDS atomics and then adds every
-// non-zero LDS entry to global J once; otherwise it falls back to global atomics.
 constexpr int TPB = 256;
-// LDS nodes per current component (2D: ~24 KB of FP32; 3D holds a box around two 8^3
-// tiles at 1 particle per cell, 19 x 11 x 11 nodes) and particles per thread
+// LDS nodes per current component and particles per thread.  2D: ~24 KB of FP32,
+// replicas of small boxes for dense beams.  3D: two replicas of the 11^3-node box of
+// one 8^3 tile with the linear-shape window (32 KB of FP32; a larger box costs more
+// in occupancy than the replicas gain).
 template <int DIM> struct TileCfg;
 template <> struct TileCfg<2> { static constexpr int NODES = 2048; static constexpr int PPT = 4; };
-template <> struct TileCfg<3> { static constexpr int NODES = 2560; static constexpr int PPT = 2; };
+template <> struct TileCfg<3> { static constexpr int NODES = 2688; static constexpr int PPT = 4; };
 
-template <typename T, int DIM, int ORDER, int PPT>
-__global__ void __launch_bounds__(TPB) k_push_deposit_tiled(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl,
-                                                            int n_slots, int push) {
+// Fused gather_push + deposit_current over chunks of cell-sorted particles.  A
+// workgroup takes one chunk: either a work item of one sort tile (by_tile: the
+// chunk's particles all belong to one tile) or a fixed range of the sorted array.  It
+// accumulates Esirkepov's current in an LDS box, replicated R times with an odd
+// stride so that lanes that share a node meet in different words and banks, and then
+// adds every non-zero entry to global J once (distinct consecutive addresses).  The
+// box is the bounding box of the chunk's old cells plus the deposit window; for a
+// tile item whose particles spread since the sort, it may instead be that box
+// clipped to the tile grown by `margin` cells per side (when the whole box does not
+// fit, or when clipping buys more replicas at the cost of at most 1/16 of the chunk),
+// and particles outside it deposit straight to global J.
+template <typename T, int DIM, int ORDER, int PPT, bool BY_TILE>
+__global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl,
+                                                            TileWork tw, int push) {
   constexpr int WLO = ORDER == 1 ? -1 : -2;
   constexpr int WHI = ORDER == 1 ? 2 : 3;
   constexpr int NODES = TileCfg<DIM>::NODES;
   __shared__ T lds[3 * NODES];
-  __shared__ int sbox[6];
-  __shared__ unsigned int n_pushed;
+  __shared__ int sbox[12];   // min[3], max[3] of the old cells; then the same clipped
+  __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
-  if (tid == 0) n_pushed = 0u;
-  const int count = min(*ctl.count, n_slots);
-  const int base = blockIdx.x * (TPB * PPT);
-  if (tid < 3) { sbox[tid] = 0x7FFFFFFF; sbox[3 + tid] = -0x7FFFFFFF; }
+  int p0, p1, t = -1;
+  if constexpr (BY_TILE) {
+    if (blockIdx.x >= tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles]) return;   // uniform over the workgroup
+    const int4 item = tw.items[blockIdx.x];
+    p0 = item.x; p1 = item.y; t = item.z;
+  } else {
+    p0 = blockIdx.x * (TPB * PPT);
+    p1 = min(p0 + TPB * PPT, *ctl.count);
+    if (p0 >= p1) return;
+  }
+  int clo[3] = {-0x3FFFFFFF, -0x3FFFFFFF, -0x3FFFFFFF}, chi[3] = {0x3FFFFFFF, 0x3FFFFFFF, 0x3FFFFFFF};
+  if (t >= 0) {   // old cells of the tile grown by the margin
+    const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      clo[d] = tc[d] * tw.tile[d] - tw.margin;
+      chi[d] = tc[d] * tw.tile[d] + tw.tile[d] - 1 + tw.margin;
+    }
+  }
+  if (tid == 0) { n_pushed = 0u; n_out = 0u; }
+  if (tid < 3) {
+    sbox[tid] = 0x7FFFFFFF; sbox[3 + tid] = -0x7FFFFFFF;
+    sbox[6 + tid] = 0x7FFFFFFF; sbox[9 + tid] = -0x7FFFFFFF;
+  }
   __syncthreads();
-  // bounding box of the chunk's old cells
-  int mn[3] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF}, mx[3] = {-0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF};
+  int mn[6] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+  int mx[6] = {-0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF};
+  unsigned int out = 0u;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int p = base + k * TPB + tid;
-    if (p < count) {
+    const int p = p0 + k * TPB + tid;
+    if (p < p1) {
       const uint32_t c = P.cell[p];
       if (c != DEAD) {
         int id[3];
         unpack_cell(DIM, c, id[0], id[1], id[2]);
+        bool in = true;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) { mn[d] = min(mn[d], id[d]); mx[d] = max(mx[d], id[d]); }
+        for (int d = 0; d < DIM; ++d) {
+          mn[d] = min(mn[d], id[d]);
+          mx[d] = max(mx[d], id[d]);
+          if constexpr (BY_TILE) {
+            const int v = min(max(id[d], clo[d]), chi[d]);
+            in = in && v == id[d];
+            mn[3 + d] = min(mn[3 + d], v);
+            mx[3 + d] = max(mx[3 + d], v);
+          }
+        }
+        out += in ? 0u : 1u;
       }
     }
   }
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    if (mn[d] <= mx[d]) { atomicMin(&sbox[d], mn[d]); atomicMax(&sbox[3 + d], mx[d]); }
+    if (mn[d] <= mx[d]) {
+      atomicMin(&sbox[d], mn[d]); atomicMax(&sbox[3 + d], mx[d]);
+      if constexpr (BY_TILE) { atomicMin(&sbox[6 + d], mn[3 + d]); atomicMax(&sbox[9 + d], mx[3 + d]); }
+    }
   }
+  if (BY_TILE && out) atomicAdd(&n_out, out);
   __syncthreads();
   LdsSink<T> lsink;
-  lsink.lds = lds;
-  int ext[3] = {1, 1, 1};
-  bool any = sbox[0] <= sbox[3];
+  const bool any = sbox[0] <= sbox[3];
+  // replicas that fit for a box of n nodes per component (0: does not fit)
+  auto reps = [&](int n) {
+    const int st = (3 * n) | 1;
+    int r = 0;
+    while (r < 16 && (r ? 2 * r : 1) * st <= 3 * NODES) r = r ? 2 * r : 1;
+    return r;
+  };
+  int o = 0;   // 0: whole bounding box; 6: clipped box, particles outside it go global
+  if (BY_TILE && any) {
+    int full = 1, clip = 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      full *= sbox[3 + d] - sbox[d] + (WHI - WLO) + 1;
+      clip *= sbox[9 + d] - sbox[6 + d] + (WHI - WLO) + 1;
+    }
+    const int rf = reps(full), rc = reps(clip);
+    // the clipped box wins if the whole one does not fit, or if it allows more
+    // replicas at the price of at most 1/16 of the chunk going to global memory
+    if (rf == 0 || (rc > rf && 16u * n_out <= (unsigned)(p1 - p0))) o = 6;
+  }
+  int ext[3] = {1, 1, 1}, bmn[3] = {0, 0, 0}, bmx[3] = {0, 0, 0};
   int total = 1;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < DIM) {
-      lsink.lo[d] = sbox[d] + WLO;
-      ext[d] = any ? sbox[3 + d] - sbox[d] + (WHI - WLO) + 1 : 1;
+      bmn[d] = sbox[o + d];
+      bmx[d] = sbox[o + 3 + d];
+      lsink.lo[d] = bmn[d] + WLO;
+      ext[d] = any ? bmx[d] - bmn[d] + (WHI - WLO) + 1 : 1;
     } else {
       lsink.lo[d] = 0;
     }
     total *= ext[d];
   }
-  // replicas of the box that fit: R in {1, 2, 4, 8, 16}, odd stride between copies
   const int stride = (3 * total) | 1;
   const bool use_lds = any && stride <= 3 * NODES;
   int R = 1;
@@ -108,14 +172,17 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiled(Grid<T> g, Fields<T>
   GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
 #pragma unroll 1
   for (int k = 0; k < PPT; ++k) {
-    const int p = base + k * TPB + tid;
+    const int p = p0 + k * TPB + tid;
     bool active = false;
-    if (p < count) {
+    if (p < p1) {
       const uint32_t c = P.cell[p];
       if (c != DEAD) {
         active = true;
         int id[3];
         unpack_cell(DIM, c, id[0], id[1], id[2]);
+        bool inbox = use_lds;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) inbox = inbox && id[d] >= bmn[d] && id[d] <= bmx[d];
         T f[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
         T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
         if (push) {
@@ -131,7 +198,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiled(Grid<T> g, Fields<T>
 #pragma unroll
         for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
         const T qw = g.charge * P.w[p];
-        if (use_lds) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
+        if (inbox) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
         else deposit<T, DIM, ORDER>(g, gsink, id0, f0, id, f, u[2] * ig, qw);
         P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
       }
@@ -155,6 +222,37 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiled(Grid<T> g, Fields<T>
       atomic_add(&F.J[comp][g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk)], v);
     }
   }
+}
+
+// chunks per tile from the sorted key ranges (count: live slots after the sort)
+__device__ __forceinline__ void tile_range(const TileWork &tw, int t, const int32_t *count, uint32_t &s, uint32_t &e) {
+  s = tw.key_start[(size_t)t * tw.tilecells];
+  e = t + 1 < tw.ntiles ? tw.key_start[(size_t)(t + 1) * tw.tilecells] : (uint32_t)*count;
+}
+__global__ void k_tile_chunks(TileWork tw, const int32_t *count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tw.ntiles) return;
+  uint32_t s, e;
+  tile_range(tw, t, count, s, e);
+  const uint32_t n = e > s ? e - s : 0u;
+  tw.prefix[t] = n / tw.chunk;
+  tw.pprefix[t] = n % tw.chunk ? 1u : 0u;
+}
+// one work item per chunk, after the scans: every full chunk first, then the partial
+// last chunks of the tiles (the short items finish the launch instead of a long one)
+__global__ void k_tile_items(TileWork tw, const int32_t *count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tw.ntiles) return;
+  uint32_t s, e;
+  tile_range(tw, t, count, s, e);
+  const uint32_t nfull = e > s ? (e - s) / tw.chunk : 0u;
+  const uint32_t first = tw.prefix[t];
+  for (uint32_t c = 0; c < nfull; ++c) {
+    const uint32_t p = s + c * tw.chunk;
+    tw.items[first + c] = make_int4((int)p, (int)(p + tw.chunk), t, 0);
+  }
+  const uint32_t p = s + nfull * tw.chunk;
+  if (p < e) tw.items[tw.prefix[tw.ntiles] + tw.pprefix[t]] = make_int4((int)p, (int)e, t, 0);
 }
 
 // second half of the unfused particle step: deposit from the saved x^n to x^{n+1}
@@ -197,19 +295,27 @@ void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P,
 }
 
 template <typename T>
-void launch_push_deposit_tiled(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, int n_slots,
-                               int push, hipStream_t s) {
+void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+                               const TileWork &tw, int n_slots, int push, hipStream_t s) {
   if (n_slots <= 0) return;
-  const int ppt = g.dim == 2 ? TileCfg<2>::PPT : TileCfg<3>::PPT;
-  dim3 blk(TPB), grd((n_slots + TPB * ppt - 1) / (TPB * ppt));
-#define PMLPIC_TILED(DIMV, ORD) \
-  hipLaunchKernelGGL((k_push_deposit_tiled<T, DIMV, ORD, TileCfg<DIMV>::PPT>), grd, blk, 0, s, g, F, P, ctl, n_slots, push)
+  // by tile, an upper bound of the item count (every tile's last chunk may be partial)
+  const long nb = (tw.by_tile ? (long)tw.ntiles : 0L) + ((long)n_slots + tw.chunk - 1) / tw.chunk;
+  dim3 blk(TPB), grd((unsigned)nb);
+#define PMLPIC_TILES(DIMV, ORD)                                                                                \
+  do {                                                                                                         \
+    if (tw.by_tile)                                                                                            \
+      hipLaunchKernelGGL((k_push_deposit_tiles<T, DIMV, ORD, TileCfg<DIMV>::PPT, true>), grd, blk, 0, s, g, F, \
+                         P, ctl, tw, push);                                                                    \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_push_deposit_tiles<T, DIMV, ORD, TileCfg<DIMV>::PPT, false>), grd, blk, 0, s, g,   \
+                         F, P, ctl, tw, push);                                                                 \
+  } while (0)
   if (g.dim == 2) {
-    if (g.order == 1) PMLPIC_TILED(2, 1); else if (g.order == 2) PMLPIC_TILED(2, 2); else PMLPIC_TILED(2, 3);
+    if (g.order == 1) PMLPIC_TILES(2, 1); else if (g.order == 2) PMLPIC_TILES(2, 2); else PMLPIC_TILES(2, 3);
   } else {
-    if (g.order == 1) PMLPIC_TILED(3, 1); else if (g.order == 2) PMLPIC_TILED(3, 2); else PMLPIC_TILED(3, 3);
+    if (g.order == 1) PMLPIC_TILES(3, 1); else if (g.order == 2) PMLPIC_TILES(3, 2); else PMLPIC_TILES(3, 3);
   }
-#undef PMLPIC_TILED
+#undef PMLPIC_TILES
 }
 
 template <typename T>
@@ -424,14 +530,32 @@ void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, Sor
   hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, new_count, ctl.count);
 }
 
+int tiled_chunk(int dim) { return TPB * (dim == 2 ? TileCfg<2>::PPT : TileCfg<3>::PPT); }
+int tiled_nodes(int dim) { return dim == 2 ? TileCfg<2>::NODES : TileCfg<3>::NODES; }
+
+void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_chunks, dim3((tw.ntiles + 255) / 256), dim3(256), 0, s, tw, count);
+  const int nb = (tw.ntiles + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.prefix, tw.ntiles, tw.blocksums);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, tw.blocksums, nb,
+                     (int32_t *)(tw.prefix + tw.ntiles));
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.prefix, tw.ntiles, tw.blocksums);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.pprefix, tw.ntiles, tw.blocksums);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, tw.blocksums, nb,
+                     (int32_t *)(tw.pprefix + tw.ntiles));
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.pprefix, tw.ntiles, tw.blocksums);
+  hipLaunchKernelGGL(k_tile_items, dim3((tw.ntiles + 255) / 256), dim3(256), 0, s, tw, count);
+}
+
+template void launch_push_deposit_tiles<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
+                                               StepCtl, const TileWork &, int, int, hipStream_t);
+template void launch_push_deposit_tiles<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
+                                                StepCtl, const TileWork &, int, int, hipStream_t);
+
 template void launch_gather_push<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
                                         Parts<float>, StepCtl, int, int, bool, hipStream_t);
 template void launch_gather_push<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
                                          Parts<double>, StepCtl, int, int, bool, hipStream_t);
-template void launch_push_deposit_tiled<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
-                                               StepCtl, int, int, hipStream_t);
-template void launch_push_deposit_tiled<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
-                                                StepCtl, int, int, hipStream_t);
 template void launch_deposit<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
                                     Parts<float>, StepCtl, int, hipStream_t);
 template void launch_deposit<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,

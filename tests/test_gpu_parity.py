@@ -263,3 +263,31 @@ def test_dense_clusters_lds_path(dim, order, precision):
     else:
         compare_fields(g, o, cfg64, 1e-5, "dense fp32", l2=True)
         compare_particles(g, o, 1e-4, 1e-4, "dense fp32")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_chunks_drifting_far_from_their_sort_tile(dim):
+    """Fast particles in random directions and a long sort interval: a chunk's cells
+    spread beyond what its LDS box can hold, so the box is clipped to the tile and the
+    particles outside it deposit to global memory."""
+    if dim == 2:
+        cfg = W.SimConfig(dim=2, n=(96, 80, 1), pml=((8, 8), (8, 8), (0, 0)), dt=0.7, shape_order=2,
+                          alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.cubic_profile(3.2), push=1, precision=64,
+                          tile=(16, 16, 1), sort_interval=40)
+        steps = 26
+    else:
+        cfg = W.SimConfig(dim=3, n=(30, 28, 26), pml=((4, 4), (4, 4), (4, 4)), dt=0.5, shape_order=1,
+                          alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.cubic_profile(3.2), push=1, precision=64,
+                          tile=(8, 8, 8), sort_interval=40)
+        steps = 14
+    rng = np.random.default_rng(300 + dim)
+    n = 4000
+    x = rng.uniform(0.2, 0.8, (n, dim)) * np.array([cfg.n[d] * cfg.dx[d] for d in range(dim)])
+    u = rng.normal(0.0, 1.0, (n, 3))
+    u *= (4.0 / np.linalg.norm(u, axis=1))[:, None]
+    parts = W.Particles(x=x, u=u, w=rng.uniform(0.5, 1.5, n))
+    g, o = both(cfg, parts)
+    g.step(steps)
+    o.step(steps)
+    compare_fields(g, o, cfg, 1e-9, "drifting chunks")
+    compare_particles(g, o, 1e-9, 1e-9, "drifting chunks")
