@@ -45,6 +45,10 @@ def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
         return cells * (3 + 3 + 3 + 3) * esz + pml * 2 * nsplit_e * esz     # E r+w, B r, J r
     if phase == "update_yee_pml_B":
         return cells * (3 + 3 + 3) * esz + pml * 2 * nsplit_e * esz         # B r+w, E r
+    if phase == "update_yee_pml":   # one pass: E, B r+w, J r; split parts of E and B r+w
+        return cells * (6 + 6 + 3) * esz + pml * 4 * nsplit_e * esz
+    if phase == "clear_current":
+        return cells * 3 * esz
     return None
 
 

@@ -57,8 +57,11 @@ enum {
     PML_PIC_FLAG_UNFUSED = 1,      /* gather_push and deposit_current as separate launches */
     PML_PIC_FLAG_NO_SORT = 2,      /* never sort; deposit with global atomics only */
     PML_PIC_FLAG_SEPARATE_DAMP = 4,/* damp_pml_current as its own pass over the PML */
-    PML_PIC_FLAG_KEEP_CURRENT = 8  /* keep J after the step (for pml_pic_get_current); by
+    PML_PIC_FLAG_KEEP_CURRENT = 8, /* keep J after the step (for pml_pic_get_current); by
                                       default the E update consumes J and zeroes it */
+    PML_PIC_FLAG_SEPARATE_FIELDS = 16 /* update_yee_pml as three sweeps (B half, E, B half);
+                                      by default 2D runs make one pass over the fields,
+                                      which keeps J after the step */
 };
 
 typedef struct {
@@ -128,6 +131,7 @@ enum {
     PML_PIC_PHASE_DAMP = 4,        /* damp_pml_current when SEPARATE_DAMP */
     PML_PIC_PHASE_UPDATE_B = 5,    /* update_yee_pml, the two B half steps */
     PML_PIC_PHASE_UPDATE_E = 6,    /* update_yee_pml, the E step (with alpha J) */
+    PML_PIC_PHASE_UPDATE_FIELDS = 7, /* update_yee_pml in one pass (2D default) */
     PML_PIC_NUM_PHASES = 8
 };
 
@@ -156,8 +160,8 @@ int pml_pic_get_fields(pml_pic_handle *h, double *host, int64_t count);
 int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count);
 
 /* The current J_x J_y J_z (3 x n_samples doubles) deposited and damped by the last
- * step, at E's sample positions; needs PML_PIC_FLAG_KEEP_CURRENT (without it the
- * arrays are zero after every step).  Synchronises. */
+ * step, at E's sample positions; needs PML_PIC_FLAG_KEEP_CURRENT or the one-pass 2D
+ * field update (otherwise the arrays are zero after every step).  Synchronises. */
 int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count);
 
 /* Static partner charge density at the nodes (n_samples doubles). */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpmlpic.so")
 PML_PIC_OK = 0
 STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_CFL", -3: "E_WORKSPACE", -4: "E_HIP",
           -5: "E_NONFINITE", -6: "E_CAPACITY"}
-FLAG_UNFUSED, FLAG_NO_SORT, FLAG_SEPARATE_DAMP, FLAG_KEEP_CURRENT = 1, 2, 4, 8
+FLAG_UNFUSED, FLAG_NO_SORT, FLAG_SEPARATE_DAMP, FLAG_KEEP_CURRENT, FLAG_SEPARATE_FIELDS = 1, 2, 4, 8, 16
 
 EXPORTED = [
     "pml_pic_workspace_size", "pml_pic_create", "pml_pic_add_particles", "pml_pic_step",
@@ -32,7 +32,7 @@ EXPORTED = [
     "pml_pic_backward",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
-          "update_yee_pml_B", "update_yee_pml_E", "unused"]
+          "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml"]
 
 
 class Params(C.Structure):

@@ -26,6 +26,8 @@ struct Layout {
   size_t esz = 4;
   int64_t cap = 0;
   size_t off_field[15] = {};   // E0-2, B0-2, Ea0-2, Ba0-2, J0-2
+  size_t off_alt[12] = {};     // second set of E, B, Ea, Ba for the out-of-place 2D update
+  bool has_alt = false;
   size_t off_tab = 0;
   size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_id[2] = {};
   size_t off_oldcell = 0, off_oldf[3] = {};
@@ -151,6 +153,10 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   for (int a = 0; a < 15; ++a) L.off_field[a] = take(L.esz * (size_t)L.nelem);
+  // the one-pass 2D field update reads one set of arrays and writes the other
+  L.has_alt = p.dim == 2 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS);
+  if (L.has_alt)
+    for (int a = 0; a < 12; ++a) L.off_alt[a] = take(L.esz * (size_t)L.nelem);
   L.off_tab = take(L.esz * 3 * T_NKIND * (size_t)L.ntab);
   const size_t cap = (size_t)std::max<int64_t>(L.cap, 1);
   for (int b = 0; b < 2; ++b) {
@@ -206,6 +212,7 @@ struct pml_pic_handle {
   hipStream_t stream = nullptr;
   std::string err;
   int cur = 0;               // active particle buffer
+  int fset = 0;              // active set of field arrays
   int64_t n_slots = 0;       // upper bound of used particle slots
   int64_t n_added = 0;
   int64_t step = 0;
@@ -243,17 +250,21 @@ struct pml_pic_handle {
     g.ntab = L.ntab;
     return g;
   }
-  template <typename T> Fields<T> fields() const {
+  // offset of field array idx (0..11: E, B, Ea, Ba) of set `set`
+  size_t foff_set(int set, int idx) const { return (set && L.has_alt) ? L.off_alt[idx] : L.off_field[idx]; }
+  size_t foff(int idx) const { return foff_set(fset, idx); }
+  template <typename T> Fields<T> fields_set(int set) const {
     Fields<T> F;
     for (int a = 0; a < 3; ++a) {
-      F.E[a] = at<T>(L.off_field[a]);
-      F.B[a] = at<T>(L.off_field[3 + a]);
-      F.Ea[a] = at<T>(L.off_field[6 + a]);
-      F.Ba[a] = at<T>(L.off_field[9 + a]);
+      F.E[a] = at<T>(foff_set(set, a));
+      F.B[a] = at<T>(foff_set(set, 3 + a));
+      F.Ea[a] = at<T>(foff_set(set, 6 + a));
+      F.Ba[a] = at<T>(foff_set(set, 9 + a));
       F.J[a] = at<T>(L.off_field[12 + a]);
     }
     return F;
   }
+  template <typename T> Fields<T> fields() const { return fields_set<T>(fset); }
   template <typename T> Parts<T> parts(int b) const {
     Parts<T> P;
     P.cell = at<uint32_t>(L.off_cell[b]);
@@ -405,10 +416,10 @@ int get_fields_t(pml_pic_handle *h, double *out) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int c = 0; c < 6; ++c) {
     const int a = c % 3;
-    HIPCHK(h, hipMemcpy(tot.data(), h->at<T>(L.off_field[c < 3 ? a : 3 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(tot.data(), h->at<T>(h->foff(c < 3 ? a : 3 + a)), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
     const int up = unsplit_part(h->p, c);
     if (up < 0)
-      HIPCHK(h, hipMemcpy(aux.data(), h->at<T>(L.off_field[c < 3 ? 6 + a : 9 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
+      HIPCHK(h, hipMemcpy(aux.data(), h->at<T>(h->foff(c < 3 ? 6 + a : 9 + a)), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
     double *p0 = out + (size_t)(2 * c) * ns, *p1 = out + (size_t)(2 * c + 1) * ns;
     for (int k = 0; k < L.nn[2]; ++k)
       for (int j = 0; j < L.nn[1]; ++j)
@@ -447,9 +458,9 @@ int set_fields_t(pml_pic_handle *h, const double *in) {
           tot[q] = (T)(p0[o] + p1[o]);
           if (up < 0 && split_active(h, c, id)) aux[q] = (T)p0[o];
         }
-    HIPCHK(h, hipMemcpy(h->at<T>(L.off_field[c < 3 ? a : 3 + a]), tot.data(), sizeof(T) * L.nelem, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->at<T>(h->foff(c < 3 ? a : 3 + a)), tot.data(), sizeof(T) * L.nelem, hipMemcpyHostToDevice));
     if (up < 0)
-      HIPCHK(h, hipMemcpy(h->at<T>(L.off_field[c < 3 ? 6 + a : 9 + a]), aux.data(), sizeof(T) * L.nelem, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(h->at<T>(h->foff(c < 3 ? 6 + a : 9 + a)), aux.data(), sizeof(T) * L.nelem, hipMemcpyHostToDevice));
   }
   return PML_PIC_OK;
 }
@@ -573,17 +584,18 @@ struct PhaseTimer {
 template <typename T>
 int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const Grid<T> g = h->grid<T>();
-  const Fields<T> F = h->fields<T>();
   const StepCtl ctl = h->ctl();
   const int fl = h->p.flags;
   const bool use_sort = !(fl & PML_PIC_FLAG_NO_SORT);
   const bool fused = !(fl & PML_PIC_FLAG_UNFUSED);
   const bool sep_damp = (fl & PML_PIC_FLAG_SEPARATE_DAMP) != 0;
-  const bool keep_j = (fl & PML_PIC_FLAG_KEEP_CURRENT) != 0;
+  const bool one_pass = h->L.has_alt;
+  const bool keep_j = (fl & PML_PIC_FLAG_KEEP_CURRENT) != 0 || one_pass;
   const int ns = (int)h->n_slots;
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
   for (int it = 0; it < nsteps; ++it) {
+    const Fields<T> F = h->fields<T>();
     if (it < (int)h->snap_state.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_state[it], F.E[0], h->L.fields_bytes, hipMemcpyDeviceToDevice, s));
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
@@ -595,9 +607,9 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       h->since_sort = 0;
       h->sort_pending = false;
     }
-    if (keep_j) {   // J survives the step for inspection; clear it before depositing
+    if (keep_j) {   // J survives the step; clear it before depositing (the three arrays are adjacent)
       pt.begin(s);
-      for (int a = 0; a < 3; ++a) HIPCHK(h, hipMemsetAsync(F.J[a], 0, jbytes, s));
+      HIPCHK(h, hipMemsetAsync(F.J[0], 0, 3 * jbytes, s));
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
     }
     const Parts<T> P = h->parts<T>(h->cur);
@@ -617,15 +629,22 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       launch_damp_current<T>(g, F, s);
       pt.end(s, PML_PIC_PHASE_DAMP);
     }
-    pt.begin(s);
-    launch_update_B<T>(g, F, true, s);
-    pt.end(s, PML_PIC_PHASE_UPDATE_B);
-    pt.begin(s);
-    launch_update_E<T>(g, F, !sep_damp, h->p.alpha_mode, !keep_j, s);
-    pt.end(s, PML_PIC_PHASE_UPDATE_E);
-    pt.begin(s);
-    launch_update_B<T>(g, F, true, s);
-    pt.end(s, PML_PIC_PHASE_UPDATE_B);
+    if (one_pass) {
+      pt.begin(s);
+      launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), !sep_damp && h->p.alpha_mode != PML_ALPHA_ONE, s);
+      pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
+      h->fset = 1 - h->fset;
+    } else {
+      pt.begin(s);
+      launch_update_B<T>(g, F, true, s);
+      pt.end(s, PML_PIC_PHASE_UPDATE_B);
+      pt.begin(s);
+      launch_update_E<T>(g, F, !sep_damp, h->p.alpha_mode, !keep_j, s);
+      pt.end(s, PML_PIC_PHASE_UPDATE_E);
+      pt.begin(s);
+      launch_update_B<T>(g, F, true, s);
+      pt.end(s, PML_PIC_PHASE_UPDATE_B);
+    }
     h->step++;
     h->since_sort++;
   }
@@ -769,6 +788,14 @@ size_t batch_items(const std::vector<Layout> &Ls, int dim, int bdx) {
   return n;
 }
 
+// a batched run: particles deposit with global atomics, fields advance in place
+pml_pic_params batch_run_params(const pml_pic_params &p) {
+  pml_pic_params pr = p;
+  pr.flags |= PML_PIC_FLAG_NO_SORT | PML_PIC_FLAG_SEPARATE_FIELDS;
+  pr.flags &= ~(PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_SEPARATE_DAMP | PML_PIC_FLAG_KEEP_CURRENT);
+  return pr;
+}
+
 int batch_layout(const pml_pic_params *runs, int32_t n, std::vector<Layout> &Ls, std::vector<size_t> &offs,
                  size_t &off_desc, size_t &off_items, size_t &max_items, size_t &total, std::string *err) {
   if (!runs || n < 1) return fail(err, PML_PIC_E_INVALID_ARG, "need at least one run");
@@ -782,7 +809,7 @@ int batch_layout(const pml_pic_params *runs, int32_t n, std::vector<Layout> &Ls,
     if (runs[r].dim != runs[0].dim || runs[r].shape_order != runs[0].shape_order ||
         runs[r].precision != runs[0].precision)
       return fail(err, PML_PIC_E_INVALID_ARG, "all runs of a batch need the same dim, shape_order and precision");
-    make_layout(runs[r], Ls[r]);
+    make_layout(batch_run_params(runs[r]), Ls[r]);
   }
   max_items = 0;
   for (int k = 0; k < 4; ++k) max_items = std::max(max_items, batch_items(Ls, runs[0].dim, BATCH_BDX[k]));
@@ -927,9 +954,7 @@ int pml_pic_batch_create(const pml_pic_params *runs, int32_t n_runs, void *devic
   b->max_items = mi;
   b->use_graph = use_graph != 0;
   for (int r = 0; r < n_runs; ++r) {
-    pml_pic_params pr = runs[r];
-    pr.flags |= PML_PIC_FLAG_NO_SORT;     // batched particles deposit with global atomics
-    pr.flags &= ~(PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_SEPARATE_DAMP | PML_PIC_FLAG_KEEP_CURRENT);
+    pml_pic_params pr = batch_run_params(runs[r]);
     pml_pic_handle *h = nullptr;
     rc = create_handle(&pr, b->ws + offs[r], Ls[r].total, stream, &h, &g_create_error);
     if (rc) {
@@ -1223,7 +1248,7 @@ int save_ckpt(pml_pic_handle *h, int c) {
   const Layout &L = h->L;
   char *dst = ckpt_ptr(h, c);
   hipStream_t s = h->stream;
-  HIPCHK(h, hipMemcpyAsync(dst, h->ws + L.off_field[0], L.fields_bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(dst, h->ws + h->foff(0), L.fields_bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(dst + L.fields_bytes, h->ws + L.off_cell[h->cur], L.parts_bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(dst + L.fields_bytes + L.parts_bytes, h->ws + L.off_count, 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(dst + L.fields_bytes + L.parts_bytes + 256, h->ws + L.off_pushes, 8 * N_PUSH_COUNTERS,
@@ -1241,7 +1266,7 @@ int restore_ckpt(pml_pic_handle *h, int c) {
   h->since_sort = m.since_sort; h->sort_pending = true;
   const char *src = ckpt_ptr(h, c);
   hipStream_t s = h->stream;
-  HIPCHK(h, hipMemcpyAsync(h->ws + L.off_field[0], src, L.fields_bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->ws + h->foff(0), src, L.fields_bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->ws + L.off_cell[h->cur], src + L.fields_bytes, L.parts_bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->ws + L.off_count, src + L.fields_bytes + L.parts_bytes, 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->ws + L.off_pushes, src + L.fields_bytes + L.parts_bytes + 256, 8 * N_PUSH_COUNTERS,
@@ -1391,7 +1416,7 @@ int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double
     h->snap_state.clear();
     h->snap_J.clear();
     if (rc) return rc;
-    HIPCHK(h, hipMemcpyAsync(seg_state + (size_t)len * L.fields_bytes, h->ws + L.off_field[0], L.fields_bytes,
+    HIPCHK(h, hipMemcpyAsync(seg_state + (size_t)len * L.fields_bytes, h->ws + h->foff(0), L.fields_bytes,
                              hipMemcpyDeviceToDevice, s));
     for (int k = len - 1; k >= 0; --k) {
       const Fields<T> Fn = fields_at<T>(h, seg_state + (size_t)k * L.fields_bytes);

@@ -194,6 +194,11 @@ void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int
 
 // adjoint of the fields: LT[c] (part driven along a+2, or the whole component where it
 // is not split), LA[c] (part driven along a+1 minus LT), c = E_x .. B_z
+// update_yee_pml in one pass over the fields (2D): reads F (and its J, not cleared),
+// writes the new E, B (and split parts) to D
+template <typename T>
+void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, bool fuse_alpha, hipStream_t s);
+
 template <typename T>
 struct AdjFields {
   T *LT[6];

@@ -13,9 +13,23 @@
 // per-axis tables (Berenger's exponential differencing).
 //
 // Memory-bound stencils: one thread per node, x fastest, coalesced rows.
+#include <algorithm>
+
 #include "field_core.h"
+#include "fused2d.h"
 
 namespace pmlpic {
+
+// one-pass update_yee_pml in 2D: one wavefront per (strip of FW columns, segment of rows)
+template <typename T>
+__global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields<T> D, int nstrips, int rows,
+                                                  int nseg, bool fuse_alpha) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nstrips * nseg) return;   // whole wavefront
+  const int strip = w % nstrips, seg = w / nstrips;
+  const int y0 = seg * rows, y1 = min(y0 + rows, g.M[1] + 1);
+  fused_segment_2d(g, F, D, strip, y0, y1, fuse_alpha, (int)(threadIdx.x & 63));
+}
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
@@ -65,6 +79,27 @@ static dim3 node_grid(const Grid<T> &g, dim3 &blk) {
   blk = dim3(64, 4, 1);
   return dim3((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, g.dim == 3 ? g.M[2] + 1 : 1);
 }
+
+// rows per segment: enough wavefronts to fill the GPU (about 4096), 8 to 64 rows
+void fused_2d_shape(int M0, int M1, int &nstrips, int &rows, int &nseg) {
+  nstrips = (M0 + 1 + FW - 1) / FW;
+  const long want = 4096;
+  rows = (int)std::min<long>(64, std::max<long>(8, (long)nstrips * (M1 + 1) / want));
+  nseg = (M1 + 1 + rows - 1) / rows;
+}
+
+template <typename T>
+void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, bool fuse_alpha, hipStream_t s) {
+  int nstrips, rows, nseg;
+  fused_2d_shape(g.M[0], g.M[1], nstrips, rows, nseg);
+  const int waves = nstrips * nseg;
+  hipLaunchKernelGGL((k_fused_2d<T>), dim3((waves + 3) / 4), dim3(256), 0, s, g, F, D, nstrips, rows, nseg,
+                     fuse_alpha);
+}
+template void launch_fused_fields<float>(const Grid<float> &, const Fields<float> &, const Fields<float> &, bool,
+                                         hipStream_t);
+template void launch_fused_fields<double>(const Grid<double> &, const Fields<double> &, const Fields<double> &, bool,
+                                          hipStream_t);
 
 // B is only ever advanced by half steps (B^n -> B^{n+1/2} -> B^{n+1})
 template <typename T>
