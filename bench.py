@@ -107,8 +107,8 @@ def run_batch(args):
     dom = max(phases.items(), key=lambda kv: kv[1][0])
     name, (ms_total, launches) = dom
     avg_s = ms_total / 1e3 / launches
-    pml = sum(c.pml_cells() for c in cfgs)
-    per = {"update_yee_pml_B": cells * 9 * 4 + pml * 2 * 4, "update_yee_pml_E": cells * 12 * 4 + pml * 2 * 4}
+    per = {k: sum(algorithmic_bytes(c, k, 0, 4) for c in cfgs)
+           for k in ("update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "clear_current")}
     roof = None
     if name in per:
         ach = per[name] / avg_s / 1e9

@@ -230,9 +230,10 @@ int pml_pic_batch_create(const pml_pic_params *runs, int32_t n_runs, void *devic
  * diagnose, get/set fields; pml_pic_step on it advances that run alone. */
 pml_pic_handle *pml_pic_batch_run(pml_pic_batch *b, int32_t run);
 
-/* Launch shape of the batched field kernels: 256-thread blocks of block_x x
- * (256/block_x) nodes (block_x in 32, 64, 128, 256) and grid_blocks persistent
- * workgroups (0 = 8 per compute unit).  Drops the captured graph. */
+/* Launch shape of the batched field kernels, block_x in 32, 64, 128, 256: in 2D the
+ * rows per wavefront segment of the one-pass field update (each wavefront owns 61
+ * columns), in 3D blocks of block_x x (256/block_x) nodes; grid_blocks persistent
+ * 256-thread workgroups (0 = 8 per compute unit).  Drops the captured graphs. */
 int pml_pic_batch_set_launch(pml_pic_batch *b, int32_t block_x, int32_t grid_blocks);
 
 /* Advances every run by n_steps, asynchronously on the batch's stream. */

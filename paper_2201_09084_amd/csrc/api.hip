@@ -34,7 +34,7 @@ struct Layout {
   size_t off_count = 0, off_pushes = 0;
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
   int ntiles = 1;
-  size_t off_items = 0, max_items = 0;
+  size_t off_items = 0, max_items = 0, off_jbox = 0, off_jblk = 0, max_push_blocks = 0;
   size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
   int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
   // adjoint storage (present when adjoint_segment > 0)
@@ -185,6 +185,10 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_partial = take(8 * (4 * (size_t)L.diag_blocks + 1024));
   L.off_result = take(8 * 8);
   L.off_flags = take(4 * 4);
+  L.off_jbox = take(4 * 8);   // two boxes of nodes with current, by step parity
+  // per-workgroup boxes of the 2D deposit launches (the most workgroups of any of them)
+  L.max_push_blocks = std::max<size_t>(L.max_items, (cap + 255) / 256) + 1;
+  L.off_jblk = take(16 * L.max_push_blocks);
   if (p.adjoint_segment > 0) {
     const size_t fb = L.esz * (size_t)L.nelem;          // one field array (multiple of 256 bytes)
     L.seg = p.adjoint_segment;
@@ -286,6 +290,7 @@ struct pml_pic_handle {
     StepCtl c;
     c.count = at<int32_t>(L.off_count);
     c.pushes = at<unsigned long long>(L.off_pushes);
+    c.jblk = nullptr;
     return c;
   }
   SortWork sortwork() const {
@@ -584,7 +589,6 @@ struct PhaseTimer {
 template <typename T>
 int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const Grid<T> g = h->grid<T>();
-  const StepCtl ctl = h->ctl();
   const int fl = h->p.flags;
   const bool use_sort = !(fl & PML_PIC_FLAG_NO_SORT);
   const bool fused = !(fl & PML_PIC_FLAG_UNFUSED);
@@ -594,8 +598,12 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const int ns = (int)h->n_slots;
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
+  int *jbox = h->at<int>(h->L.off_jbox);
   for (int it = 0; it < nsteps; ++it) {
     const Fields<T> F = h->fields<T>();
+    StepCtl ctl = h->ctl();
+    int *box_cur = jbox + 4 * h->fset;            // this step's box; the other holds the last step's
+    if (one_pass) ctl.jblk = h->at<int4>(h->L.off_jblk);
     if (it < (int)h->snap_state.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_state[it], F.E[0], h->L.fields_bytes, hipMemcpyDeviceToDevice, s));
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
@@ -607,7 +615,11 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       h->since_sort = 0;
       h->sort_pending = false;
     }
-    if (keep_j) {   // J survives the step; clear it before depositing (the three arrays are adjacent)
+    if (one_pass) {   // J survives the step; clear the last step's box before depositing
+      pt.begin(s);
+      launch_jbox_clear<T>(g, F, jbox + 4 * (1 - h->fset), s);
+      pt.end(s, PML_PIC_PHASE_CLEAR_J);
+    } else if (keep_j) {   // J survives the step; clear it before depositing (the three arrays are adjacent)
       pt.begin(s);
       HIPCHK(h, hipMemsetAsync(F.J[0], 0, 3 * jbytes, s));
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
@@ -622,6 +634,11 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, s);
       pt.end(s, PML_PIC_PHASE_DEPOSIT);
     }
+    if (one_pass) {   // union of the deposit workgroups' boxes (also with no particles: empty)
+      pt.begin(s);
+      launch_jbox_reduce(ctl.jblk, deposit_blocks<T>(g, h->tilework(), ns, fused && use_sort), box_cur, s);
+      pt.end(s, PML_PIC_PHASE_CLEAR_J);
+    }
     if (it < (int)h->snap_J.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_J[it], F.J[0], h->L.J_bytes, hipMemcpyDeviceToDevice, s));
     if (sep_damp && h->p.alpha_mode != PML_ALPHA_ONE) {
@@ -631,7 +648,8 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (one_pass) {
       pt.begin(s);
-      launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), !sep_damp && h->p.alpha_mode != PML_ALPHA_ONE, s);
+      launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), box_cur,
+                             !sep_damp && h->p.alpha_mode != PML_ALPHA_ONE, s);
       pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
       h->fset = 1 - h->fset;
     } else {
@@ -771,27 +789,38 @@ struct pml_pic_batch {
   int dim = 2, order = 1, prec = 32;
   size_t off_desc = 0, off_items = 0, max_items = 0;
   int n_items = 0, bdx = 64, grid_blocks = 0;
+  int parity = 0;               // 2D: field set holding the current state
   bool use_graph = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};        // one step from each field set
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 namespace {
 
 const int BATCH_BDX[4] = {32, 64, 128, 256};
 
+// Work items of a batched step.  2D: (run, strip of FW columns, first row, end row)
+// for the one-pass field update, `bdx` rows per segment.  3D: (run, bx, by, z) blocks
+// of bdx x (256 / bdx) nodes for the in-place sweeps.
 size_t batch_items(const std::vector<Layout> &Ls, int dim, int bdx) {
-  const int bdy = 256 / bdx;
   size_t n = 0;
+  if (dim == 2) {
+    for (const Layout &L : Ls) n += (size_t)((L.M[0] + FW) / FW) * ((L.M[1] + bdx) / bdx);
+    return n;
+  }
+  const int bdy = 256 / bdx;
   for (const Layout &L : Ls)
-    n += (size_t)((L.M[0] + bdx) / bdx) * ((L.M[1] + bdy) / bdy) * (dim == 3 ? L.M[2] + 1 : 1);
+    n += (size_t)((L.M[0] + bdx) / bdx) * ((L.M[1] + bdy) / bdy) * (L.M[2] + 1);
   return n;
 }
 
-// a batched run: particles deposit with global atomics, fields advance in place
+// a batched run: particles deposit with global atomics; in 3D the fields advance in
+// place, in 2D out of place between two sets
 pml_pic_params batch_run_params(const pml_pic_params &p) {
   pml_pic_params pr = p;
-  pr.flags |= PML_PIC_FLAG_NO_SORT | PML_PIC_FLAG_SEPARATE_FIELDS;
+  pr.flags |= PML_PIC_FLAG_NO_SORT;
+  if (p.dim == 3) pr.flags |= PML_PIC_FLAG_SEPARATE_FIELDS;
+  else pr.flags &= ~PML_PIC_FLAG_SEPARATE_FIELDS;
   pr.flags &= ~(PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_SEPARATE_DAMP | PML_PIC_FLAG_KEEP_CURRENT);
   return pr;
 }
@@ -832,7 +861,10 @@ int batch_upload_descs(pml_pic_batch *b) {
   for (size_t r = 0; r < b->runs.size(); ++r) {
     pml_pic_handle *h = b->runs[r];
     d[r].g = h->grid<T>();
-    d[r].F = h->fields<T>();
+    d[r].F = h->fields_set<T>(0);
+    d[r].F2 = h->fields_set<T>(1);
+    d[r].jbox = h->at<int>(h->L.off_jbox);
+    d[r].pad2[0] = d[r].pad2[1] = 0;
     d[r].P = h->parts<T>(h->cur);
     d[r].ctl = h->ctl();
     d[r].n_slots = (int)h->n_slots;
@@ -852,7 +884,13 @@ int batch_build_items(pml_pic_batch *b, int bdx) {
   it.reserve(b->max_items);
   for (size_t r = 0; r < b->runs.size(); ++r) {
     const Layout &L = b->runs[r]->L;
-    const int nbx = (L.M[0] + bdx) / bdx, nby = (L.M[1] + bdy) / bdy, nbz = b->dim == 3 ? L.M[2] + 1 : 1;
+    if (b->dim == 2) {
+      const int ns = (L.M[0] + FW) / FW;
+      for (int y0 = 0; y0 <= L.M[1]; y0 += bdx)
+        for (int st = 0; st < ns; ++st) it.push_back(make_int4((int)r, st, y0, std::min(y0 + bdx, L.M[1] + 1)));
+      continue;
+    }
+    const int nbx = (L.M[0] + bdx) / bdx, nby = (L.M[1] + bdy) / bdy, nbz = L.M[2] + 1;
     for (int bz = 0; bz < nbz; ++bz)
       for (int by = 0; by < nby; ++by)
         for (int bx = 0; bx < nbx; ++bx) it.push_back(make_int4((int)r, bx, by, bz));
@@ -866,22 +904,41 @@ int batch_build_items(pml_pic_batch *b, int bdx) {
 }
 
 void batch_drop_graph(pml_pic_batch *b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    b->exec[k] = nullptr;
+    b->graph[k] = nullptr;
+  }
 }
 
-// particles, B half step, E step, B half step (the order of the single-run step)
+// One step of every run, the order of the single-run step.  2D: J cleared over the
+// previous step's box, particles, one-pass fields from set `parity` to the other.  3D: particles, B half step, E
+// step (consuming J), B half step, in place.
 template <typename T>
-void batch_launch(pml_pic_batch *b, PhaseTimer *pt = nullptr) {
+void batch_launch(pml_pic_batch *b, int parity, PhaseTimer *pt = nullptr) {
+  const RunDesc<T> *runs = (const RunDesc<T> *)(b->ws + b->off_desc);
+  const int4 *items = (const int4 *)(b->ws + b->off_items);
+  if (b->dim == 2) {
+    if (pt) pt->begin(b->stream);
+    launch_batch_clear_j<T>(runs, (int)b->runs.size(), parity, b->stream);
+    if (pt) pt->end(b->stream, PML_PIC_PHASE_CLEAR_J);
+    if (pt) pt->begin(b->stream);
+    launch_batch_phase<T>(0, b->dim, b->order, runs, (int)b->runs.size(), items, b->n_items, b->bdx, b->grid_blocks,
+                          parity, b->stream);
+    if (pt) pt->end(b->stream, PML_PIC_PHASE_PUSH);
+    if (pt) pt->begin(b->stream);
+    launch_batch_fused<T>(runs, items, b->n_items, parity, b->grid_blocks, b->stream);
+    if (pt) pt->end(b->stream, PML_PIC_PHASE_UPDATE_FIELDS);
+    return;
+  }
   static const int order_of_phases[4] = {0, 1, 2, 1};
   static const int timer_phase[3] = {PML_PIC_PHASE_PUSH, PML_PIC_PHASE_UPDATE_B, PML_PIC_PHASE_UPDATE_E};
   for (int k = 0; k < 4; ++k) {
     const int ph = order_of_phases[k];
     if (pt) pt->begin(b->stream);
-    launch_batch_phase<T>(ph, b->dim, b->order, (const RunDesc<T> *)(b->ws + b->off_desc), (int)b->runs.size(),
-                          (const int4 *)(b->ws + b->off_items), b->n_items, b->bdx, b->grid_blocks, b->stream);
+    launch_batch_phase<T>(ph, b->dim, b->order, runs, (int)b->runs.size(), items, b->n_items, b->bdx,
+                          b->grid_blocks, 0, b->stream);
     if (pt) pt->end(b->stream, timer_phase[ph]);
   }
 }
@@ -894,24 +951,38 @@ int batch_step_t(pml_pic_batch *b, int n, PhaseTimer *pt = nullptr) {
     const int rc = batch_upload_descs<T>(b);
     if (rc) return rc;
   }
+  const int flip = b->dim == 2 ? 1 : 0;   // 2D steps alternate between the field sets
   if (pt) {
-    for (int it = 0; it < n; ++it) batch_launch<T>(b, pt);
+    for (int it = 0; it < n; ++it) {
+      batch_launch<T>(b, b->parity, pt);
+      b->parity ^= flip;
+    }
     HIPCHK(b, hipGetLastError());
   } else if (b->use_graph) {
-    if (!b->exec) {
-      HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      batch_launch<T>(b);
-      hipGraph_t g = nullptr;
-      HIPCHK(b, hipStreamEndCapture(b->stream, &g));
-      b->graph = g;
-      HIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    for (int it = 0; it < n; ++it) {
+      const int k = b->parity;
+      if (!b->exec[k]) {
+        HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        batch_launch<T>(b, k);
+        hipGraph_t g = nullptr;
+        HIPCHK(b, hipStreamEndCapture(b->stream, &g));
+        b->graph[k] = g;
+        HIPCHK(b, hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0));
+      }
+      HIPCHK(b, hipGraphLaunch(b->exec[k], b->stream));
+      b->parity ^= flip;
     }
-    for (int it = 0; it < n; ++it) HIPCHK(b, hipGraphLaunch(b->exec, b->stream));
   } else {
-    for (int it = 0; it < n; ++it) batch_launch<T>(b);
+    for (int it = 0; it < n; ++it) {
+      batch_launch<T>(b, b->parity);
+      b->parity ^= flip;
+    }
     HIPCHK(b, hipGetLastError());
   }
-  for (pml_pic_handle *h : b->runs) h->step += n;
+  for (pml_pic_handle *h : b->runs) {
+    h->step += n;
+    h->fset = b->parity;
+  }
   return PML_PIC_OK;
 }
 

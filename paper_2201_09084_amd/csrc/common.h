@@ -30,6 +30,18 @@ enum TabKind {
   T_NKIND
 };
 
+// The same pointer in the global address space.  Field arrays reached through a
+// descriptor in device memory (batched runs) are otherwise accessed with flat
+// instructions, which also tie up the LDS counters.
+template <typename T>
+__host__ __device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const T *p) {
+  return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__host__ __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 template <typename T>
 struct Grid {
   int dim, order;
@@ -48,7 +60,7 @@ struct Grid {
 
   __host__ __device__ long at(int i, int j, int k) const { return base + i + j * sy + k * sz; }
   __device__ T tb(int axis, int kind, int i) const {
-    return tab[(axis * T_NKIND + kind) * ntab + i + G];
+    return gptr(tab)[(axis * T_NKIND + kind) * ntab + i + G];
   }
 };
 
@@ -130,6 +142,8 @@ constexpr int N_PUSH_COUNTERS = 256;   // push tallies are spread over this many
 struct StepCtl {
   int32_t *count;                 // device: live particle slots in use
   unsigned long long *pushes;     // N_PUSH_COUNTERS partial push counts
+  int4 *jblk;                     // 2D one-pass runs: per workgroup of the deposit, the box of
+                                  // nodes it gave current (x lo, x hi, y lo, y hi); else null
 };
 
 template <typename T>
@@ -194,10 +208,24 @@ void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int
 
 // adjoint of the fields: LT[c] (part driven along a+2, or the whole component where it
 // is not split), LA[c] (part driven along a+1 minus LT), c = E_x .. B_z
+// J <- 0 over the box `prev` (the previous step's deposits)
+template <typename T>
+void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, hipStream_t s);
+// cur <- union of the n per-workgroup boxes
+void launch_jbox_reduce(const int4 *jblk, int n, int *cur, hipStream_t s);
+// workgroups of the deposit launch of a step (entries of the per-workgroup boxes)
+template <typename T>
+int deposit_blocks(const Grid<T> &g, const TileWork &tw, int n_slots, bool tiled);
+
+// output columns per wavefront strip of the one-pass 2D field update (64 lanes less
+// one halo column on the left and two on the right)
+constexpr int FW = 61;
+
 // update_yee_pml in one pass over the fields (2D): reads F (and its J, not cleared),
 // writes the new E, B (and split parts) to D
 template <typename T>
-void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, bool fuse_alpha, hipStream_t s);
+void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jbox, bool fuse_alpha,
+                         hipStream_t s);
 
 template <typename T>
 struct AdjFields {
@@ -216,7 +244,10 @@ void launch_adj_E(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> &Fe, 
 template <typename T>
 struct RunDesc {
   Grid<T> g;
-  Fields<T> F;
+  Fields<T> F;    // field set 0 (and J)
+  Fields<T> F2;   // field set 1 of the out-of-place 2D update (same J)
+  int *jbox;      // 2D: two boxes of nodes with current (by step parity)
+  int pad2[2];
   Parts<T> P;
   StepCtl ctl;
   int n_slots;
@@ -225,9 +256,17 @@ struct RunDesc {
   int pad;
 };
 
+// 2D batches: one-pass field update of every run, reading set `parity` and writing
+// the other (items: run, strip, first row, end row), then J cleared over the same items
+template <typename T>
+void launch_batch_fused(const RunDesc<T> *runs, const int4 *items, int n_items, int parity, int grid_blocks,
+                        hipStream_t s);
+template <typename T>
+void launch_batch_clear_j(const RunDesc<T> *runs, int n_runs, int parity, hipStream_t s);
+
 // one phase of a batched step: 0 particles, 1 B half step, 2 E step
 template <typename T>
 void launch_batch_phase(int phase, int dim, int order, const RunDesc<T> *runs, int n_runs, const int4 *items,
-                        int n_items, int bdx, int grid_blocks, hipStream_t s);
+                        int n_items, int bdx, int grid_blocks, int parity, hipStream_t s);
 
 }  // namespace pmlpic

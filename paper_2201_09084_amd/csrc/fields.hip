@@ -22,14 +22,43 @@ namespace pmlpic {
 
 // one-pass update_yee_pml in 2D: one wavefront per (strip of FW columns, segment of rows)
 template <typename T>
-__global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields<T> D, int nstrips, int rows,
-                                                  int nseg, bool fuse_alpha) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields<T> D, const int *jbox, int nstrips,
+                                                  int rows, int nseg, bool fuse_alpha) {
+  // workgroup b runs on XCD b mod 8: give each XCD a contiguous eighth of the
+  // wavefronts so that neighbouring strips share its L2 (gridDim is a multiple of 8)
+  const int per = (int)(gridDim.x >> 3);
+  const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  const int w = b * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (w >= nstrips * nseg) return;   // whole wavefront
   const int strip = w % nstrips, seg = w / nstrips;
   const int y0 = seg * rows, y1 = min(y0 + rows, g.M[1] + 1);
-  fused_segment_2d(g, F, D, strip, y0, y1, fuse_alpha, (int)(threadIdx.x & 63));
+  fused_segment_2d(g, F, D, jbox, strip, y0, y1, fuse_alpha, (int)(threadIdx.x & 63));
 }
+
+// J <- 0 over the box `prev`
+template <typename T>
+__global__ void __launch_bounds__(256) k_jbox_clear(Grid<T> g, Fields<T> F, const int *prev) {
+  const int x0 = max(prev[0], -G), x1 = min(prev[1], g.M[0] + G);
+  const int y0 = max(prev[2], -G), y1 = min(prev[3], g.M[1] + G);
+  if (x0 > x1 || y0 > y1) return;
+  const int w = x1 - x0 + 1;
+  const long n = (long)w * (y1 - y0 + 1);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const long q = g.at(x0 + (int)(e % w), y0 + (int)(e / w), 0);
+    F.J[0][q] = T(0);
+    F.J[1][q] = T(0);
+    F.J[2][q] = T(0);
+  }
+}
+
+template <typename T>
+void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, hipStream_t s) {
+  const long n = (long)(g.M[0] + 1 + 2 * G) * (g.M[1] + 1 + 2 * G);
+  const int blocks = (int)std::min<long>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL((k_jbox_clear<T>), dim3(blocks), dim3(256), 0, s, g, F, prev);
+}
+template void launch_jbox_clear<float>(const Grid<float> &, const Fields<float> &, const int *, hipStream_t);
+template void launch_jbox_clear<double>(const Grid<double> &, const Fields<double> &, const int *, hipStream_t);
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
@@ -89,17 +118,19 @@ void fused_2d_shape(int M0, int M1, int &nstrips, int &rows, int &nseg) {
 }
 
 template <typename T>
-void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, bool fuse_alpha, hipStream_t s) {
+void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jbox, bool fuse_alpha,
+                         hipStream_t s) {
   int nstrips, rows, nseg;
   fused_2d_shape(g.M[0], g.M[1], nstrips, rows, nseg);
   const int waves = nstrips * nseg;
-  hipLaunchKernelGGL((k_fused_2d<T>), dim3((waves + 3) / 4), dim3(256), 0, s, g, F, D, nstrips, rows, nseg,
+  const int blocks = ((waves + 3) / 4 + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_fused_2d<T>), dim3(blocks), dim3(256), 0, s, g, F, D, jbox, nstrips, rows, nseg,
                      fuse_alpha);
 }
-template void launch_fused_fields<float>(const Grid<float> &, const Fields<float> &, const Fields<float> &, bool,
-                                         hipStream_t);
-template void launch_fused_fields<double>(const Grid<double> &, const Fields<double> &, const Fields<double> &, bool,
-                                          hipStream_t);
+template void launch_fused_fields<float>(const Grid<float> &, const Fields<float> &, const Fields<float> &,
+                                         const int *, bool, hipStream_t);
+template void launch_fused_fields<double>(const Grid<double> &, const Fields<double> &, const Fields<double> &,
+                                          const int *, bool, hipStream_t);
 
 // B is only ever advanced by half steps (B^n -> B^{n+1/2} -> B^{n+1})
 template <typename T>

@@ -11,13 +11,12 @@
 // B^{n+1}(j-1).  Halo work: the lanes 0, 62, 63 and one row before and after the
 // segment, computed and thrown away.  Every owned sample in [0, M] is written (a
 // sample the update leaves alone is copied); split parts wherever the split is active.
-// The current is read, not cleared.
+// The current is read, not cleared, and only inside the box of nodes the deposits of
+// this step touched (it is zero elsewhere).
 #pragma once
 #include "common.h"
 
 namespace pmlpic {
-
-constexpr int FW = 61;   // output columns per wavefront strip
 
 template <typename T>
 struct XTab {            // per-lane tables along x at the lane's column
@@ -98,11 +97,19 @@ __device__ __forceinline__ void estep_2d(ERow<T> &e, const XTab<T> &X, const YTa
   }
 }
 
+// Loads of one row j, issued one row ahead of their use: E_x, E_z at row j+1 and
+// E_y, the split parts, B and J at row j.
+template <typename T>
+struct RowIn {
+  T ex1, ez1, ey, eza, bx, by, bz, bza, jx, jy, jz;
+};
+
 // One wavefront: strip `strip`, output rows [y0, y1).  All 64 lanes run every
 // iteration (the shuffles need them); only the lanes and rows owned are written.
 template <typename T>
-__device__ __forceinline__ void fused_segment_2d(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, int strip,
-                                                 int y0, int y1, bool fuse_alpha, int lane) {
+__device__ __forceinline__ void fused_segment_2d(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D,
+                                                 const int *jbox, int strip, int y0, int y1, bool fuse_alpha,
+                                                 int lane) {
   const int M0 = g.M[0], M1 = g.M[1];
   const int i = strip * FW - 1 + lane;
   const bool colok = i >= -G && i <= M0 + G;
@@ -112,49 +119,74 @@ __device__ __forceinline__ void fused_segment_2d(const Grid<T> &g, const Fields<
   load_tabs(g, 0, ti, X.ehC, X.ghkC, X.sigC, X.eN, X.gN, X.gkN, X.sigN, X.aC, X.aN);
   // update extents along x (0 <= i <= M0 - 1 or M0) per component
   const bool xi0 = i >= 0 && i <= M0, xi1 = i >= 0 && i <= M0 - 1, xe = i >= 1 && i <= M0 - 1;
-  auto ld = [&](const T *a, int j) -> T { return colok ? a[g.at(i, j, 0)] : T(0); };
+  // 32-bit sample offsets from the arrays' (uniform) base pointers
+  const int q0 = (int)(g.base + i), sy = (int)g.sy;
+  auto ld = [&](const T *a, int j) -> T { return colok ? gptr(a)[q0 + j * sy] : T(0); };
   auto bsplit = [&](const YTab<T> &Y) { return X.sigC + Y.sigC > T(0); };
   auto esplit = [&](const YTab<T> &Y) { return X.sigN + Y.sigN > T(0); };
+  auto ytab = [&](int j, YTab<T> &Y) {
+    load_tabs(g, 1, min(max(j, -G), M1 + G), Y.ehC, Y.ghkC, Y.sigC, Y.eN, Y.gN, Y.gkN, Y.sigN, Y.aC, Y.aN);
+  };
+  const int jb0 = __builtin_amdgcn_readfirstlane(jbox[0]), jb1 = __builtin_amdgcn_readfirstlane(jbox[1]);
+  const int jb2 = __builtin_amdgcn_readfirstlane(jbox[2]), jb3 = __builtin_amdgcn_readfirstlane(jbox[3]);
+  const bool jcol = i >= jb0 && i <= jb1;
+  auto fetch = [&](int j, const YTab<T> &Y, RowIn<T> &r) {
+    r.ex1 = ld(F.E[0], j + 1);
+    r.ez1 = ld(F.E[2], j + 1);
+    r.ey = ld(F.E[1], j);
+    r.eza = esplit(Y) ? ld(F.Ea[2], j) : T(0);
+    r.bx = ld(F.B[0], j);
+    r.by = ld(F.B[1], j);
+    r.bz = ld(F.B[2], j);
+    r.bza = bsplit(Y) ? ld(F.Ba[2], j) : T(0);
+    const bool need_j = j >= y0 && jcol && j >= jb2 && j <= jb3;
+    r.jx = need_j ? ld(F.J[0], j) : T(0);
+    r.jy = need_j ? ld(F.J[1], j) : T(0);
+    r.jz = need_j ? ld(F.J[2], j) : T(0);
+  };
 
-  YTab<T> Yp, Yc;   // tables of rows j-1 and j
+  YTab<T> Yp, Yc, Yn;   // tables of rows j-1, j, j+1
   int j = y0 - 1;
-  load_tabs(g, 1, min(max(j, -G), M1 + G), Yc.ehC, Yc.ghkC, Yc.sigC, Yc.eN, Yc.gN, Yc.gkN, Yc.sigN, Yc.aC, Yc.aN);
-  ERow<T> ec;       // E^n at row j
+  ytab(j, Yc);
+  ERow<T> ec;           // E^n at row j
   ec.x = ld(F.E[0], j);
-  ec.y = ld(F.E[1], j);
   ec.z = ld(F.E[2], j);
-  ec.za = esplit(Yc) ? ld(F.Ea[2], j) : T(0);
-  BRow<T> bhp;      // B^{n+1/2} at row j-1
-  ERow<T> enp;      // E^{n+1} at row j-1
+  RowIn<T> cur, nxt;
+  fetch(j, Yc, cur);
+  BRow<T> bhp;          // B^{n+1/2} at row j-1
+  ERow<T> enp;          // E^{n+1} at row j-1
   bhp.x = bhp.y = bhp.z = bhp.za = T(0);
   enp.x = enp.y = enp.z = enp.za = T(0);
   for (; j <= y1; ++j) {
-    // E^n at row j+1 (x and z components are read across rows)
-    const T nx = ld(F.E[0], j + 1), nz = ld(F.E[2], j + 1);
+    // next row's loads go out before this row's arithmetic
+    ytab(j + 1, Yn);
+    if (j < y1) fetch(j + 1, Yn, nxt);
+    ec.y = cur.ey;
+    ec.za = cur.eza;
     // B^{n+1/2}(j)
     BRow<T> bh;
-    bh.x = ld(F.B[0], j);
-    bh.y = ld(F.B[1], j);
-    bh.z = ld(F.B[2], j);
-    bh.za = bsplit(Yc) ? ld(F.Ba[2], j) : T(0);
+    bh.x = cur.bx;
+    bh.y = cur.by;
+    bh.z = cur.bz;
+    bh.za = cur.bza;
     const bool byj = j >= 0 && j <= M1, byj1 = j >= 0 && j <= M1 - 1;
     {
       const T ez_r = __shfl_down(ec.z, 1), ey_r = __shfl_down(ec.y, 1);
-      bhalf_2d(bh, X, Yc, xi0 && byj1, xi1 && byj, xi1 && byj1, nz - ec.z, ez_r - ec.z, ey_r - ec.y, nx - ec.x);
+      bhalf_2d(bh, X, Yc, xi0 && byj1, xi1 && byj, xi1 && byj1, cur.ez1 - ec.z, ez_r - ec.z, ey_r - ec.y,
+               cur.ex1 - ec.x);
     }
     ERow<T> en = ec;   // E^{n+1}(j)
     const T bz_l = __shfl_up(bh.z, 1), by_l = __shfl_up(bh.y, 1);
     if (j >= y0) {
-      const T jx = ld(F.J[0], j), jy = ld(F.J[1], j), jz = ld(F.J[2], j);
       const bool eyj = j >= 1 && j <= M1 - 1;
       estep_2d(en, X, Yc, xi1 && eyj, xe && byj1, xe && eyj, bh.z - bhp.z, bh.z - bz_l, bh.y - by_l, bh.x - bhp.x,
-               jx, jy, jz, fuse_alpha, g.dt);
+               cur.jx, cur.jy, cur.jz, fuse_alpha, g.dt);
       if (own && j < y1) {
-        const long q = g.at(i, j, 0);
-        D.E[0][q] = en.x;
-        D.E[1][q] = en.y;
-        D.E[2][q] = en.z;
-        if (esplit(Yc)) D.Ea[2][q] = en.za;
+        const int q = q0 + j * sy;
+        gptr(D.E[0])[q] = en.x;
+        gptr(D.E[1])[q] = en.y;
+        gptr(D.E[2])[q] = en.z;
+        if (esplit(Yc)) gptr(D.Ea[2])[q] = en.za;
       }
     }
     // B^{n+1}(j-1) from B^{n+1/2}(j-1) and E^{n+1} at rows j-1, j
@@ -166,23 +198,21 @@ __device__ __forceinline__ void fused_segment_2d(const Grid<T> &g, const Fields<
       bhalf_2d(b, X, Yp, xi0 && bm1, xi1 && bm0, xi1 && bm1, en.z - enp.z, pz_r - enp.z, py_r - enp.y,
                en.x - enp.x);
       if (own) {
-        const long q = g.at(i, jm, 0);
-        D.B[0][q] = b.x;
-        D.B[1][q] = b.y;
-        D.B[2][q] = b.z;
-        if (bsplit(Yp)) D.Ba[2][q] = b.za;
+        const int q = q0 + jm * sy;
+        gptr(D.B[0])[q] = b.x;
+        gptr(D.B[1])[q] = b.y;
+        gptr(D.B[2])[q] = b.z;
+        if (bsplit(Yp)) gptr(D.Ba[2])[q] = b.za;
       }
     }
     // advance one row
     bhp = bh;
     enp = en;
     Yp = Yc;
-    const int jn = j + 1;
-    load_tabs(g, 1, min(max(jn, -G), M1 + G), Yc.ehC, Yc.ghkC, Yc.sigC, Yc.eN, Yc.gN, Yc.gkN, Yc.sigN, Yc.aC, Yc.aN);
-    ec.x = nx;
-    ec.z = nz;
-    ec.y = ld(F.E[1], jn);
-    ec.za = esplit(Yc) ? ld(F.Ea[2], jn) : T(0);
+    Yc = Yn;
+    ec.x = cur.ex1;
+    ec.z = cur.ez1;
+    cur = nxt;
   }
 }
 

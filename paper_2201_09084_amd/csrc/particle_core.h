@@ -239,13 +239,48 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, Sink &sink, const int 
 }
 
 
+// Nodes along one axis that a deposit moving from cell i0 to cell i1 can touch
+template <int ORDER>
+__device__ __forceinline__ void dep_range(int i0, int i1, int &lo, int &hi) {
+  lo = min(i0, i1) + (ORDER == 1 ? -1 : -2);
+  hi = max(i0, i1) + (ORDER == 1 ? 2 : 3);
+}
+
+// Union of the threads' node boxes (x lo, x hi, y lo, y hi; empty when lo > hi) over
+// the workgroup, valid in thread 0.  Every thread of the workgroup calls it.
+__device__ __forceinline__ int4 block_box(int xlo, int xhi, int ylo, int yhi) {
+  __shared__ int sb[4];
+  if (threadIdx.x == 0) { sb[0] = 0x7FFFFFFF; sb[1] = -0x7FFFFFFF; sb[2] = 0x7FFFFFFF; sb[3] = -0x7FFFFFFF; }
+  __syncthreads();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    xlo = min(xlo, __shfl_xor(xlo, off));
+    xhi = max(xhi, __shfl_xor(xhi, off));
+    ylo = min(ylo, __shfl_xor(ylo, off));
+    yhi = max(yhi, __shfl_xor(yhi, off));
+  }
+  if ((threadIdx.x & 63) == 0 && xlo <= xhi) {
+    atomicMin(&sb[0], xlo); atomicMax(&sb[1], xhi); atomicMin(&sb[2], ylo); atomicMax(&sb[3], yhi);
+  }
+  __syncthreads();
+  return make_int4(sb[0], sb[1], sb[2], sb[3]);
+}
+
+// A batched run's box of nodes given current this step, grown by one workgroup
+__device__ __forceinline__ void jbox_grow(int *jbox, int xlo, int xhi, int ylo, int yhi) {
+  const int4 b = block_box(xlo, xhi, ylo, yhi);
+  if (threadIdx.x == 0 && b.x <= b.y) {
+    atomicMin(&jbox[0], b.x); atomicMax(&jbox[1], b.y); atomicMin(&jbox[2], b.z); atomicMax(&jbox[3], b.w);
+  }
+}
+
 // One particle of the fused step (fused = true: gather, Boris, move, Esirkepov deposit
 // into global J, removal) or of the first half of the unfused step (fused = false: the
 // old position goes to `old`, the deposit follows in k_deposit).  Returns whether
 // the slot held a live particle.
 template <typename T, int DIM, int ORDER>
 __device__ __forceinline__ bool push_one(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, const Parts<T> &old,
-                                         int p, int push, bool fused) {
+                                         int p, int push, bool fused, int *rng = nullptr) {
   const uint32_t c = P.cell[p];
   if (c == DEAD) return false;
   int id[3];
@@ -267,6 +302,10 @@ __device__ __forceinline__ bool push_one(const Grid<T> &g, const Fields<T> &F, c
   if (fused) {
     GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
     deposit<T, DIM, ORDER>(g, sink, id0, f0, id, f, u[2] * ig, g.charge * P.w[p]);
+    if (rng) {
+      dep_range<ORDER>(id0[0], id[0], rng[0], rng[1]);
+      dep_range<ORDER>(id0[1], id[1], rng[2], rng[3]);
+    }
     P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
   } else {
     old.cell[p] = c;

@@ -26,8 +26,13 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int count = *ctl.count;
   bool active = false;
-  if (p < n_slots && p < count) active = push_one<T, DIM, ORDER>(g, F, P, old, p, push, fused);
+  int rng[4] = {0, -1, 0, -1};
+  if (p < n_slots && p < count) active = push_one<T, DIM, ORDER>(g, F, P, old, p, push, fused, rng);
   count_pushes(ctl.pushes, active);
+  if (DIM == 2 && fused && ctl.jblk) {
+    const int4 b = block_box(rng[0], rng[1], rng[2], rng[3]);
+    if (threadIdx.x == 0) ctl.jblk[blockIdx.x] = b;
+  }
 }
 
 constexpr int TPB = 256;
@@ -61,14 +66,21 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
   int p0, p1, t = -1;
+  const int4 no_box = make_int4(0x7FFFFFFF, -0x7FFFFFFF, 0x7FFFFFFF, -0x7FFFFFFF);
   if constexpr (BY_TILE) {
-    if (blockIdx.x >= tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles]) return;   // uniform over the workgroup
+    if (blockIdx.x >= tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles]) {   // uniform over the workgroup
+      if (DIM == 2 && ctl.jblk && tid == 0) ctl.jblk[blockIdx.x] = no_box;
+      return;
+    }
     const int4 item = tw.items[blockIdx.x];
     p0 = item.x; p1 = item.y; t = item.z;
   } else {
     p0 = blockIdx.x * (TPB * PPT);
     p1 = min(p0 + TPB * PPT, *ctl.count);
-    if (p0 >= p1) return;
+    if (p0 >= p1) {
+      if (DIM == 2 && ctl.jblk && tid == 0) ctl.jblk[blockIdx.x] = no_box;
+      return;
+    }
   }
   int clo[3] = {-0x3FFFFFFF, -0x3FFFFFFF, -0x3FFFFFFF}, chi[3] = {0x3FFFFFFF, 0x3FFFFFFF, 0x3FFFFFFF};
   if (t >= 0) {   // old cells of the tile grown by the margin
@@ -121,6 +133,10 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   }
   if (BY_TILE && out) atomicAdd(&n_out, out);
   __syncthreads();
+  if (DIM == 2 && ctl.jblk && tid == 0)   // nodes this chunk can deposit to
+    ctl.jblk[blockIdx.x] = sbox[0] <= sbox[3]
+                               ? make_int4(sbox[0] + WLO, sbox[3] + WHI, sbox[1] + WLO, sbox[4] + WHI)
+                               : no_box;
   LdsSink<T> lsink;
   const bool any = sbox[0] <= sbox[3];
   // replicas that fit for a box of n nodes per component (0: does not fit)
@@ -260,22 +276,29 @@ template <typename T, int DIM, int ORDER>
 __global__ void __launch_bounds__(256) k_deposit(Grid<T> g, Fields<T> F, Parts<T> P, Parts<T> old,
                                                   StepCtl ctl, int n_slots) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_slots || p >= *ctl.count) return;
-  const uint32_t c = P.cell[p];
-  if (c == DEAD) return;
-  int i1[3], i0[3];
-  unpack_cell(DIM, c, i1[0], i1[1], i1[2]);
-  unpack_cell(DIM, old.cell[p], i0[0], i0[1], i0[2]);
-  const T f1[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
-  const T f0[3] = {old.f[0][p], old.f[1][p], DIM == 3 ? old.f[2][p] : T(0)};
-  const T ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
-  const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
-  GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
-  deposit<T, DIM, ORDER>(g, sink, i0, f0, i1, f1, uz * ig, g.charge * P.w[p]);
-  bool inside = true;
+  int rng[4] = {0, -1, 0, -1};
+  const uint32_t c = (p < n_slots && p < *ctl.count) ? P.cell[p] : DEAD;
+  if (c != DEAD) {
+    int i1[3], i0[3];
+    unpack_cell(DIM, c, i1[0], i1[1], i1[2]);
+    unpack_cell(DIM, old.cell[p], i0[0], i0[1], i0[2]);
+    const T f1[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
+    const T f0[3] = {old.f[0][p], old.f[1][p], DIM == 3 ? old.f[2][p] : T(0)};
+    const T ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
+    const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
+    GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+    deposit<T, DIM, ORDER>(g, sink, i0, f0, i1, f1, uz * ig, g.charge * P.w[p]);
+    dep_range<ORDER>(i0[0], i1[0], rng[0], rng[1]);
+    dep_range<ORDER>(i0[1], i1[1], rng[2], rng[3]);
+    bool inside = true;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) inside = inside && i1[d] >= 0 && i1[d] < g.M[d];
-  if (!inside) P.cell[p] = DEAD;
+    for (int d = 0; d < DIM; ++d) inside = inside && i1[d] >= 0 && i1[d] < g.M[d];
+    if (!inside) P.cell[p] = DEAD;
+  }
+  if (DIM == 2 && ctl.jblk) {
+    const int4 b = block_box(rng[0], rng[1], rng[2], rng[3]);
+    if (threadIdx.x == 0) ctl.jblk[blockIdx.x] = b;
+  }
 }
 
 #define PMLPIC_DISPATCH_ORDER(DIMV, KERNEL, ...)                                         \
@@ -529,6 +552,30 @@ void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, Sor
   hipLaunchKernelGGL((k_sort_scatter<T>), grd, blk, 0, s, g.dim, src, dst, sw, ctl.count, n_slots);
   hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, new_count, ctl.count);
 }
+
+// union of the per-workgroup boxes (one workgroup of 1024 threads)
+__global__ void __launch_bounds__(1024) k_jbox_reduce(const int4 *jblk, int n, int *cur) {
+  int xlo = 0x7FFFFFFF, xhi = -0x7FFFFFFF, ylo = 0x7FFFFFFF, yhi = -0x7FFFFFFF;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int4 b = jblk[k];
+    if (b.x <= b.y) { xlo = min(xlo, b.x); xhi = max(xhi, b.y); ylo = min(ylo, b.z); yhi = max(yhi, b.w); }
+  }
+  const int4 b = block_box(xlo, xhi, ylo, yhi);
+  if (threadIdx.x == 0) { cur[0] = b.x; cur[1] = b.y; cur[2] = b.z; cur[3] = b.w; }
+}
+
+void launch_jbox_reduce(const int4 *jblk, int n, int *cur, hipStream_t s) {
+  hipLaunchKernelGGL(k_jbox_reduce, dim3(1), dim3(1024), 0, s, jblk, n, cur);
+}
+
+template <typename T>
+int deposit_blocks(const Grid<T> &g, const TileWork &tw, int n_slots, bool tiled) {
+  if (n_slots <= 0) return 0;
+  if (!tiled) return (n_slots + 255) / 256;
+  return (tw.by_tile ? tw.ntiles : 0) + (n_slots + tw.chunk - 1) / tw.chunk;
+}
+template int deposit_blocks<float>(const Grid<float> &, const TileWork &, int, bool);
+template int deposit_blocks<double>(const Grid<double> &, const TileWork &, int, bool);
 
 int tiled_chunk(int dim) { return TPB * (dim == 2 ? TileCfg<2>::PPT : TileCfg<3>::PPT); }
 int tiled_nodes(int dim) { return dim == 2 ? TileCfg<2>::NODES : TileCfg<3>::NODES; }
