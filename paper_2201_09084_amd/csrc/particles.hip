@@ -36,13 +36,12 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
 }
 
 constexpr int TPB = 256;
-// LDS nodes per current component and particles per thread.  2D: ~24 KB of FP32,
-// replicas of small boxes for dense beams.  3D: two replicas of the 11^3-node box of
-// one 8^3 tile with the linear-shape window (32 KB of FP32; a larger box costs more
-// in occupancy than the replicas gain).
+// LDS nodes per current component (FP64 sums) and particles per thread.  2D: 36 KB,
+// replicas of small boxes for dense beams.  3D: the 11^3-node box of one 8^3 tile with
+// the linear-shape window (32 KB; a larger box costs more in occupancy than it gains).
 template <int DIM> struct TileCfg;
-template <> struct TileCfg<2> { static constexpr int NODES = 2048; static constexpr int PPT = 4; };
-template <> struct TileCfg<3> { static constexpr int NODES = 2688; static constexpr int PPT = 4; };
+template <> struct TileCfg<2> { static constexpr int NODES = 1536; static constexpr int PPT = 4; };
+template <> struct TileCfg<3> { static constexpr int NODES = 1344; static constexpr int PPT = 4; };
 
 // Fused gather_push + deposit_current over chunks of cell-sorted particles.  A
 // workgroup takes one chunk: either a work item of one sort tile (by_tile: the
@@ -61,7 +60,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   constexpr int WLO = ORDER == 1 ? -1 : -2;
   constexpr int WHI = ORDER == 1 ? 2 : 3;
   constexpr int NODES = TileCfg<DIM>::NODES;
-  __shared__ T lds[3 * NODES];
+  __shared__ double lds[3 * NODES];
   __shared__ int sbox[12];   // min[3], max[3] of the old cells; then the same clipped
   __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
@@ -181,7 +180,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   lsink.e01 = ext[0] * ext[1];
   lsink.total = total;
   if (use_lds) {
-    for (int e = tid; e < R * stride; e += TPB) lds[e] = T(0);
+    for (int e = tid; e < R * stride; e += TPB) lds[e] = 0.0;
   }
   lsink.lds = lds + (tid % R) * stride;
   __syncthreads();
@@ -226,8 +225,9 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
   if (use_lds) {
     for (int e = tid; e < 3 * total; e += TPB) {
-      T v = lds[e];
-      for (int r = 1; r < R; ++r) v += lds[r * stride + e];
+      double acc = lds[e];
+      for (int r = 1; r < R; ++r) acc += lds[r * stride + e];
+      const T v = (T)acc;
       if (v == T(0)) continue;
       const int comp = e / total;
       int r = e - comp * total;
