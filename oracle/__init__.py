@@ -36,7 +36,8 @@ class OrcParams(C.Structure):
     ]
 
 
-def build(force: bool = False) -> str:
+def build_library(force: bool = False) -> str:
+    """Compiles liboracle.so with gcc (oracle/build.py)."""
     from . import build as _b
     return _b.build(force=force)
 
@@ -45,7 +46,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            build()
+            build_library()
         L = C.CDLL(_LIB_PATH)
         P = C.POINTER
         d, vp, i, l, sz = C.c_double, C.c_void_p, C.c_int, C.c_long, C.c_size_t
