@@ -26,10 +26,25 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("particles.hip", "fields.hip", "common.h", "api.hip"):
+    for f in ("particles.hip", "fields.hip", "batch.hip", "api.hip", "common.h", "field_core.h", "fused2d.h",
+              "particle_core.h"):
         with open(os.path.join(ROOT, "paper_2201_09084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def traffic_bytes(workload, phase, precision):
+    """HBM bytes per launch from the committed PMC summary, if the kernel sources are
+    the ones it was measured on (else None)."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tf):
+        return None
+    with open(tf) as fh:
+        t = json.load(fh)
+    key = "%s/%s/fp%d" % (workload, phase, precision)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch", {}).get(key)
 
 
 def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
@@ -121,8 +136,8 @@ def run_batch(args):
     if name in per:
         ach = per[name] / avg_s / 1e9
         roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_bytes_per_launch": int(per[name]),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_bytes("batch", name, 32),
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(per[name]),
                 "timing": "HIP events around each kernel in %d eager steps after the timed graph replays" % n_prof}
     out = {
         "metric": "PIC particle-pushes/s & Yee+PML cell-updates/s; FP32 vs FP64 at stated err",
@@ -158,7 +173,7 @@ def main():
     ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch"], default="beam2d")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (calibrates the HBM byte counters)")
@@ -221,13 +236,7 @@ def main():
                 "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(per_launch),
                 "timing": "HIP events around each kernel phase on the library stream, %d steps right after "
                           "the timed region" % n_prof}
-        tf = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tf):
-            with open(tf) as fh:
-                t = json.load(fh)
-            key = "%s/%s/fp%d" % (args.workload, name, args.precision)
-            if t.get("source_hash") == kernel_source_hash() and key in t.get("bytes_per_launch", {}):
-                roof["traffic"] = t["bytes_per_launch"][key]
+        roof["traffic"] = traffic_bytes(args.workload, name, args.precision)
 
     cpu = None
     if not args.no_cpu_baseline:
