@@ -81,6 +81,8 @@ def lib():
             "orc_step": (None, [vp, i]),
             "orc_diagnose": (None, [vp, dp]),
             "orc_rho": (None, [vp, dp]),
+            "orc_get_lambda": (None, [vp, dp]),
+            "orc_path_sigma": (d, [vp, dp, dp, d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -199,6 +201,20 @@ class OracleSim:
         if n:
             lib().orc_get_particles(self._h, _lp(ids), _dp(X), _dp(u), _dp(w))
         return ids, X, u, w
+
+    def lam(self) -> np.ndarray:
+        """Per particle (order of particles()): the integral of sigma/eps0 over time
+        along its path, whose exponential damps its weight in alpha mode 3."""
+        n = self.num_particles
+        out = np.zeros(n)
+        if n:
+            lib().orc_get_lambda(self._h, _dp(out))
+        return out
+
+    def path_sigma(self, X0, X1, tau: float) -> float:
+        """Integral of sigma/eps0 over time along the straight move X0 -> X1 (grid
+        coordinates) taking tau."""
+        return lib().orc_path_sigma(self._h, _dp(_pad3(X0)), _dp(_pad3(X1)), float(tau))
 
     # ---- fields
     def _shape(self):

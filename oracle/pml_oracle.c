@@ -118,11 +118,13 @@ double orc_alpha_axis(const orc_sim *s, int d, double X)
  *   mode 0: alpha = 0 anywhere in the PML (standard Berenger PML, no source there);
  *   mode 1: alpha = 1 (undamped deposition);
  *   mode 2: Eq. (alpha); in edges and corners the product of the per-axis factors
- *           (reading: reduces to Eq. (alpha) on a face). */
+ *           (reading: reduces to Eq. (alpha) on a face);
+ *   mode 3: alpha = 1 in the field equations, each particle's weight damped instead
+ *           (Sec. II.C, discussion of the velocity limitation; see path_sigma). */
 double orc_alpha(const orc_sim *s, const double X[3])
 {
     int mode = s->p.alpha_mode;
-    if (mode == 1) return 1.0;
+    if (mode == 1 || mode == 3) return 1.0;
     double a = 1.0;
     for (int d = 0; d < s->p.dim; ++d) {
         double L, del = depth(s, d, X[d], &L);
@@ -130,6 +132,49 @@ double orc_alpha(const orc_sim *s, const double X[3])
         else a *= exp(-s->p.damping_scale * phi_of_depth(s, d, del, L));
     }
     return a;
+}
+
+/* Per-particle damping of the weight (Sec. II.C, discussion and limitations): the
+ * weight becomes w exp(-Lambda), Lambda = int sigma(x(t))/eps0 dt over the time spent
+ * in the layers (the sum over axes in edges and corners).  Over one move along a
+ * straight line from X0 to X1 (grid coordinates) in time tau, with s the signed
+ * distance into a face's layer, the integral is exactly
+ *     tau (Phi(max(s1,0)) - Phi(max(s0,0))) / (s1 - s0),
+ * or tau sigma(s0) when the coordinate does not change. */
+static double path_sigma(const orc_sim *s, const double X0[3], const double X1[3], double tau)
+{
+    double acc = 0.0;
+    for (int d = 0; d < s->p.dim; ++d) {
+        double h = s->p.dx[d];
+        double lo = (double)s->p.pml[d][0], hi = (double)(s->p.pml[d][0] + s->p.n[d]);
+        double Llo = s->p.pml[d][0] * h, Lhi = s->p.pml[d][1] * h;
+        double sl0 = (lo - X0[d]) * h, sl1 = (lo - X1[d]) * h;   /* into the low layer */
+        double sh0 = (X0[d] - hi) * h, sh1 = (X1[d] - hi) * h;   /* into the high layer */
+        if (X1[d] == X0[d]) {
+            acc += tau * (sigma_of_depth(s, d, sl0, Llo) + sigma_of_depth(s, d, sh0, Lhi));
+        } else {
+            acc += tau * (phi_of_depth(s, d, sl1, Llo) - phi_of_depth(s, d, sl0, Llo)) / (sl1 - sl0);
+            acc += tau * (phi_of_depth(s, d, sh1, Lhi) - phi_of_depth(s, d, sh0, Lhi)) / (sh1 - sh0);
+        }
+    }
+    return acc;
+}
+
+/* a particle's weight with its damping (mode 3) */
+static double particle_weight(const orc_sim *s, long t)
+{
+    return s->p.alpha_mode == 3 ? s->W[t] * exp(-s->LAM[t]) : s->W[t];
+}
+
+/* Lambda of the particles, in the order of orc_get_particles */
+void orc_get_lambda(const orc_sim *s, double *lam)
+{
+    for (long t = 0; t < s->np; ++t) lam[t] = s->LAM[t];
+}
+
+double orc_path_sigma(const orc_sim *s, const double X0[3], const double X1[3], double tau)
+{
+    return path_sigma(s, X0, X1, tau);
 }
 
 /* Exponential time-differencing factors for dF/dt = -sig F + rhs over tau:
@@ -208,7 +253,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     for (int q = 0; q < NPART; ++q) free(s->F[q]);
     for (int a = 0; a < 3; ++a) free(s->J[a]);
-    free(s->rho_static); free(s->X); free(s->U); free(s->W); free(s->id);
+    free(s->rho_static); free(s->X); free(s->U); free(s->W); free(s->LAM); free(s->id);
     free(s);
 }
 
@@ -224,6 +269,7 @@ static void reserve(orc_sim *s, long n)
     s->X = (double *)realloc(s->X, sizeof(double) * 3 * c);
     s->U = (double *)realloc(s->U, sizeof(double) * 3 * c);
     s->W = (double *)realloc(s->W, sizeof(double) * c);
+    s->LAM = (double *)realloc(s->LAM, sizeof(double) * c);
     s->id = (long *)realloc(s->id, sizeof(long) * c);
     s->cap = c;
 }
@@ -263,6 +309,7 @@ int orc_add_particles(orc_sim *s, long n, const double *x, const double *u, cons
             s->U[3 * q + d] = u[3 * t + d];
         }
         s->W[q] = w[t];
+        s->LAM[q] = 0.0;
         s->id[q] = s->next_id++;
         deposit_rho(s, &s->X[3 * q], s->p.charge * w[t], -1.0, s->rho_static);
     }
@@ -277,7 +324,7 @@ int orc_set_particles(orc_sim *s, long n, const long *id, const double *X, const
     reserve(s, n);
     for (long t = 0; t < n; ++t) {
         for (int d = 0; d < 3; ++d) { s->X[3 * t + d] = X[3 * t + d]; s->U[3 * t + d] = u[3 * t + d]; }
-        s->W[t] = w[t]; s->id[t] = id[t];
+        s->W[t] = w[t]; s->LAM[t] = 0.0; s->id[t] = id[t];
         if (id[t] >= s->next_id) s->next_id = id[t] + 1;
     }
     s->np = n;
@@ -580,12 +627,20 @@ void orc_step(orc_sim *s, int nsteps)
             double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
             double X1[3] = {X[0], X[1], X[2]};
             for (int d = 0; d < dim; ++d) X1[d] = X[d] + s->p.dt * u[d] / gam / s->p.dx[d];
-            orc_deposit(s, X, X1, u[2] / gam, s->p.charge * s->W[t], s->J);
+            double qw = s->p.charge * s->W[t], lam = s->LAM[t];
+            if (s->p.alpha_mode == 3) {
+                /* weight damped by Lambda at mid-step (the time of the deposited current) */
+                double Xh[3] = {X[0], X[1], X[2]};
+                for (int d = 0; d < dim; ++d) Xh[d] = 0.5 * (X[d] + X1[d]);
+                qw *= exp(-(lam + path_sigma(s, X, Xh, 0.5 * s->p.dt)));
+                lam += path_sigma(s, X, X1, s->p.dt);
+            }
+            orc_deposit(s, X, X1, u[2] / gam, qw, s->J);
             int out = 0;
             for (int d = 0; d < dim; ++d) if (X1[d] < 0.0 || X1[d] >= (double)s->M[d]) out = 1;
             if (out) continue;
             for (int d = 0; d < 3; ++d) { s->X[3 * keep + d] = X1[d]; s->U[3 * keep + d] = u[d]; }
-            s->W[keep] = s->W[t]; s->id[keep] = s->id[t];
+            s->W[keep] = s->W[t]; s->LAM[keep] = lam; s->id[keep] = s->id[t];
             ++keep;
         }
         s->np = keep;
@@ -629,7 +684,7 @@ void orc_diagnose(const orc_sim *s, double out[7])
         }
     }
     double *rho = (double *)calloc(s->nsamp, sizeof(double));
-    for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * s->W[t], 1.0, rho);
+    for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * particle_weight(s, t), 1.0, rho);
     double rmax = 0.0;
     for (size_t q = 0; q < s->nsamp; ++q) if (fabs(rho[q]) > rmax) rmax = fabs(rho[q]);
     double gmax = 0.0, gsum = 0.0;
@@ -663,5 +718,5 @@ void orc_diagnose(const orc_sim *s, double out[7])
 void orc_rho(const orc_sim *s, double *rho)
 {
     memset(rho, 0, sizeof(double) * s->nsamp);
-    for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * s->W[t], 1.0, rho);
+    for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * particle_weight(s, t), 1.0, rho);
 }

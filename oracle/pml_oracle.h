@@ -15,7 +15,7 @@ typedef struct {
     double dx[3];
     double dt;
     int shape_order;         /* 1, 2, 3 */
-    int alpha_mode;          /* 0: alpha = 0, 1: alpha = 1, 2: Eq. (alpha) */
+    int alpha_mode;          /* 0: alpha = 0, 1: alpha = 1, 2: Eq. (alpha), 3: weights damped */
     double damping_scale;    /* 1/v of Eq. (alpha) */
     int n_sigma_coef;
     double sigma_coef[3][16];/* sigma_d/eps0 = sum_k coef[d][k] (depth/L)^k */
@@ -33,6 +33,7 @@ typedef struct {
     double *rho_static;
     long np, cap, next_id;
     double *X, *U, *W;       /* grid coordinates (np x 3), u = gamma v (np x 3), weights */
+    double *LAM;             /* mode 3: int sigma/eps0 dt along each particle's path */
     long *id;
     long step;
 } orc_sim;
@@ -66,5 +67,7 @@ void orc_advance_E(orc_sim *s, double tau);
 void orc_step(orc_sim *s, int nsteps);
 void orc_diagnose(const orc_sim *s, double out[7]);
 void orc_rho(const orc_sim *s, double *rho);
+void orc_get_lambda(const orc_sim *s, double *lam);
+double orc_path_sigma(const orc_sim *s, const double X0[3], const double X1[3], double tau);
 
 #endif

@@ -17,7 +17,7 @@ from typing import List, Optional
 
 import numpy as np
 
-ALPHA_ZERO, ALPHA_ONE, ALPHA_DAMPED = 0, 1, 2
+ALPHA_ZERO, ALPHA_ONE, ALPHA_DAMPED, ALPHA_WEIGHT = 0, 1, 2, 3
 
 
 @dataclasses.dataclass
