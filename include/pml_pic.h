@@ -50,7 +50,14 @@ typedef enum {
 } pml_pic_status;
 
 /* current-damping scheme in the PML (the alpha of Eq. MaxwellE) */
-enum { PML_ALPHA_ZERO = 0, PML_ALPHA_ONE = 1, PML_ALPHA_DAMPED = 2 };
+enum {
+    PML_ALPHA_ZERO = 0,    /* alpha = 0 in the PML: no current there (standard PML)          */
+    PML_ALPHA_ONE = 1,     /* alpha = 1: undamped current                                      */
+    PML_ALPHA_DAMPED = 2,  /* Eq. (alpha) at each current sample, assumed velocity 1/damping_scale */
+    PML_ALPHA_WEIGHT = 3   /* alpha = 1 in the field equations; instead each particle's weight is
+                              damped by exp(-int sigma/eps0 dt) along its own path (Sec. II.C,
+                              discussion of the velocity limitation) */
+};
 
 /* pml_pic_params.flags */
 enum {
@@ -71,7 +78,7 @@ typedef struct {
     double dx[3];               /* cell sizes */
     double dt;                  /* time step; c dt < 1/sqrt(sum 1/dx_d^2) */
     int32_t shape_order;        /* particle shape: 1 linear, 2 quadratic, 3 cubic */
-    int32_t alpha_mode;         /* PML_ALPHA_ZERO / ONE / DAMPED */
+    int32_t alpha_mode;         /* PML_ALPHA_ZERO / ONE / DAMPED / WEIGHT */
     double damping_scale;       /* 1/v of Eq. (alpha): alpha = exp(-damping_scale * int sigma/eps0) */
     int32_t n_sigma_coef;       /* K <= 16 */
     double sigma_coef[3][16];   /* sigma_d/eps0 = sum_k coef[d][k] (depth/L_d)^k, depth > 0 */
@@ -161,7 +168,10 @@ int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count);
 
 /* The current J_x J_y J_z (3 x n_samples doubles) deposited and damped by the last
  * step, at E's sample positions; needs PML_PIC_FLAG_KEEP_CURRENT or the one-pass 2D
- * field update (otherwise the arrays are zero after every step).  Synchronises. */
+ * field update (otherwise the arrays are zero after every step).  J_a at node index
+ * M_a along its own axis a (the edge half a cell beyond the outer wall) is padding: a
+ * particle leaving the box may deposit there, nothing reads it, and its value is
+ * unspecified.  Synchronises. */
 int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count);
 
 /* Static partner charge density at the nodes (n_samples doubles). */
@@ -178,7 +188,8 @@ int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *
                           double *w, int64_t *n_out);
 
 /* Replaces all particles by the given ones (grid coordinates as above); the static
- * partner density is left as it is. */
+ * partner density is left as it is; with PML_ALPHA_WEIGHT their damping integrals
+ * restart at zero. */
 int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X,
                           const double *u, const double *w);
 

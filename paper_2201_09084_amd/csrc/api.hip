@@ -29,7 +29,7 @@ struct Layout {
   size_t off_alt[12] = {};     // second set of E, B, Ea, Ba for the out-of-place 2D update
   bool has_alt = false;
   size_t off_tab = 0;
-  size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_id[2] = {};
+  size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_lam[2] = {}, off_id[2] = {};
   size_t off_oldcell = 0, off_oldf[3] = {};
   size_t off_count = 0, off_pushes = 0;
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
@@ -98,7 +98,7 @@ int validate(const pml_pic_params *p, std::string *err) {
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(err, PML_PIC_E_INVALID_ARG, "dt must be > 0");
   if (!(p->dt < 1.0 / std::sqrt(s2))) return fail(err, PML_PIC_E_CFL, "c dt violates the Yee CFL limit");
   if (p->shape_order < 1 || p->shape_order > 3) return fail(err, PML_PIC_E_INVALID_ARG, "shape_order must be 1, 2 or 3");
-  if (p->alpha_mode < 0 || p->alpha_mode > 2) return fail(err, PML_PIC_E_INVALID_ARG, "alpha_mode must be 0, 1 or 2");
+  if (p->alpha_mode < 0 || p->alpha_mode > 3) return fail(err, PML_PIC_E_INVALID_ARG, "alpha_mode must be 0, 1, 2 or 3");
   if (!(p->damping_scale >= 0.0) || !std::isfinite(p->damping_scale))
     return fail(err, PML_PIC_E_INVALID_ARG, "damping_scale must be >= 0");
   if (p->n_sigma_coef < 0 || p->n_sigma_coef > 16) return fail(err, PML_PIC_E_INVALID_ARG, "n_sigma_coef must be in [0,16]");
@@ -157,13 +157,14 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.has_alt = p.dim == 2 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS);
   if (L.has_alt)
     for (int a = 0; a < 12; ++a) L.off_alt[a] = take(L.esz * (size_t)L.nelem);
-  L.off_tab = take(L.esz * 3 * T_NKIND * (size_t)L.ntab);
+  L.off_tab = take(L.esz * (3 * T_NKIND * (size_t)L.ntab + 3 * PROF_N));
   const size_t cap = (size_t)std::max<int64_t>(L.cap, 1);
   for (int b = 0; b < 2; ++b) {
     L.off_cell[b] = take(4 * cap);
     for (int d = 0; d < 3; ++d) L.off_f[b][d] = d < p.dim ? take(L.esz * cap) : 0;
     for (int d = 0; d < 3; ++d) L.off_u[b][d] = take(L.esz * cap);
     L.off_w[b] = take(L.esz * cap);
+    L.off_lam[b] = p.alpha_mode == PML_ALPHA_WEIGHT ? take(L.esz * cap) : 0;
     L.off_id[b] = take(4 * cap);
   }
   L.off_oldcell = take(4 * cap);
@@ -252,6 +253,8 @@ struct pml_pic_handle {
     g.charge = (T)p.charge;
     g.tab = at<T>(L.off_tab);
     g.ntab = L.ntab;
+    g.wdamp = p.alpha_mode == PML_ALPHA_WEIGHT ? 1 : 0;
+    g.prof = at<T>(L.off_tab) + 3 * T_NKIND * (size_t)L.ntab;
     return g;
   }
   // offset of field array idx (0..11: E, B, Ea, Ba) of set `set`
@@ -277,6 +280,7 @@ struct pml_pic_handle {
       P.u[d] = at<T>(L.off_u[b][d]);
     }
     P.w = at<T>(L.off_w[b]);
+    P.lam = p.alpha_mode == PML_ALPHA_WEIGHT ? at<T>(L.off_lam[b]) : nullptr;
     P.id = at<int32_t>(L.off_id[b]);
     return P;
   }
@@ -355,7 +359,16 @@ namespace {
 void build_tables(pml_pic_handle *h) {
   const pml_pic_params &p = h->p;
   const Layout &L = h->L;
-  h->tab64.assign((size_t)3 * T_NKIND * L.ntab, 0.0);
+  h->tab64.assign((size_t)3 * T_NKIND * L.ntab + 3 * PROF_N, 0.0);
+  for (int d = 0; d < p.dim; ++d) {   // profile block of the per-particle weight damping
+    double *pr = h->tab64.data() + (size_t)3 * T_NKIND * L.ntab + d * PROF_N;
+    pr[PROF_LO] = p.pml[d][0];
+    pr[PROF_HI] = p.pml[d][0] + p.n[d];
+    pr[PROF_LLO] = p.pml[d][0] * p.dx[d];
+    pr[PROF_LHI] = p.pml[d][1] * p.dx[d];
+    pr[PROF_DX] = p.dx[d];
+    for (int k = 0; k < p.n_sigma_coef; ++k) pr[PROF_C + k] = p.sigma_coef[d][k] / (k + 1);
+  }
   auto put = [&](int axis, int kind, int i, double v) { h->tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G] = v; };
   for (int d = 0; d < 3; ++d) {
     for (int i = -G; i <= L.M[d] + G; ++i) {
@@ -475,7 +488,7 @@ int get_current_t(pml_pic_handle *h, double *out) {
   const Layout &L = h->L;
   const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
   std::vector<T> buf(L.nelem);
-  const bool alpha_in_update = !(h->p.flags & PML_PIC_FLAG_SEPARATE_DAMP) && h->p.alpha_mode != PML_ALPHA_ONE;
+  const bool alpha_in_update = !(h->p.flags & PML_PIC_FLAG_SEPARATE_DAMP) && current_alpha(h->p.alpha_mode);
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int a = 0; a < 3; ++a) {
     HIPCHK(h, hipMemcpy(buf.data(), h->at<T>(L.off_field[12 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
@@ -549,6 +562,10 @@ int write_particles(pml_pic_handle *h, int64_t at_slot, int64_t n, const int64_t
     HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_u[b][d]) + at_slot, uu[d].data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_w[b]) + at_slot, ww.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->at<int32_t>(L.off_id[b]) + at_slot, id.data(), 4 * n, hipMemcpyHostToDevice, s));
+  if (h->p.alpha_mode == PML_ALPHA_WEIGHT) {   // damping integrals start at zero
+    std::vector<T> zero(n, T(0));
+    HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_lam[b]) + at_slot, zero.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  }
   HIPCHK(h, hipStreamSynchronize(s));
   return PML_PIC_OK;
 }
@@ -641,7 +658,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (it < (int)h->snap_J.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_J[it], F.J[0], h->L.J_bytes, hipMemcpyDeviceToDevice, s));
-    if (sep_damp && h->p.alpha_mode != PML_ALPHA_ONE) {
+    if (sep_damp && current_alpha(h->p.alpha_mode)) {
       pt.begin(s);
       launch_damp_current<T>(g, F, s);
       pt.end(s, PML_PIC_PHASE_DAMP);
@@ -649,7 +666,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     if (one_pass) {
       pt.begin(s);
       launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), box_cur,
-                             !sep_damp && h->p.alpha_mode != PML_ALPHA_ONE, s);
+                             !sep_damp && current_alpha(h->p.alpha_mode), s);
       pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
       h->fset = 1 - h->fset;
     } else {
@@ -1350,6 +1367,8 @@ int check_adjoint(pml_pic_handle *h) {
   if (h->p.push != 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint covers ballistic runs (push = 0)");
   if (h->p.alpha_mode == PML_ALPHA_ZERO)
     return fail(&h->err, PML_PIC_E_INVALID_ARG, "alpha_mode 0 is not differentiable in the profile");
+  if (h->p.alpha_mode == PML_ALPHA_WEIGHT)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint does not cover per-particle weight damping");
   return PML_PIC_OK;
 }
 

@@ -35,7 +35,8 @@ __global__ void __launch_bounds__(256) k_batch_fused_2d(const RunDesc<T> *__rest
     const Grid<T> g = runs[w.x].g;
     const Fields<T> src = parity ? runs[w.x].F2 : runs[w.x].F;
     const Fields<T> dst = parity ? runs[w.x].F : runs[w.x].F2;
-    fused_segment_2d(g, src, dst, runs[w.x].jbox + 4 * parity, w.y, w.z, w.w, runs[w.x].alpha_mode != 1, lane);
+    fused_segment_2d(g, src, dst, runs[w.x].jbox + 4 * parity, w.y, w.z, w.w, current_alpha(runs[w.x].alpha_mode),
+                     lane);
   }
 }
 
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(256) k_batch_update_E(const RunDesc<T> *__rest
     const int4 w = items[it];
     const Grid<T> g = runs[w.x].g;
     const Fields<T> F = runs[w.x].F;
-    const bool fuse_alpha = runs[w.x].alpha_mode != 1;
+    const bool fuse_alpha = current_alpha(runs[w.x].alpha_mode);
     const int i = w.y * bdx + tx, j = w.z * bdy + ty, k = w.w;
     if (i > g.M[0] || j > g.M[1]) continue;
     const int id[3] = {i, j, k};

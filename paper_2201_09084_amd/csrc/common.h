@@ -42,6 +42,14 @@ __host__ __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T 
   return (__attribute__((address_space(1))) T *)p;
 }
 
+// Per axis, the profile block used by the per-particle weight damping: low and high
+// layer edges (grid units), their thicknesses (physical), then a_k / (k + 1) for the
+// 16 coefficients of sigma/eps0 = sum_k a_k (depth/L)^k.
+enum { PROF_LO = 0, PROF_HI, PROF_LLO, PROF_LHI, PROF_DX, PROF_C, PROF_N = PROF_C + 16 };
+
+// alpha applied to the current in the field update (modes 0 and 2)
+__host__ __device__ __forceinline__ bool current_alpha(int alpha_mode) { return alpha_mode == 0 || alpha_mode == 2; }
+
 template <typename T>
 struct Grid {
   int dim, order;
@@ -57,6 +65,8 @@ struct Grid {
   T charge;
   const T *tab;        // [3][T_NKIND][ntab], entry i + G for index i in [-G, M+G]
   int ntab;
+  int wdamp;           // 1: per-particle weight damping (alpha mode 3)
+  const T *prof;       // [3][PROF_N]: layer edges, thicknesses and sigma coefficients
 
   __host__ __device__ long at(int i, int j, int k) const { return base + i + j * sy + k * sz; }
   __device__ T tb(int axis, int kind, int i) const {
@@ -79,6 +89,7 @@ struct Parts {
   T *f[3];            // offsets in [0,1)
   T *u[3];            // gamma v
   T *w;               // weight
+  T *lam;             // alpha mode 3: int sigma/eps0 dt along the path (else null)
   int32_t *id;
 };
 

@@ -99,7 +99,9 @@ __global__ void __launch_bounds__(256) k_rho(Grid<T> g, Parts<T> P, const int32_
   for (int d = 0; d < DIM; ++d) st[d] = id[d] + shape_weights<ORDER>((double)P.f[d][p], wts[d]);
   double dV = 1.0;
   for (int d = 0; d < DIM; ++d) dV /= (double)g.inv_dx[d];
-  const double qw = sign * (double)g.charge * (double)P.w[p] / dV;
+  double w = (double)P.w[p];
+  if (g.wdamp) w *= exp(-(double)P.lam[p]);   // weight damping: the particle's present charge
+  const double qw = sign * (double)g.charge * w / dV;
   const int nz = DIM == 3 ? ORDER + 1 : 1;
   for (int cz = 0; cz < nz; ++cz)
     for (int b = 0; b <= ORDER; ++b)

@@ -144,7 +144,7 @@ template <typename T>
 void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode, bool consume,
                      hipStream_t s) {
   dim3 blk, grd = node_grid(g, blk);
-  const bool fa = fuse_alpha && alpha_mode != 1;
+  const bool fa = fuse_alpha && current_alpha(alpha_mode);
   if (g.dim == 2) hipLaunchKernelGGL((k_update_E<T, 2>), grd, blk, 0, s, g, F, fa, consume);
   else hipLaunchKernelGGL((k_update_E<T, 3>), grd, blk, 0, s, g, F, fa, consume);
 }

@@ -241,6 +241,73 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, Sink &sink, const int 
 }
 
 
+// Per-particle weight damping (Sec. II.C, discussion of the velocity limitation): the
+// weight is w exp(-Lambda), Lambda = int sigma/eps0 dt along the particle's path.
+// For one layer face, with the signed depth s into the layer at the start and end of
+// a straight move taking tau, a = max(s0, 0), b = max(s1, 0), the integral is
+// tau (b - a) / (s1 - s0) times the divided difference (Phi(b) - Phi(a)) / (b - a) of
+// the antiderivative of the polynomial profile, evaluated as sum_k c_k h_k with
+// c_k = a_k / (k + 1), h_0 = 1, h_k = (b/L) h_{k-1} + (a/L)^k (no cancellation when b
+// is close to a; it is sigma(a) when b = a).
+template <typename T>
+__device__ __forceinline__ T face_sigma_integral(const T *pc, T L, T s0, T s1, T tau) {
+  if (!(s0 > T(0)) && !(s1 > T(0))) return T(0);
+  const T a = s0 > T(0) ? s0 : T(0), b = s1 > T(0) ? s1 : T(0);
+  const T frac = (s1 == s0) ? T(1) : (b - a) / (s1 - s0);
+  const T ra = a / L, rb = b / L;
+  T h = T(1), pa = T(1), dd = pc[0];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    pa *= ra;
+    h = fma(rb, h, pa);
+    dd = fma(pc[k], h, dd);
+  }
+  return tau * frac * dd;
+}
+
+// Lambda gained over the first half of the move (i0, f0) -> (i1, f1) and over the
+// whole move (summed over the layers of every axis)
+template <typename T, int DIM>
+__device__ __forceinline__ void path_lambda(const Grid<T> &g, const int (&i0)[3], const T (&f0)[3],
+                                            const int (&i1)[3], const T (&f1)[3], T &half, T &full) {
+  half = T(0);
+  full = T(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const T *pr = g.prof + d * PROF_N;
+    const T h = pr[PROF_DX];
+    const int lo = (int)pr[PROF_LO], hi = (int)pr[PROF_HI];
+    // signed depths into the low and high layers (exact integer parts)
+    const T l0 = ((T)(lo - i0[d]) - f0[d]) * h, l1 = ((T)(lo - i1[d]) - f1[d]) * h;
+    const T u0 = ((T)(i0[d] - hi) + f0[d]) * h, u1 = ((T)(i1[d] - hi) + f1[d]) * h;
+    const T lm = T(0.5) * (l0 + l1), um = T(0.5) * (u0 + u1);
+    if (pr[PROF_LLO] > T(0)) {
+      half += face_sigma_integral(pr + PROF_C, pr[PROF_LLO], l0, lm, T(0.5) * g.dt);
+      full += face_sigma_integral(pr + PROF_C, pr[PROF_LLO], l0, l1, g.dt);
+    }
+    if (pr[PROF_LHI] > T(0)) {
+      half += face_sigma_integral(pr + PROF_C, pr[PROF_LHI], u0, um, T(0.5) * g.dt);
+      full += face_sigma_integral(pr + PROF_C, pr[PROF_LHI], u0, u1, g.dt);
+    }
+  }
+}
+
+// charge times weight of a particle for the deposit of the move (i0, f0) -> (i1, f1);
+// with weight damping also updates its Lambda
+template <typename T, int DIM>
+__device__ __forceinline__ T deposit_charge(const Grid<T> &g, const Parts<T> &P, int p, const int (&i0)[3],
+                                            const T (&f0)[3], const int (&i1)[3], const T (&f1)[3]) {
+  T qw = g.charge * P.w[p];
+  if (g.wdamp) {
+    T half, full;
+    path_lambda<T, DIM>(g, i0, f0, i1, f1, half, full);
+    const T lam = P.lam[p];
+    qw *= exp(-(lam + half));
+    P.lam[p] = lam + full;
+  }
+  return qw;
+}
+
 // Nodes along one axis that a deposit moving from cell i0 to cell i1 can touch
 template <int ORDER>
 __device__ __forceinline__ void dep_range(int i0, int i1, int &lo, int &hi) {
@@ -303,7 +370,7 @@ __device__ __forceinline__ bool push_one(const Grid<T> &g, const Fields<T> &F, c
   for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
   if (fused) {
     GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
-    deposit<T, DIM, ORDER>(g, sink, id0, f0, id, f, u[2] * ig, g.charge * P.w[p]);
+    deposit<T, DIM, ORDER>(g, sink, id0, f0, id, f, u[2] * ig, deposit_charge<T, DIM>(g, P, p, id0, f0, id, f));
     if (rng) {
       dep_range<ORDER>(id0[0], id[0], rng[0], rng[1]);
       dep_range<ORDER>(id0[1], id[1], rng[2], rng[3]);

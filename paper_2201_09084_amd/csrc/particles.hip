@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
         P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
-        const T qw = g.charge * P.w[p];
+        const T qw = deposit_charge<T, DIM>(g, P, p, id0, f0, id, f);
         if (inbox) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
         else deposit<T, DIM, ORDER>(g, gsink, id0, f0, id, f, u[2] * ig, qw);
         P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256) k_deposit(Grid<T> g, Fields<T> F, Parts<T
     const T ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
     const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
     GlobalSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
-    deposit<T, DIM, ORDER>(g, sink, i0, f0, i1, f1, uz * ig, g.charge * P.w[p]);
+    deposit<T, DIM, ORDER>(g, sink, i0, f0, i1, f1, uz * ig, deposit_charge<T, DIM>(g, P, p, i0, f0, i1, f1));
     dep_range<ORDER>(i0[0], i1[0], rng[0], rng[1]);
     dep_range<ORDER>(i0[1], i1[1], rng[2], rng[3]);
     bool inside = true;
@@ -530,6 +530,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int dim, Parts<T> src, Par
   dst.u[1][q] = src.u[1][p];
   dst.u[2][q] = src.u[2][p];
   dst.w[q] = src.w[p];
+  if (src.lam) dst.lam[q] = src.lam[p];
   dst.id[q] = src.id[p];
 }
 

@@ -86,6 +86,21 @@ def compare_fields(g, o, cfg, tol, what="", l2=False):
     return worst
 
 
+def compare_current(g, o, tol, what=""):
+    """J of the last step, component by component, over the edges inside the box: J_a
+    at the last node index along axis a is padding beyond the outer wall (a particle
+    leaving the box may deposit there on the GPU, the oracle drops it)."""
+    Jg, Jo = g.current(), o.current()
+    for a in range(3):
+        sl = [slice(None)] * 3
+        if Jg[a].shape[2 - a] > 1:        # J_z of a 2D run has no staggered axis
+            sl[2 - a] = slice(0, -1)
+        jg, jo = Jg[a][tuple(sl)], Jo[a][tuple(sl)]
+        s = np.max(np.abs(jo))
+        err = np.max(np.abs(jg - jo))
+        assert err <= tol * max(s, 1e-30), (what, "J", a, err, s)
+
+
 def compare_particles(g, o, tol_x, tol_u, what=""):
     ig, Xg, ug, wg = g.particles()
     io, Xo, uo, wo = o.particles()

@@ -58,7 +58,8 @@ def test_parameter_validation_codes(lib):
     assert _size(cfg, dt=0.71)[0] == -2                  # beyond the 2D Yee CFL limit 1/sqrt(2)
     assert _size(cfg, dim=4)[0] == -1
     assert _size(cfg, shape_order=4)[0] == -1
-    assert _size(cfg, alpha_mode=3)[0] == -1
+    assert _size(cfg, alpha_mode=4)[0] == -1
+    assert _size(cfg, alpha_mode=3)[0] == 0                # per-particle weight damping
     assert _size(cfg, precision=16)[0] == -1
     assert _size(cfg, max_particles=-1)[0] == -1
     p = B.make_params(cfg)

@@ -54,8 +54,9 @@ def test_batch_equals_runs_stepped_alone(precision, use_graph):
         assert b.runs[k].diagnose()["n_pushes"] == alone.diagnose()["n_pushes"]
 
 
-def test_batch_matches_oracle_fp64():
-    runs = _small_runs(3, 64, seed=11)
+@pytest.mark.parametrize("mode", [W.ALPHA_DAMPED, W.ALPHA_WEIGHT])
+def test_batch_matches_oracle_fp64(mode):
+    runs = [(c.replace(alpha_mode=mode), p) for c, p in _small_runs(3, 64, seed=11)]
     b = _batch(runs, True)
     b.step(30)
     b.synchronize()
