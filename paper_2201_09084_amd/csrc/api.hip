@@ -35,6 +35,7 @@ struct Layout {
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
   int ntiles = 1;
   size_t off_items = 0, max_items = 0, off_jbox = 0, off_jblk = 0, max_push_blocks = 0;
+  size_t off_rflags = 0, off_nitems = 0, max_ranges = 0;
   size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
   int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
   // adjoint storage (present when adjoint_segment > 0)
@@ -178,9 +179,13 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_tprefix = take(4 * ((size_t)L.ntiles + 1));
   L.off_tpartial = take(4 * ((size_t)L.ntiles + 1));
   L.off_tblocks = take(4 * ((size_t)(L.ntiles + 4095) / 4096 + 2));
-  // chunks of the tiled step: at most one partial chunk per tile beyond cap / chunk
-  L.max_items = (size_t)L.ntiles + (cap + tiled_chunk(p.dim) - 1) / tiled_chunk(p.dim);
+  // chunks of the tiled step: 3D, at most one partial chunk per tile beyond cap / chunk;
+  // 2D, fixed ranges of the sorted array, each split into at most RANGE_SPLIT_MAX items
+  L.max_ranges = (cap + tiled_chunk(p.dim) - 1) / tiled_chunk(p.dim);
+  L.max_items = std::max((size_t)L.ntiles + L.max_ranges, RANGE_SPLIT_MAX * L.max_ranges);
   L.off_items = take(16 * L.max_items);
+  L.off_rflags = take(4 * L.max_ranges + 4);
+  L.off_nitems = take(16);
   L.off_rho = take(8 * (size_t)L.nelem);
   L.off_rho_static = take(8 * (size_t)L.nelem);
   L.off_partial = take(8 * (4 * (size_t)L.diag_blocks + 1024));
@@ -313,6 +318,8 @@ struct pml_pic_handle {
     w.pprefix = at<uint32_t>(L.off_tpartial);
     w.blocksums = at<uint32_t>(L.off_tblocks);
     w.items = at<int4>(L.off_items);
+    w.flags = at<uint32_t>(L.off_rflags);
+    w.n_items = at<uint32_t>(L.off_nitems);
     w.ntiles = L.ntiles;
     w.tilecells = L.tile[0] * L.tile[1] * L.tile[2];
     w.chunk = tiled_chunk(p.dim);
@@ -627,6 +634,9 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       pt.begin(s);
       launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
       if (fused && h->p.dim == 3) launch_tile_chunks(h->tilework(), ctl.count, s);
+      if (fused && h->p.dim == 2)
+        launch_range_items(h->tilework(), h->parts<T>(1 - h->cur).cell, ctl.count, h->p.shape_order,
+                           (int)h->L.max_ranges, std::min(h->sort_interval - 1, 2), s);
       pt.end(s, PML_PIC_PHASE_SORT);
       h->cur = 1 - h->cur;
       h->since_sort = 0;

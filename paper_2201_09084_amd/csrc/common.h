@@ -176,11 +176,19 @@ struct TileWork {
   uint32_t *pprefix;           // ntiles + 1: the same for the partial last chunk of each tile
   uint32_t *blocksums;         // scan scratch
   int4 *items;                 // per chunk: first slot, end slot, tile
+  uint32_t *flags;             // 2D: per fixed range, 1 if its node box does not fit in LDS
+  uint32_t *n_items;           // 2D: number of items in `items`
   int ntiles, tilecells, chunk, margin;
   int tile[3], ntile[3];
-  int by_tile;                 // 1: tile items; 0: fixed ranges of the sorted array
+  int by_tile;                 // 1: tile items; 0: ranges of the sorted array (2D list)
 };
 void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s);
+// 2D work list after a sort: cell = the sorted particles' cells, max_ranges = ranges of
+// `chunk` particles at full capacity, drift = cells a particle may move per side before
+// the next sort (allowance in the LDS fit test)
+void launch_range_items(const TileWork &tw, const uint32_t *cell, const int32_t *count, int order, int max_ranges,
+                        int drift, hipStream_t s);
+constexpr int RANGE_SPLIT_MAX = 4;                      // items per range at most
 int tiled_chunk(int dim);   // particles per chunk of the tiled step
 int tiled_nodes(int dim);   // LDS nodes per current component of one chunk's box
 template <typename T>

@@ -64,11 +64,58 @@ __device__ __forceinline__ T gather_comp(const Grid<T> &g, const T *__restrict__
   return acc;
 }
 
+// 2D: every stencil load is issued before the first product, with 32-bit offsets
+// (left to itself the compiler interleaved loads and waits in the register-heavy
+// fused kernel: one memory round trip per stencil row)
+template <typename T, int ORDER, int MASK>
+__device__ __forceinline__ void load_stencil_2d(const Grid<T> &g, const T *arr, const Shape3<ORDER, T> &S,
+                                                T (&v)[ORDER + 1][ORDER + 1]) {
+  constexpr bool hx = MASK & 1, hy = MASK & 2;
+  const int sy = (int)g.sy;
+  const int q0 = (int)g.base + (hx ? S.sc[0] : S.sn[0]) + (hy ? S.sc[1] : S.sn[1]) * sy;
+  const auto *a = gptr(arr) + q0;
+#pragma unroll
+  for (int b = 0; b <= ORDER; ++b)
+#pragma unroll
+    for (int c = 0; c <= ORDER; ++c) v[b][c] = a[b * sy + c];
+}
+template <typename T, int ORDER, int MASK>
+__device__ __forceinline__ T interp_2d(const Shape3<ORDER, T> &S, const T (&v)[ORDER + 1][ORDER + 1]) {
+  constexpr bool hx = MASK & 1, hy = MASK & 2;
+  T acc = T(0);
+#pragma unroll
+  for (int b = 0; b <= ORDER; ++b) {
+    T row = T(0);
+#pragma unroll
+    for (int c = 0; c <= ORDER; ++c) row += (hx ? S.wc[0][c] : S.wn[0][c]) * v[b][c];
+    acc += (hy ? S.wc[1][b] : S.wn[1][b]) * row;
+  }
+  return acc;
+}
+
 template <typename T, int DIM, int ORDER>
 __device__ __forceinline__ void gather(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
                                        const T (&f)[3], T (&EB)[6]) {
   Shape3<ORDER, T> S;
   shape_all<T, DIM, ORDER>(id, f, S);
+  if constexpr (DIM == 2) {   // E, then B: two memory round trips
+    T v[3][ORDER + 1][ORDER + 1];
+    load_stencil_2d<T, ORDER, 1>(g, F.E[0], S, v[0]);
+    load_stencil_2d<T, ORDER, 2>(g, F.E[1], S, v[1]);
+    load_stencil_2d<T, ORDER, 0>(g, F.E[2], S, v[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    EB[0] = interp_2d<T, ORDER, 1>(S, v[0]);
+    EB[1] = interp_2d<T, ORDER, 2>(S, v[1]);
+    EB[2] = interp_2d<T, ORDER, 0>(S, v[2]);
+    load_stencil_2d<T, ORDER, 2>(g, F.B[0], S, v[0]);
+    load_stencil_2d<T, ORDER, 1>(g, F.B[1], S, v[1]);
+    load_stencil_2d<T, ORDER, 3>(g, F.B[2], S, v[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    EB[3] = interp_2d<T, ORDER, 2>(S, v[0]);
+    EB[4] = interp_2d<T, ORDER, 1>(S, v[1]);
+    EB[5] = interp_2d<T, ORDER, 3>(S, v[2]);
+    return;
+  }
   EB[0] = gather_comp<T, DIM, ORDER, 1>(g, F.E[0], S);
   EB[1] = gather_comp<T, DIM, ORDER, 2>(g, F.E[1], S);
   EB[2] = gather_comp<T, DIM, ORDER, 4>(g, F.E[2], S);

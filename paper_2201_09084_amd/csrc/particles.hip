@@ -44,8 +44,8 @@ template <> struct TileCfg<2> { static constexpr int NODES = 1536; static conste
 template <> struct TileCfg<3> { static constexpr int NODES = 1344; static constexpr int PPT = 4; };
 
 // Fused gather_push + deposit_current over chunks of cell-sorted particles.  A
-// workgroup takes one chunk: either a work item of one sort tile (by_tile: the
-// chunk's particles all belong to one tile) or a fixed range of the sorted array.  It
+// workgroup takes one work item: a chunk of one sort tile (by_tile, 3D: the chunk's
+// particles all belong to one tile) or a range of the sorted array (2D).  It
 // accumulates Esirkepov's current in an LDS box, replicated R times with an odd
 // stride so that lanes that share a node meet in different words and banks, and then
 // adds every non-zero entry to global J once (distinct consecutive addresses).  The
@@ -64,22 +64,20 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   __shared__ int sbox[12];   // min[3], max[3] of the old cells; then the same clipped
   __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
-  int p0, p1, t = -1;
   const int4 no_box = make_int4(0x7FFFFFFF, -0x7FFFFFFF, 0x7FFFFFFF, -0x7FFFFFFF);
-  if constexpr (BY_TILE) {
-    if (blockIdx.x >= tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles]) {   // uniform over the workgroup
-      if (DIM == 2 && ctl.jblk && tid == 0) ctl.jblk[blockIdx.x] = no_box;
-      return;
-    }
-    const int4 item = tw.items[blockIdx.x];
-    p0 = item.x; p1 = item.y; t = item.z;
-  } else {
-    p0 = blockIdx.x * (TPB * PPT);
-    p1 = min(p0 + TPB * PPT, *ctl.count);
-    if (p0 >= p1) {
-      if (DIM == 2 && ctl.jblk && tid == 0) ctl.jblk[blockIdx.x] = no_box;
-      return;
-    }
+  int p0, p1, t = -1;
+  {
+    // by tile: the items of the tiles; else the 2D list (heavy pieces first).  Uniform.
+    const unsigned n_items = BY_TILE ? tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles] : *tw.n_items;
+    int4 item = make_int4(0, 0, -1, 0);
+    if (blockIdx.x < n_items) item = tw.items[blockIdx.x];
+    p0 = __builtin_amdgcn_readfirstlane(item.x);
+    p1 = __builtin_amdgcn_readfirstlane(item.y);
+    if (BY_TILE) t = __builtin_amdgcn_readfirstlane(item.z);
+  }
+  if (p0 >= p1) {
+    if (DIM == 2 && ctl.jblk && tid == 0) ctl.jblk[blockIdx.x] = no_box;
+    return;
   }
   int clo[3] = {-0x3FFFFFFF, -0x3FFFFFFF, -0x3FFFFFFF}, chi[3] = {0x3FFFFFFF, 0x3FFFFFFF, 0x3FFFFFFF};
   if (t >= 0) {   // old cells of the tile grown by the margin
@@ -149,12 +147,13 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     if (BY_TILE && out) atomicAdd(&n_out, out);
   }
   __syncthreads();
+  int sb[12];   // the box words, wave-uniform (scalar registers)
+#pragma unroll
+  for (int k = 0; k < 12; ++k) sb[k] = __builtin_amdgcn_readfirstlane(sbox[k]);
   if (DIM == 2 && ctl.jblk && tid == 0)   // nodes this chunk can deposit to
-    ctl.jblk[blockIdx.x] = sbox[0] <= sbox[3]
-                               ? make_int4(sbox[0] + WLO, sbox[3] + WHI, sbox[1] + WLO, sbox[4] + WHI)
-                               : no_box;
+    ctl.jblk[blockIdx.x] = sb[0] <= sb[3] ? make_int4(sb[0] + WLO, sb[3] + WHI, sb[1] + WLO, sb[4] + WHI) : no_box;
   LdsSink<T> lsink;
-  const bool any = sbox[0] <= sbox[3];
+  const bool any = sb[0] <= sb[3];
   // replicas that fit for a box of n nodes per component (0: does not fit)
   auto reps = [&](int n) {
     const int st = (3 * n) | 1;
@@ -167,21 +166,22 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     int full = 1, clip = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      full *= sbox[3 + d] - sbox[d] + (WHI - WLO) + 1;
-      clip *= sbox[9 + d] - sbox[6 + d] + (WHI - WLO) + 1;
+      full *= sb[3 + d] - sb[d] + (WHI - WLO) + 1;
+      clip *= sb[9 + d] - sb[6 + d] + (WHI - WLO) + 1;
     }
     const int rf = reps(full), rc = reps(clip);
+    const unsigned nout = __builtin_amdgcn_readfirstlane(n_out);
     // the clipped box wins if the whole one does not fit, or if it allows more
     // replicas at the price of at most 1/16 of the chunk going to global memory
-    if (rf == 0 || (rc > rf && 16u * n_out <= (unsigned)(p1 - p0))) o = 6;
+    if (rf == 0 || (rc > rf && 16u * nout <= (unsigned)(p1 - p0))) o = 6;
   }
   int ext[3] = {1, 1, 1}, bmn[3] = {0, 0, 0}, bmx[3] = {0, 0, 0};
   int total = 1;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < DIM) {
-      bmn[d] = sbox[o + d];
-      bmx[d] = sbox[o + 3 + d];
+      bmn[d] = o ? sb[6 + d] : sb[d];
+      bmx[d] = o ? sb[9 + d] : sb[3 + d];
       lsink.lo[d] = bmn[d] + WLO;
       ext[d] = any ? bmx[d] - bmn[d] + (WHI - WLO) + 1 : 1;
     } else {
@@ -255,6 +255,112 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
       atomic_add(&F.J[comp][g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk)], v);
     }
   }
+}
+
+// 2D work list, built after every sort: fixed ranges of `chunk` sorted particles.  A
+// range whose node box does not fit in LDS (sparse particles: its deposits go to
+// global memory, about forty atomics per particle) is split into RANGE_SPLIT items,
+// and those items come first: the workgroups of the pieces start together and land on
+// different compute units, so no unit issues all of a range's global atomics while
+// its other workgroups wait behind them.  The workgroups of the later ranges start as
+// earlier ones finish.  (A work queue with an atomic counter was slower: atomics on
+// one word from every workgroup serialise across the chip.)
+constexpr int RANGE_SPLIT = RANGE_SPLIT_MAX;
+
+// per range: 1 if its box (cells at the sort plus the deposit window and the drift
+// allowance: win1 nodes wider than the cell span per axis) does not fit in `nodes`
+// LDS nodes per component
+__global__ void k_range_classify(TileWork tw, const uint32_t *cell, const int32_t *count, int win1, int nodes) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  const int n = *count;
+  const int nch = (n + tw.chunk - 1) / tw.chunk;
+  if (wave >= nch) return;   // uniform over the wavefront
+  const int p0 = wave * tw.chunk, p1 = min(p0 + tw.chunk, n);
+  int xl = 0x7FFFFFFF, xh = -0x7FFFFFFF, yl = 0x7FFFFFFF, yh = -0x7FFFFFFF;
+  for (int p = p0 + lane; p < p1; p += 64) {
+    const uint32_t c = cell[p];
+    if (c == DEAD) continue;
+    int i, j, k;
+    unpack_cell(2, c, i, j, k);
+    xl = min(xl, i); xh = max(xh, i); yl = min(yl, j); yh = max(yh, j);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    xl = min(xl, __shfl_xor(xl, off)); xh = max(xh, __shfl_xor(xh, off));
+    yl = min(yl, __shfl_xor(yl, off)); yh = max(yh, __shfl_xor(yh, off));
+  }
+  if (lane == 0) {
+    bool heavy = false;
+    if (xl <= xh) {
+      const long total = (long)(xh - xl + win1) * (long)(yh - yl + win1);
+      heavy = ((3 * total) | 1) > 3L * nodes;   // the kernel's LDS test
+    }
+    tw.flags[wave] = heavy ? 1u : 0u;
+  }
+}
+
+// one workgroup: heavy ranges first (RANGE_SPLIT items each), then the others in order;
+// the item count goes to *n_items
+constexpr int ITEMS_TPB = 1024;
+__global__ void __launch_bounds__(ITEMS_TPB) k_range_items(TileWork tw, const int32_t *count) {
+  __shared__ uint32_t sh[ITEMS_TPB];
+  __shared__ uint32_t carry_h, carry_l;
+  const int tid = threadIdx.x;
+  const int n = *count;
+  const int nch = (n + tw.chunk - 1) / tw.chunk;
+  const int piece = (tw.chunk + RANGE_SPLIT - 1) / RANGE_SPLIT;
+  uint32_t h = 0;
+  for (int c = tid; c < nch; c += ITEMS_TPB) h += tw.flags[c];
+  sh[tid] = h;
+  __syncthreads();
+  for (int off = ITEMS_TPB / 2; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] += sh[tid + off];
+    __syncthreads();
+  }
+  const uint32_t n_heavy = sh[0];
+  if (tid == 0) { carry_h = 0u; carry_l = 0u; }
+  __syncthreads();
+  for (int start = 0; start < nch; start += ITEMS_TPB) {
+    const int c = start + tid;
+    const uint32_t f = c < nch ? tw.flags[c] : 0u;
+    const uint32_t v = c < nch ? (f ? (1u << 16) : 1u) : 0u;   // heavy count high, light low
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < ITEMS_TPB; off <<= 1) {   // inclusive scan
+      const uint32_t add = tid >= off ? sh[tid - off] : 0u;
+      __syncthreads();
+      sh[tid] += add;
+      __syncthreads();
+    }
+    const uint32_t ex = sh[tid] - v;
+    if (c < nch) {
+      const int p0 = c * tw.chunk, p1 = min(p0 + tw.chunk, n);
+      if (f) {
+        const int first = (int)((carry_h + (ex >> 16)) * RANGE_SPLIT);
+        for (int k = 0; k < RANGE_SPLIT; ++k) {
+          const int q0 = min(p0 + k * piece, p1), q1 = min(q0 + piece, p1);
+          tw.items[first + k] = make_int4(q0, q1, 0, 0);
+        }
+      } else {
+        tw.items[n_heavy * RANGE_SPLIT + carry_l + (ex & 0xFFFFu)] = make_int4(p0, p1, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (tid == ITEMS_TPB - 1) { carry_h += sh[tid] >> 16; carry_l += sh[tid] & 0xFFFFu; }
+    __syncthreads();
+  }
+  if (tid == 0) *tw.n_items = n_heavy * RANGE_SPLIT + ((uint32_t)nch - n_heavy);
+}
+
+void launch_range_items(const TileWork &tw, const uint32_t *cell, const int32_t *count, int order, int max_ranges,
+                        int drift, hipStream_t s) {
+  if (max_ranges <= 0) return;
+  // WHI - WLO + 1 of the deposit window, plus the cells the particles may drift per
+  // side before the next sort
+  const int win1 = (order == 1 ? 4 : 6) + 2 * drift;
+  hipLaunchKernelGGL(k_range_classify, dim3((max_ranges + 3) / 4), dim3(256), 0, s, tw, cell, count, win1,
+                     TileCfg<2>::NODES);
+  hipLaunchKernelGGL(k_range_items, dim3(1), dim3(ITEMS_TPB), 0, s, tw, count);
 }
 
 // chunks per tile from the sorted key ranges (count: live slots after the sort)
@@ -338,8 +444,9 @@ template <typename T>
 void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
                                const TileWork &tw, int n_slots, int push, hipStream_t s) {
   if (n_slots <= 0) return;
-  // by tile, an upper bound of the item count (every tile's last chunk may be partial)
-  const long nb = (tw.by_tile ? (long)tw.ntiles : 0L) + ((long)n_slots + tw.chunk - 1) / tw.chunk;
+  // an upper bound of the item count: by tile, every tile's last chunk may be partial;
+  // else every range may be split
+  const long nb = deposit_blocks<T>(g, tw, n_slots, true);
   dim3 blk(TPB), grd((unsigned)nb);
 #define PMLPIC_TILES(DIMV, ORD)                                                                                \
   do {                                                                                                         \
@@ -595,8 +702,10 @@ template <typename T>
 int deposit_blocks(const Grid<T> &g, const TileWork &tw, int n_slots, bool tiled) {
   if (n_slots <= 0) return 0;
   if (!tiled) return (n_slots + 255) / 256;
-  return (tw.by_tile ? tw.ntiles : 0) + (n_slots + tw.chunk - 1) / tw.chunk;
+  const int ranges = (n_slots + tw.chunk - 1) / tw.chunk;
+  return tw.by_tile ? tw.ntiles + ranges : RANGE_SPLIT * ranges;
 }
+
 template int deposit_blocks<float>(const Grid<float> &, const TileWork &, int, bool);
 template int deposit_blocks<double>(const Grid<double> &, const TileWork &, int, bool);
 
