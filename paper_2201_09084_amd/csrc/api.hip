@@ -34,7 +34,7 @@ struct Layout {
   size_t off_count = 0, off_pushes = 0;
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
   int ntiles = 1;
-  size_t off_items = 0, max_items = 0, off_jbox = 0, off_jblk = 0, max_push_blocks = 0;
+  size_t off_items = 0, max_items = 0, off_jbox = 0, off_jslot = 0;
   size_t off_rflags = 0, off_nitems = 0, max_ranges = 0;
   size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
   int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
@@ -192,9 +192,8 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_result = take(8 * 8);
   L.off_flags = take(4 * 4);
   L.off_jbox = take(4 * 8);   // two boxes of nodes with current, by step parity
-  // per-workgroup boxes of the 2D deposit launches (the most workgroups of any of them)
-  L.max_push_blocks = std::max<size_t>(L.max_items, (cap + 255) / 256) + 1;
-  L.off_jblk = take(16 * L.max_push_blocks);
+  // slots of the boxes of nodes given current by the 2D deposits, two sets by step parity
+  L.off_jslot = take(2 * 16 * JSLOTS);
   if (p.adjoint_segment > 0) {
     const size_t fb = L.esz * (size_t)L.nelem;          // one field array (multiple of 256 bytes)
     L.seg = p.adjoint_segment;
@@ -299,7 +298,7 @@ struct pml_pic_handle {
     StepCtl c;
     c.count = at<int32_t>(L.off_count);
     c.pushes = at<unsigned long long>(L.off_pushes);
-    c.jblk = nullptr;
+    c.jslot = nullptr;
     return c;
   }
   SortWork sortwork() const {
@@ -622,12 +621,12 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const int ns = (int)h->n_slots;
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
-  int *jbox = h->at<int>(h->L.off_jbox);
+  int *jslot = h->at<int>(h->L.off_jslot);
   for (int it = 0; it < nsteps; ++it) {
     const Fields<T> F = h->fields<T>();
     StepCtl ctl = h->ctl();
-    int *box_cur = jbox + 4 * h->fset;            // this step's box; the other holds the last step's
-    if (one_pass) ctl.jblk = h->at<int4>(h->L.off_jblk);
+    int *slot_cur = jslot + 4 * JSLOTS * h->fset;   // this step's boxes; the other set, the last step's
+    if (one_pass) ctl.jslot = slot_cur;
     if (it < (int)h->snap_state.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_state[it], F.E[0], h->L.fields_bytes, hipMemcpyDeviceToDevice, s));
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
@@ -644,7 +643,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (one_pass) {   // J survives the step; clear the last step's box before depositing
       pt.begin(s);
-      launch_jbox_clear<T>(g, F, jbox + 4 * (1 - h->fset), s);
+      launch_jbox_clear<T>(g, F, jslot + 4 * JSLOTS * (1 - h->fset), slot_cur, s);
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
     } else if (keep_j) {   // J survives the step; clear it before depositing (the three arrays are adjacent)
       pt.begin(s);
@@ -661,11 +660,6 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, s);
       pt.end(s, PML_PIC_PHASE_DEPOSIT);
     }
-    if (one_pass) {   // union of the deposit workgroups' boxes (also with no particles: empty)
-      pt.begin(s);
-      launch_jbox_reduce(ctl.jblk, deposit_blocks<T>(g, h->tilework(), ns, fused && use_sort), box_cur, s);
-      pt.end(s, PML_PIC_PHASE_CLEAR_J);
-    }
     if (it < (int)h->snap_J.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_J[it], F.J[0], h->L.J_bytes, hipMemcpyDeviceToDevice, s));
     if (sep_damp && current_alpha(h->p.alpha_mode)) {
@@ -675,7 +669,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (one_pass) {
       pt.begin(s);
-      launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), box_cur,
+      launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), slot_cur,
                              !sep_damp && current_alpha(h->p.alpha_mode), s);
       pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
       h->fset = 1 - h->fset;
@@ -791,6 +785,14 @@ static int create_handle(const pml_pic_params *params, void *device_workspace, s
   build_tables(h);
   hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) {   // current-box slots start empty
+    std::vector<int> empty(2 * 4 * JSLOTS);
+    for (int k = 0; k < 2 * JSLOTS; ++k) {
+      empty[4 * k] = 0x7FFFFFFF; empty[4 * k + 1] = -0x7FFFFFFF;
+      empty[4 * k + 2] = 0x7FFFFFFF; empty[4 * k + 3] = -0x7FFFFFFF;
+    }
+    e = hipMemcpy(h->ws + L.off_jslot, empty.data(), sizeof(int) * empty.size(), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     *err = std::string("HIP error while clearing the workspace: ") + hipGetErrorString(e);
     delete h;

@@ -35,8 +35,10 @@ __global__ void __launch_bounds__(256) k_batch_fused_2d(const RunDesc<T> *__rest
     const Grid<T> g = runs[w.x].g;
     const Fields<T> src = parity ? runs[w.x].F2 : runs[w.x].F;
     const Fields<T> dst = parity ? runs[w.x].F : runs[w.x].F2;
-    fused_segment_2d(g, src, dst, runs[w.x].jbox + 4 * parity, w.y, w.z, w.w, current_alpha(runs[w.x].alpha_mode),
-                     lane);
+    const int *jb = runs[w.x].jbox + 4 * parity;
+    const int4 box = make_int4(__builtin_amdgcn_readfirstlane(jb[0]), __builtin_amdgcn_readfirstlane(jb[1]),
+                               __builtin_amdgcn_readfirstlane(jb[2]), __builtin_amdgcn_readfirstlane(jb[3]));
+    fused_segment_2d(g, src, dst, box, w.y, w.z, w.w, current_alpha(runs[w.x].alpha_mode), lane);
   }
 }
 

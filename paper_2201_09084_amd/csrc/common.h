@@ -153,9 +153,35 @@ constexpr int N_PUSH_COUNTERS = 256;   // push tallies are spread over this many
 struct StepCtl {
   int32_t *count;                 // device: live particle slots in use
   unsigned long long *pushes;     // N_PUSH_COUNTERS partial push counts
-  int4 *jblk;                     // 2D one-pass runs: per workgroup of the deposit, the box of
-                                  // nodes it gave current (x lo, x hi, y lo, y hi); else null
+  int *jslot;                     // 2D one-pass runs: JSLOTS boxes of nodes given current this
+                                  // step (x lo, x hi, y lo, y hi each); workgroup b merges its
+                                  // box into slot b mod JSLOTS; else null
 };
+// Slots of the boxes of nodes that received current: workgroups merge into different
+// slots (atomics on one word from every workgroup serialise across the chip), and a
+// wavefront reads all of them (one slot per lane) to form the union.
+constexpr int JSLOTS = 64;
+__device__ __forceinline__ void jslot_merge(int *slots, int xlo, int xhi, int ylo, int yhi) {
+  if (xlo > xhi) return;
+  int *s = slots + 4 * (int)(blockIdx.x % JSLOTS);
+  atomicMin(&s[0], xlo); atomicMax(&s[1], xhi); atomicMin(&s[2], ylo); atomicMax(&s[3], yhi);
+}
+// union of the slots, uniform over the wavefront (every lane calls it)
+__device__ __forceinline__ int4 jslot_union(const int *slots) {
+  const int l = (int)(threadIdx.x & 63);
+  int4 b = make_int4(0x7FFFFFFF, -0x7FFFFFFF, 0x7FFFFFFF, -0x7FFFFFFF);
+  if (l < JSLOTS) {
+    const auto *p = gptr(slots) + 4 * l;
+    b = make_int4(p[0], p[1], p[2], p[3]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    b.x = min(b.x, __shfl_xor(b.x, off)); b.y = max(b.y, __shfl_xor(b.y, off));
+    b.z = min(b.z, __shfl_xor(b.z, off)); b.w = max(b.w, __shfl_xor(b.w, off));
+  }
+  return make_int4(__builtin_amdgcn_readfirstlane(b.x), __builtin_amdgcn_readfirstlane(b.y),
+                   __builtin_amdgcn_readfirstlane(b.z), __builtin_amdgcn_readfirstlane(b.w));
+}
 
 template <typename T>
 void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool half, hipStream_t s);
@@ -227,12 +253,11 @@ void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int
 
 // adjoint of the fields: LT[c] (part driven along a+2, or the whole component where it
 // is not split), LA[c] (part driven along a+1 minus LT), c = E_x .. B_z
-// J <- 0 over the box `prev` (the previous step's deposits)
+// J <- 0 over the union of the slots `prev` (the previous step's deposits); the slots
+// `cur` are emptied for this step's deposits
 template <typename T>
-void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, hipStream_t s);
-// cur <- union of the n per-workgroup boxes
-void launch_jbox_reduce(const int4 *jblk, int n, int *cur, hipStream_t s);
-// workgroups of the deposit launch of a step (entries of the per-workgroup boxes)
+void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, int *cur, hipStream_t s);
+// workgroups of the deposit launch of a step
 template <typename T>
 int deposit_blocks(const Grid<T> &g, const TileWork &tw, int n_slots, bool tiled);
 
@@ -240,10 +265,10 @@ int deposit_blocks(const Grid<T> &g, const TileWork &tw, int n_slots, bool tiled
 // one halo column on the left and two on the right)
 constexpr int FW = 61;
 
-// update_yee_pml in one pass over the fields (2D): reads F (and its J, not cleared),
-// writes the new E, B (and split parts) to D
+// update_yee_pml in one pass over the fields (2D): reads F (and its J, not cleared, inside
+// the union of the slots `jslot`), writes the new E, B (and split parts) to D
 template <typename T>
-void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jbox, bool fuse_alpha,
+void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jslot, bool fuse_alpha,
                          hipStream_t s);
 
 template <typename T>

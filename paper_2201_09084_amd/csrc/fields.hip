@@ -22,7 +22,7 @@ namespace pmlpic {
 
 // one-pass update_yee_pml in 2D: one wavefront per (strip of FW columns, segment of rows)
 template <typename T>
-__global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields<T> D, const int *jbox, int nstrips,
+__global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields<T> D, const int *jslot, int nstrips,
                                                   int rows, int nseg, bool fuse_alpha) {
   // workgroup b runs on XCD b mod 8: give each XCD a contiguous eighth of the
   // wavefronts so that neighbouring strips share its L2 (gridDim is a multiple of 8)
@@ -32,14 +32,19 @@ __global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields
   if (w >= nstrips * nseg) return;   // whole wavefront
   const int strip = w % nstrips, seg = w / nstrips;
   const int y0 = seg * rows, y1 = min(y0 + rows, g.M[1] + 1);
-  fused_segment_2d(g, F, D, jbox, strip, y0, y1, fuse_alpha, (int)(threadIdx.x & 63));
+  fused_segment_2d(g, F, D, jslot_union(jslot), strip, y0, y1, fuse_alpha, (int)(threadIdx.x & 63));
 }
 
-// J <- 0 over the box `prev`
+// J <- 0 over the union of the slots `prev`; the slots `cur` emptied
 template <typename T>
-__global__ void __launch_bounds__(256) k_jbox_clear(Grid<T> g, Fields<T> F, const int *prev) {
-  const int x0 = max(prev[0], -G), x1 = min(prev[1], g.M[0] + G);
-  const int y0 = max(prev[2], -G), y1 = min(prev[3], g.M[1] + G);
+__global__ void __launch_bounds__(256) k_jbox_clear(Grid<T> g, Fields<T> F, const int *prev, int *cur) {
+  if (blockIdx.x == 0 && threadIdx.x < JSLOTS) {   // this step's slots start empty
+    auto *p = gptr(cur) + 4 * threadIdx.x;
+    p[0] = 0x7FFFFFFF; p[1] = -0x7FFFFFFF; p[2] = 0x7FFFFFFF; p[3] = -0x7FFFFFFF;
+  }
+  const int4 b = jslot_union(prev);
+  const int x0 = max(b.x, -G), x1 = min(b.y, g.M[0] + G);
+  const int y0 = max(b.z, -G), y1 = min(b.w, g.M[1] + G);
   if (x0 > x1 || y0 > y1) return;
   const int w = x1 - x0 + 1;
   const long n = (long)w * (y1 - y0 + 1);
@@ -52,13 +57,13 @@ __global__ void __launch_bounds__(256) k_jbox_clear(Grid<T> g, Fields<T> F, cons
 }
 
 template <typename T>
-void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, hipStream_t s) {
+void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, int *cur, hipStream_t s) {
   const long n = (long)(g.M[0] + 1 + 2 * G) * (g.M[1] + 1 + 2 * G);
   const int blocks = (int)std::min<long>(1024, (n + 255) / 256);
-  hipLaunchKernelGGL((k_jbox_clear<T>), dim3(blocks), dim3(256), 0, s, g, F, prev);
+  hipLaunchKernelGGL((k_jbox_clear<T>), dim3(blocks), dim3(256), 0, s, g, F, prev, cur);
 }
-template void launch_jbox_clear<float>(const Grid<float> &, const Fields<float> &, const int *, hipStream_t);
-template void launch_jbox_clear<double>(const Grid<double> &, const Fields<double> &, const int *, hipStream_t);
+template void launch_jbox_clear<float>(const Grid<float> &, const Fields<float> &, const int *, int *, hipStream_t);
+template void launch_jbox_clear<double>(const Grid<double> &, const Fields<double> &, const int *, int *, hipStream_t);
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
@@ -118,13 +123,13 @@ void fused_2d_shape(int M0, int M1, int &nstrips, int &rows, int &nseg) {
 }
 
 template <typename T>
-void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jbox, bool fuse_alpha,
+void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jslot, bool fuse_alpha,
                          hipStream_t s) {
   int nstrips, rows, nseg;
   fused_2d_shape(g.M[0], g.M[1], nstrips, rows, nseg);
   const int waves = nstrips * nseg;
   const int blocks = ((waves + 3) / 4 + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused_2d<T>), dim3(blocks), dim3(256), 0, s, g, F, D, jbox, nstrips, rows, nseg,
+  hipLaunchKernelGGL((k_fused_2d<T>), dim3(blocks), dim3(256), 0, s, g, F, D, jslot, nstrips, rows, nseg,
                      fuse_alpha);
 }
 template void launch_fused_fields<float>(const Grid<float> &, const Fields<float> &, const Fields<float> &,

@@ -108,7 +108,7 @@ struct RowIn {
 // iteration (the shuffles need them); only the lanes and rows owned are written.
 template <typename T>
 __device__ __forceinline__ void fused_segment_2d(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D,
-                                                 const int *jbox, int strip, int y0, int y1, bool fuse_alpha,
+                                                 int4 jbox, int strip, int y0, int y1, bool fuse_alpha,
                                                  int lane) {
   const int M0 = g.M[0], M1 = g.M[1];
   const int i = strip * FW - 1 + lane;
@@ -127,8 +127,7 @@ __device__ __forceinline__ void fused_segment_2d(const Grid<T> &g, const Fields<
   auto ytab = [&](int j, YTab<T> &Y) {
     load_tabs(g, 1, min(max(j, -G), M1 + G), Y.ehC, Y.ghkC, Y.sigC, Y.eN, Y.gN, Y.gkN, Y.sigN, Y.aC, Y.aN);
   };
-  const int jb0 = __builtin_amdgcn_readfirstlane(jbox[0]), jb1 = __builtin_amdgcn_readfirstlane(jbox[1]);
-  const int jb2 = __builtin_amdgcn_readfirstlane(jbox[2]), jb3 = __builtin_amdgcn_readfirstlane(jbox[3]);
+  const int jb0 = jbox.x, jb1 = jbox.y, jb2 = jbox.z, jb3 = jbox.w;   // wave-uniform
   const bool jcol = i >= jb0 && i <= jb1;
   auto fetch = [&](int j, const YTab<T> &Y, RowIn<T> &r) {
     r.ex1 = ld(F.E[0], j + 1);

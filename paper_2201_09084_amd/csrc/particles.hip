@@ -29,9 +29,9 @@ __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Par
   int rng[4] = {0, -1, 0, -1};
   if (p < n_slots && p < count) active = push_one<T, DIM, ORDER>(g, F, P, old, p, push, fused, rng);
   count_pushes(ctl.pushes, active);
-  if (DIM == 2 && fused && ctl.jblk) {
+  if (DIM == 2 && fused && ctl.jslot) {
     const int4 b = block_box(rng[0], rng[1], rng[2], rng[3]);
-    if (threadIdx.x == 0) ctl.jblk[blockIdx.x] = b;
+    if (threadIdx.x == 0) jslot_merge(ctl.jslot, b.x, b.y, b.z, b.w);
   }
 }
 
@@ -64,7 +64,6 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   __shared__ int sbox[12];   // min[3], max[3] of the old cells; then the same clipped
   __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
-  const int4 no_box = make_int4(0x7FFFFFFF, -0x7FFFFFFF, 0x7FFFFFFF, -0x7FFFFFFF);
   int p0, p1, t = -1;
   {
     // by tile: the items of the tiles; else the 2D list (heavy pieces first).  Uniform.
@@ -75,10 +74,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     p1 = __builtin_amdgcn_readfirstlane(item.y);
     if (BY_TILE) t = __builtin_amdgcn_readfirstlane(item.z);
   }
-  if (p0 >= p1) {
-    if (DIM == 2 && ctl.jblk && tid == 0) ctl.jblk[blockIdx.x] = no_box;
-    return;
-  }
+  if (p0 >= p1) return;
   int clo[3] = {-0x3FFFFFFF, -0x3FFFFFFF, -0x3FFFFFFF}, chi[3] = {0x3FFFFFFF, 0x3FFFFFFF, 0x3FFFFFFF};
   if (t >= 0) {   // old cells of the tile grown by the margin
     const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
@@ -150,8 +146,8 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   int sb[12];   // the box words, wave-uniform (scalar registers)
 #pragma unroll
   for (int k = 0; k < 12; ++k) sb[k] = __builtin_amdgcn_readfirstlane(sbox[k]);
-  if (DIM == 2 && ctl.jblk && tid == 0)   // nodes this chunk can deposit to
-    ctl.jblk[blockIdx.x] = sb[0] <= sb[3] ? make_int4(sb[0] + WLO, sb[3] + WHI, sb[1] + WLO, sb[4] + WHI) : no_box;
+  if (DIM == 2 && ctl.jslot && tid == 0 && sb[0] <= sb[3])   // nodes this chunk can deposit to
+    jslot_merge(ctl.jslot, sb[0] + WLO, sb[3] + WHI, sb[1] + WLO, sb[4] + WHI);
   LdsSink<T> lsink;
   const bool any = sb[0] <= sb[3];
   // replicas that fit for a box of n nodes per component (0: does not fit)
@@ -418,9 +414,9 @@ __global__ void __launch_bounds__(256) k_deposit(Grid<T> g, Fields<T> F, Parts<T
     for (int d = 0; d < DIM; ++d) inside = inside && i1[d] >= 0 && i1[d] < g.M[d];
     if (!inside) P.cell[p] = DEAD;
   }
-  if (DIM == 2 && ctl.jblk) {
+  if (DIM == 2 && ctl.jslot) {
     const int4 b = block_box(rng[0], rng[1], rng[2], rng[3]);
-    if (threadIdx.x == 0) ctl.jblk[blockIdx.x] = b;
+    if (threadIdx.x == 0) jslot_merge(ctl.jslot, b.x, b.y, b.z, b.w);
   }
 }
 
@@ -681,21 +677,6 @@ void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, Sor
   hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, sw.counts, sw.nkeys, sw.blocksums);
   hipLaunchKernelGGL((k_sort_scatter<T>), grd, blk, 0, s, g.dim, src, dst, sw, ctl.count, n_slots);
   hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, new_count, ctl.count);
-}
-
-// union of the per-workgroup boxes (one workgroup of 1024 threads)
-__global__ void __launch_bounds__(1024) k_jbox_reduce(const int4 *jblk, int n, int *cur) {
-  int xlo = 0x7FFFFFFF, xhi = -0x7FFFFFFF, ylo = 0x7FFFFFFF, yhi = -0x7FFFFFFF;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const int4 b = jblk[k];
-    if (b.x <= b.y) { xlo = min(xlo, b.x); xhi = max(xhi, b.y); ylo = min(ylo, b.z); yhi = max(yhi, b.w); }
-  }
-  const int4 b = block_box(xlo, xhi, ylo, yhi);
-  if (threadIdx.x == 0) { cur[0] = b.x; cur[1] = b.y; cur[2] = b.z; cur[3] = b.w; }
-}
-
-void launch_jbox_reduce(const int4 *jblk, int n, int *cur, hipStream_t s) {
-  hipLaunchKernelGGL(k_jbox_reduce, dim3(1), dim3(1024), 0, s, jblk, n, cur);
 }
 
 template <typename T>
