@@ -497,52 +497,67 @@ __device__ __forceinline__ void key_run(uint32_t key, int lane, int &first, int 
 }
 
 // Histogram of the sort keys with the rank of every particle among equal keys.
-// A workgroup takes a chunk of HIST_TPB*HIST_PPT consecutive particles; runs of equal
-// keys in a wavefront take one counter update; if the chunk's key range fits, the
-// counters live in LDS and each distinct key costs one global atomic per chunk.
+// A workgroup takes a chunk of HIST_TPB*HIST_PPT consecutive particles (in the order
+// of the previous sort) and counts in LDS: one block of tile-cells counters per sort
+// tile its particles now occupy, the tiles entered in a small table (a chunk spans a
+// few tiles, but their keys can lie far apart: the next row of tiles starts a whole
+// row of tiles later).  Runs of equal keys in a wavefront take one counter update, and
+// each distinct key costs one global atomic per chunk.  A chunk that meets more tiles
+// than the table holds counts straight in global memory.
 constexpr int HIST_TPB = 256;
 constexpr int HIST_PPT = 4;
 constexpr int HIST_LDS = 4096;
+constexpr int HIST_MAX_TILES = 64;
+constexpr uint32_t NO_TILE = 0xFFFFFFFFu;
 
 template <typename T>
 __global__ void __launch_bounds__(HIST_TPB) k_sort_hist(int dim, Parts<T> P, SortWork sw, StepCtl ctl, int n_slots) {
   __shared__ uint32_t cnt[HIST_LDS];
-  __shared__ uint32_t kmin_s, kmax_s;
+  __shared__ uint32_t stile[HIST_MAX_TILES];
+  __shared__ int overflow;
   const int tid = threadIdx.x, lane = tid & 63;
   const int count = min(*ctl.count, n_slots);
   const int base = blockIdx.x * (HIST_TPB * HIST_PPT);
-  uint32_t key[HIST_PPT];
-  if (tid == 0) { kmin_s = 0xFFFFFFFFu; kmax_s = 0u; }
+  const uint32_t tc = (uint32_t)(sw.tile[0] * sw.tile[1] * sw.tile[2]);
+  const int nslot = (int)min((uint32_t)HIST_MAX_TILES, (uint32_t)HIST_LDS / tc);   // 0: no LDS counting
+  if (tid < HIST_MAX_TILES) stile[tid] = NO_TILE;
+  if (tid == 0) overflow = nslot == 0;
   __syncthreads();
-  uint32_t lmin = 0xFFFFFFFFu, lmax = 0u;
+  uint32_t key[HIST_PPT];
+  int slot[HIST_PPT];
 #pragma unroll
   for (int k = 0; k < HIST_PPT; ++k) {
     const int p = base + k * HIST_TPB + tid;
     key[k] = 0xFFFFFFFFu;
+    slot[k] = -1;
     if (p < count) {
       const uint32_t c = P.cell[p];
       if (c != DEAD) {
         int i, j, kk;
         unpack_cell(dim, c, i, j, kk);
         key[k] = cell_key(dim, sw, i, j, kk);
-        lmin = min(lmin, key[k]);
-        lmax = max(lmax, key[k]);
       }
     }
+    // the table slot of my tile: the first lane of each run of equal tiles looks it up
+    // (open addressing), the others take its answer
+    const uint32_t t = key[k] != 0xFFFFFFFFu ? key[k] / tc : NO_TILE;
+    int first, next;
+    key_run(t, lane, first, next);
+    int sl = -1;
+    if (lane == first && t != NO_TILE && nslot > 0) {
+      for (int a = 0; a < nslot; ++a) {
+        const int h = (int)((t + (uint32_t)a) % (uint32_t)nslot);
+        const uint32_t v = atomicCAS(&stile[h], NO_TILE, t);
+        if (v == NO_TILE || v == t) { sl = h; break; }
+      }
+      if (sl < 0) overflow = 1;
+    }
+    slot[k] = __shfl(sl, first);
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {   // wavefront first: one LDS update per wave
-    lmin = min(lmin, (uint32_t)__shfl_xor(lmin, off));
-    lmax = max(lmax, (uint32_t)__shfl_xor(lmax, off));
-  }
-  if (lane == 0 && lmin <= lmax) { atomicMin(&kmin_s, lmin); atomicMax(&kmax_s, lmax); }
   __syncthreads();
-  const uint32_t kmin = kmin_s, kmax = kmax_s;
-  const bool any = kmin <= kmax;
-  const bool local = any && (kmax - kmin) < (uint32_t)HIST_LDS;
-  if (local) {
-    for (uint32_t e = tid; e <= kmax - kmin; e += HIST_TPB) cnt[e] = 0u;
-  }
+  const bool local = overflow == 0;   // uniform
+  if (local)
+    for (int e = tid; e < nslot * (int)tc; e += HIST_TPB) cnt[e] = 0u;
   __syncthreads();
   uint32_t r[HIST_PPT];
 #pragma unroll
@@ -552,23 +567,25 @@ __global__ void __launch_bounds__(HIST_TPB) k_sort_hist(int dim, Parts<T> P, Sor
     uint32_t b = 0;
     if (lane == first && key[k] != 0xFFFFFFFFu) {
       const uint32_t n = (uint32_t)(next - lane);
-      b = local ? atomicAdd(&cnt[key[k] - kmin], n) : atomicAdd(&sw.counts[key[k]], n);
+      b = local ? atomicAdd(&cnt[slot[k] * tc + key[k] % tc], n) : atomicAdd(&sw.counts[key[k]], n);
     }
     b = __shfl(b, first);
     r[k] = b + (uint32_t)(lane - first);
   }
   if (local) {
     __syncthreads();
-    for (uint32_t e = tid; e <= kmax - kmin; e += HIST_TPB) {
+    for (int e = tid; e < nslot * (int)tc; e += HIST_TPB) {
+      const uint32_t t = stile[e / tc];
+      if (t == NO_TILE) continue;
       const uint32_t c = cnt[e];
-      if (c) cnt[e] = atomicAdd(&sw.counts[kmin + e], c);
+      if (c) cnt[e] = atomicAdd(&sw.counts[t * tc + e % tc], c);
     }
     __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < HIST_PPT; ++k) {
     const int p = base + k * HIST_TPB + tid;
-    if (key[k] != 0xFFFFFFFFu) sw.rank[p] = local ? cnt[key[k] - kmin] + r[k] : r[k];
+    if (key[k] != 0xFFFFFFFFu) sw.rank[p] = local ? cnt[slot[k] * tc + key[k] % tc] + r[k] : r[k];
   }
 }
 

@@ -340,3 +340,26 @@ def test_weight_damping_matches_oracle(dim, flags, precision):
     dg, do = g.diagnose(), o.diagnose()
     tol = 1e-10 if precision == 64 else 1e-4
     assert abs(dg["rho_max"] - do["rho_max"]) <= tol * do["rho_max"]
+
+
+def test_dense_and_sparse_ranges_2d():
+    """A dense cluster (ranges of 1024 sorted particles whose node box fits in LDS) next
+    to a sparse population (ranges whose box does not: split into four pieces that
+    deposit to global memory, listed first), over several sort intervals."""
+    cfg = W.SimConfig(dim=2, n=(120, 100, 1), pml=((10, 10), (10, 10), (0, 0)), dt=0.7, shape_order=2,
+                      alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.cubic_profile(3.2), push=1, precision=64,
+                      tile=(16, 16, 1), sort_interval=4)
+    rng = np.random.default_rng(77)
+    n_dense, n_sparse = 5000, 3000
+    xd = np.array([60.0, 50.0]) + rng.normal(0.0, 1.5, (n_dense, 2))
+    xs = rng.uniform([-8.0, -8.0], [128.0, 108.0], (n_sparse, 2))
+    x = np.vstack([xd, xs])
+    u = rng.normal(0.0, 0.8, (n_dense + n_sparse, 3))
+    parts = W.Particles(x=x, u=u, w=rng.uniform(0.5, 1.5, n_dense + n_sparse))
+    g, o = both(cfg, parts, flags=B.FLAG_KEEP_CURRENT)
+    for k in range(3):
+        g.step(5)
+        o.step(5)
+        compare_fields(g, o, cfg, 1e-10, "step %d" % (5 * k + 5))
+        compare_current(g, o, 1e-10, "step %d" % (5 * k + 5))
+        compare_particles(g, o, 1e-10, 1e-10, "step %d" % (5 * k + 5))
