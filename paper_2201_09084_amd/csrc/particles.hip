@@ -67,6 +67,8 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   int p0, p1, t = -1;
   {
     // by tile: the items of the tiles; else the 2D list (heavy pieces first).  Uniform.
+    // (Giving each XCD a contiguous eighth of the 3D list cut the fetched bytes by 3x
+    // but ran 5% slower: the order below spreads the work of every region over all XCDs.)
     const unsigned n_items = BY_TILE ? tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles] : *tw.n_items;
     int4 item = make_int4(0, 0, -1, 0);
     if (blockIdx.x < n_items) item = tw.items[blockIdx.x];
