@@ -27,6 +27,7 @@ struct Layout {
   int64_t cap = 0;
   size_t off_field[15] = {};   // E0-2, B0-2, Ea0-2, Ba0-2, J0-2
   size_t off_alt[12] = {};     // second set of E, B, Ea, Ba for the out-of-place 2D update
+  size_t off_altj[3] = {};     // second current buffer (2D one-pass runs, by step parity)
   bool has_alt = false;
   size_t off_tab = 0;
   size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_lam[2] = {}, off_id[2] = {};
@@ -156,8 +157,10 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   for (int a = 0; a < 15; ++a) L.off_field[a] = take(L.esz * (size_t)L.nelem);
   // the one-pass 2D field update reads one set of arrays and writes the other
   L.has_alt = p.dim == 2 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS);
-  if (L.has_alt)
+  if (L.has_alt) {
     for (int a = 0; a < 12; ++a) L.off_alt[a] = take(L.esz * (size_t)L.nelem);
+    for (int a = 0; a < 3; ++a) L.off_altj[a] = take(L.esz * (size_t)L.nelem);
+  }
   L.off_tab = take(L.esz * (3 * T_NKIND * (size_t)L.ntab + 3 * PROF_N));
   const size_t cap = (size_t)std::max<int64_t>(L.cap, 1);
   for (int b = 0; b < 2; ++b) {
@@ -192,8 +195,9 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   L.off_result = take(8 * 8);
   L.off_flags = take(4 * 4);
   L.off_jbox = take(4 * 8);   // two boxes of nodes with current, by step parity
-  // slots of the boxes of nodes given current by the 2D deposits, two sets by step parity
-  L.off_jslot = take(2 * 16 * JSLOTS);
+  // slots of the boxes of nodes given current by the 2D deposits, three sets in rotation
+  // (this step's, the last step's being cleared, the next step's being emptied)
+  L.off_jslot = take(3 * 16 * JSLOTS);
   if (p.adjoint_segment > 0) {
     const size_t fb = L.esz * (size_t)L.nelem;          // one field array (multiple of 256 bytes)
     L.seg = p.adjoint_segment;
@@ -221,6 +225,7 @@ struct pml_pic_handle {
   hipStream_t stream = nullptr;
   std::string err;
   int cur = 0;               // active particle buffer
+  int jphase = 0;            // 2D one-pass: steps taken (rotation of the box slots)
   int fset = 0;              // active set of field arrays
   int64_t n_slots = 0;       // upper bound of used particle slots
   int64_t n_added = 0;
@@ -254,6 +259,11 @@ struct pml_pic_handle {
     g.sy = L.sy; g.sz = L.sz; g.base = L.base; g.nelem = L.nelem;
     g.dt = (T)p.dt;
     g.qdt_2m = (T)(p.charge * p.dt / (2.0 * p.mass));
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      const double ib = b < p.dim ? 1.0 / p.dx[b] : 1.0, ic = c < p.dim ? 1.0 / p.dx[c] : 1.0;
+      g.jcoef[a] = (T)(ib * ic / p.dt);
+    }
     g.charge = (T)p.charge;
     g.tab = at<T>(L.off_tab);
     g.ntab = L.ntab;
@@ -276,6 +286,10 @@ struct pml_pic_handle {
     return F;
   }
   template <typename T> Fields<T> fields() const { return fields_set<T>(fset); }
+  // the current buffer of parity k (2D one-pass runs keep two)
+  template <typename T> T *jbuf(int k, int a) const {
+    return at<T>((k && L.has_alt) ? L.off_altj[a] : L.off_field[12 + a]);
+  }
   template <typename T> Parts<T> parts(int b) const {
     Parts<T> P;
     P.cell = at<uint32_t>(L.off_cell[b]);
@@ -497,7 +511,9 @@ int get_current_t(pml_pic_handle *h, double *out) {
   const bool alpha_in_update = !(h->p.flags & PML_PIC_FLAG_SEPARATE_DAMP) && current_alpha(h->p.alpha_mode);
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int a = 0; a < 3; ++a) {
-    HIPCHK(h, hipMemcpy(buf.data(), h->at<T>(L.off_field[12 + a]), sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
+    // 2D one-pass runs: the buffer of the last step (the parity flipped after it)
+    T *src = L.has_alt ? h->jbuf<T>(1 - h->fset, a) : h->at<T>(L.off_field[12 + a]);
+    HIPCHK(h, hipMemcpy(buf.data(), src, sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
     for (int k = 0; k < L.nn[2]; ++k)
       for (int j = 0; j < L.nn[1]; ++j)
         for (int i = 0; i < L.nn[0]; ++i) {
@@ -623,10 +639,20 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
   int *jslot = h->at<int>(h->L.off_jslot);
   for (int it = 0; it < nsteps; ++it) {
-    const Fields<T> F = h->fields<T>();
+    Fields<T> F = h->fields<T>();
     StepCtl ctl = h->ctl();
-    int *slot_cur = jslot + 4 * JSLOTS * h->fset;   // this step's boxes; the other set, the last step's
-    if (one_pass) ctl.jslot = slot_cur;
+    const int ph = h->jphase % 3;
+    int *slot_cur = jslot + 4 * JSLOTS * ph;                 // this step's boxes
+    JClear<T> jc{{nullptr, nullptr, nullptr}, nullptr, nullptr};
+    if (one_pass) {
+      ctl.jslot = slot_cur;
+      for (int a = 0; a < 3; ++a) {
+        F.J[a] = h->jbuf<T>(h->fset, a);        // deposited this step
+        jc.J[a] = h->jbuf<T>(1 - h->fset, a);   // the last step's, cleared during this step
+      }
+      jc.prev = jslot + 4 * JSLOTS * ((ph + 2) % 3);
+      jc.next = jslot + 4 * JSLOTS * ((ph + 1) % 3);
+    }
     if (it < (int)h->snap_state.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_state[it], F.E[0], h->L.fields_bytes, hipMemcpyDeviceToDevice, s));
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
@@ -641,18 +667,19 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       h->since_sort = 0;
       h->sort_pending = false;
     }
-    if (one_pass) {   // J survives the step; clear the last step's box before depositing
+    const bool tiled = fused && use_sort && ns > 0;
+    if (one_pass && !tiled) {   // the tiled deposit clears the other buffer itself
       pt.begin(s);
-      launch_jbox_clear<T>(g, F, jslot + 4 * JSLOTS * (1 - h->fset), slot_cur, s);
+      launch_jbox_clear<T>(g, jc, s);
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
-    } else if (keep_j) {   // J survives the step; clear it before depositing (the three arrays are adjacent)
+    } else if (!one_pass && keep_j) {   // J survives the step; clear it before depositing (the three arrays are adjacent)
       pt.begin(s);
       HIPCHK(h, hipMemsetAsync(F.J[0], 0, 3 * jbytes, s));
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
     }
     const Parts<T> P = h->parts<T>(h->cur);
     pt.begin(s);
-    if (fused && use_sort) launch_push_deposit_tiles<T>(g, F, P, ctl, h->tilework(), ns, h->p.push, s);
+    if (fused && use_sort) launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);
     else launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
     pt.end(s, PML_PIC_PHASE_PUSH);
     if (!fused) {
@@ -673,6 +700,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
                              !sep_damp && current_alpha(h->p.alpha_mode), s);
       pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
       h->fset = 1 - h->fset;
+      h->jphase++;
     } else {
       pt.begin(s);
       launch_update_B<T>(g, F, true, s);
@@ -786,8 +814,8 @@ static int create_handle(const pml_pic_params *params, void *device_workspace, s
   hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) {   // current-box slots start empty
-    std::vector<int> empty(2 * 4 * JSLOTS);
-    for (int k = 0; k < 2 * JSLOTS; ++k) {
+    std::vector<int> empty(3 * 4 * JSLOTS);
+    for (int k = 0; k < 3 * JSLOTS; ++k) {
       empty[4 * k] = 0x7FFFFFFF; empty[4 * k + 1] = -0x7FFFFFFF;
       empty[4 * k + 2] = 0x7FFFFFFF; empty[4 * k + 3] = -0x7FFFFFFF;
     }

@@ -62,6 +62,8 @@ struct Grid {
   T dt;
   T inv_dx[3];
   T qdt_2m;            // charge dt / (2 mass)
+  T jcoef[3];          // Esirkepov factor of J_a: (1/dx_b)(1/dx_c)/dt over the other two axes
+                       // (1/dx = 1 on the invariant axis of a 2D run)
   T charge;
   const T *tab;        // [3][T_NKIND][ntab], entry i + G for index i in [-G, M+G]
   int ntab;
@@ -183,6 +185,37 @@ __device__ __forceinline__ int4 jslot_union(const int *slots) {
                    __builtin_amdgcn_readfirstlane(b.z), __builtin_amdgcn_readfirstlane(b.w));
 }
 
+// 2D one-pass runs keep J in two buffers by step parity: while the deposit of a step
+// fills one, the other (consumed by the previous step's field update) is cleared over
+// that step's node box, and the slots of the next step are emptied.  prev = null: none.
+template <typename T>
+struct JClear {
+  T *J[3];
+  const int *prev;   // JSLOTS boxes of the step whose current is cleared
+  int *next;         // JSLOTS boxes of the next step, emptied
+};
+// inside a kernel: every workgroup clears its share (grid-stride), workgroup 0 empties
+// `next`; all threads of the workgroup call it
+template <typename T>
+__device__ __forceinline__ void jclear_share(const Grid<T> &g, const JClear<T> &jc) {
+  if (blockIdx.x == 0 && threadIdx.x < JSLOTS) {
+    auto *p = gptr(jc.next) + 4 * threadIdx.x;
+    p[0] = 0x7FFFFFFF; p[1] = -0x7FFFFFFF; p[2] = 0x7FFFFFFF; p[3] = -0x7FFFFFFF;
+  }
+  const int4 b = jslot_union(jc.prev);
+  const int x0 = max(b.x, -G), x1 = min(b.y, g.M[0] + G);
+  const int y0 = max(b.z, -G), y1 = min(b.w, g.M[1] + G);
+  if (x0 > x1 || y0 > y1) return;
+  const int w = x1 - x0 + 1, n = w * (y1 - y0 + 1);
+  const int sy = (int)g.sy, q0 = (int)g.base;
+  for (int e = (int)(blockIdx.x * blockDim.x + threadIdx.x); e < n; e += (int)(gridDim.x * blockDim.x)) {
+    const int q = q0 + x0 + e % w + (y0 + e / w) * sy;
+    gptr(jc.J[0])[q] = T(0);
+    gptr(jc.J[1])[q] = T(0);
+    gptr(jc.J[2])[q] = T(0);
+  }
+}
+
 template <typename T>
 void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool half, hipStream_t s);
 template <typename T>
@@ -218,7 +251,7 @@ constexpr int RANGE_SPLIT_MAX = 4;                      // items per range at mo
 int tiled_chunk(int dim);   // particles per chunk of the tiled step
 int tiled_nodes(int dim);   // LDS nodes per current component of one chunk's box
 template <typename T>
-void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, JClear<T> jc,
                                const TileWork &tw, int n_slots, int push, hipStream_t s);
 template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
@@ -253,10 +286,9 @@ void launch_rho(const Grid<T> &g, const Parts<T> &P, StepCtl ctl, int first, int
 
 // adjoint of the fields: LT[c] (part driven along a+2, or the whole component where it
 // is not split), LA[c] (part driven along a+1 minus LT), c = E_x .. B_z
-// J <- 0 over the union of the slots `prev` (the previous step's deposits); the slots
-// `cur` are emptied for this step's deposits
+// the clear of a JClear as its own launch (steps whose deposit is not the tiled kernel)
 template <typename T>
-void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, int *cur, hipStream_t s);
+void launch_jbox_clear(const Grid<T> &g, const JClear<T> &jc, hipStream_t s);
 // workgroups of the deposit launch of a step
 template <typename T>
 int deposit_blocks(const Grid<T> &g, const TileWork &tw, int n_slots, bool tiled);

@@ -35,35 +35,19 @@ __global__ void __launch_bounds__(256) k_fused_2d(Grid<T> g, Fields<T> F, Fields
   fused_segment_2d(g, F, D, jslot_union(jslot), strip, y0, y1, fuse_alpha, (int)(threadIdx.x & 63));
 }
 
-// J <- 0 over the union of the slots `prev`; the slots `cur` emptied
 template <typename T>
-__global__ void __launch_bounds__(256) k_jbox_clear(Grid<T> g, Fields<T> F, const int *prev, int *cur) {
-  if (blockIdx.x == 0 && threadIdx.x < JSLOTS) {   // this step's slots start empty
-    auto *p = gptr(cur) + 4 * threadIdx.x;
-    p[0] = 0x7FFFFFFF; p[1] = -0x7FFFFFFF; p[2] = 0x7FFFFFFF; p[3] = -0x7FFFFFFF;
-  }
-  const int4 b = jslot_union(prev);
-  const int x0 = max(b.x, -G), x1 = min(b.y, g.M[0] + G);
-  const int y0 = max(b.z, -G), y1 = min(b.w, g.M[1] + G);
-  if (x0 > x1 || y0 > y1) return;
-  const int w = x1 - x0 + 1;
-  const long n = (long)w * (y1 - y0 + 1);
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const long q = g.at(x0 + (int)(e % w), y0 + (int)(e / w), 0);
-    F.J[0][q] = T(0);
-    F.J[1][q] = T(0);
-    F.J[2][q] = T(0);
-  }
+__global__ void __launch_bounds__(256) k_jbox_clear(Grid<T> g, JClear<T> jc) {
+  jclear_share(g, jc);
 }
 
 template <typename T>
-void launch_jbox_clear(const Grid<T> &g, const Fields<T> &F, const int *prev, int *cur, hipStream_t s) {
+void launch_jbox_clear(const Grid<T> &g, const JClear<T> &jc, hipStream_t s) {
   const long n = (long)(g.M[0] + 1 + 2 * G) * (g.M[1] + 1 + 2 * G);
   const int blocks = (int)std::min<long>(1024, (n + 255) / 256);
-  hipLaunchKernelGGL((k_jbox_clear<T>), dim3(blocks), dim3(256), 0, s, g, F, prev, cur);
+  hipLaunchKernelGGL((k_jbox_clear<T>), dim3(blocks), dim3(256), 0, s, g, jc);
 }
-template void launch_jbox_clear<float>(const Grid<float> &, const Fields<float> &, const int *, int *, hipStream_t);
-template void launch_jbox_clear<double>(const Grid<double> &, const Fields<double> &, const int *, int *, hipStream_t);
+template void launch_jbox_clear<float>(const Grid<float> &, const JClear<float> &, hipStream_t);
+template void launch_jbox_clear<double>(const Grid<double> &, const JClear<double> &, hipStream_t);
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {

@@ -227,8 +227,8 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, Sink &sink, const int 
   for (int d = 0; d < DIM; ++d) ws[d] = move_window<T, ORDER>(i0[d], f0[d], i1[d], f1[d], S0[d], S1[d]);
   sink.origin(g, ws);
   if constexpr (DIM == 2) {
-    const T cx = qw * g.inv_dx[1] / g.dt;
-    const T cy = qw * g.inv_dx[0] / g.dt;
+    const T cx = qw * g.jcoef[0];
+    const T cy = qw * g.jcoef[1];
     const T cz = qw * vz * g.inv_dx[0] * g.inv_dx[1];
 #pragma unroll
     for (int b = 0; b < W; ++b) {            // J_x: running sum along x
@@ -264,7 +264,7 @@ __device__ __forceinline__ void deposit(const Grid<T> &g, Sink &sink, const int 
 #pragma unroll
     for (int A = 0; A < 3; ++A) {
       const int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
-      const T coef = qw * g.inv_dx[Bx] * g.inv_dx[Cx] / g.dt;
+      const T coef = qw * g.jcoef[A];
 #pragma unroll
       for (int c = 0; c < W; ++c)
 #pragma unroll

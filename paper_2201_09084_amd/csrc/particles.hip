@@ -56,7 +56,7 @@ template <> struct TileCfg<3> { static constexpr int NODES = 1344; static conste
 // and particles outside it deposit straight to global J.
 template <typename T, int DIM, int ORDER, int PPT, bool BY_TILE>
 __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl,
-                                                            TileWork tw, int push) {
+                                                            JClear<T> jc, TileWork tw, int push) {
   constexpr int WLO = ORDER == 1 ? -1 : -2;
   constexpr int WHI = ORDER == 1 ? 2 : 3;
   constexpr int NODES = TileCfg<DIM>::NODES;
@@ -64,6 +64,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   __shared__ int sbox[12];   // min[3], max[3] of the old cells; then the same clipped
   __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
+  if (DIM == 2 && jc.prev) jclear_share(g, jc);   // the other current buffer (a different array)
   int p0, p1, t = -1;
   {
     // by tile: the items of the tiles; else the 2D list (heavy pieces first).  Uniform.
@@ -439,7 +440,7 @@ void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P,
 }
 
 template <typename T>
-void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, JClear<T> jc,
                                const TileWork &tw, int n_slots, int push, hipStream_t s) {
   if (n_slots <= 0) return;
   // an upper bound of the item count: by tile, every tile's last chunk may be partial;
@@ -450,10 +451,10 @@ void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts
   do {                                                                                                         \
     if (tw.by_tile)                                                                                            \
       hipLaunchKernelGGL((k_push_deposit_tiles<T, DIMV, ORD, TileCfg<DIMV>::PPT, true>), grd, blk, 0, s, g, F, \
-                         P, ctl, tw, push);                                                                    \
+                         P, ctl, jc, tw, push);                                                                \
     else                                                                                                       \
       hipLaunchKernelGGL((k_push_deposit_tiles<T, DIMV, ORD, TileCfg<DIMV>::PPT, false>), grd, blk, 0, s, g,   \
-                         F, P, ctl, tw, push);                                                                 \
+                         F, P, ctl, jc, tw, push);                                                             \
   } while (0)
   if (g.dim == 2) {
     if (g.order == 1) PMLPIC_TILES(2, 1); else if (g.order == 2) PMLPIC_TILES(2, 2); else PMLPIC_TILES(2, 3);
@@ -727,9 +728,9 @@ void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s)
 }
 
 template void launch_push_deposit_tiles<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
-                                               StepCtl, const TileWork &, int, int, hipStream_t);
+                                               StepCtl, JClear<float>, const TileWork &, int, int, hipStream_t);
 template void launch_push_deposit_tiles<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
-                                                StepCtl, const TileWork &, int, int, hipStream_t);
+                                                StepCtl, JClear<double>, const TileWork &, int, int, hipStream_t);
 
 template void launch_gather_push<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
                                         Parts<float>, StepCtl, int, int, bool, hipStream_t);
