@@ -33,6 +33,7 @@ class OrcParams(C.Structure):
         ("alpha_mode", C.c_int), ("damping_scale", C.c_double), ("n_sigma_coef", C.c_int),
         ("sigma_coef", (C.c_double * 16) * 3), ("push", C.c_int),
         ("charge", C.c_double), ("mass", C.c_double),
+        ("solver", C.c_int), ("filter_passes", C.c_int),
     ]
 
 
@@ -72,6 +73,7 @@ def lib():
             "orc_get_rho_static": (None, [vp, dp]),
             "orc_set_rho_static": (None, [vp, dp]),
             "orc_gather": (None, [vp, dp, dp]),
+            "orc_filter_current": (None, [vp]),
             "orc_boris": (None, [d, dp, dp, dp]),
             "orc_deposit_into": (None, [vp, dp, dp, d, d]),
             "orc_zero_current": (None, [vp]),
@@ -145,6 +147,8 @@ def make_params(cfg) -> OrcParams:
     p.push = int(cfg.push)
     p.charge = float(cfg.charge)
     p.mass = float(cfg.mass)
+    p.solver = int(getattr(cfg, "solver", 0))
+    p.filter_passes = int(getattr(cfg, "filter_passes", 0))
     return p
 
 
@@ -275,6 +279,10 @@ class OracleSim:
 
     def damp_current(self):
         lib().orc_damp_current(self._h)
+
+    def filter_current(self):
+        """filter_passes binomial passes over the current (App. A)"""
+        lib().orc_filter_current(self._h)
 
     def advance_B(self, tau):
         lib().orc_advance_B(self._h, float(tau))

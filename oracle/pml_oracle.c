@@ -526,6 +526,62 @@ static double source_weight(int a, int b, double sb, double sc)
  *   dB_ab/dt = -eps_abc d_b E_c - sigma_b B_ab                     (Eq. MaxwellB)
  * with sigma_b taken at the sample's coordinate along b, integrated with the
  * exponential factors of expfac().  In 2D the z derivatives vanish. */
+/* Cole-Karkkainen difference (App. A: the paper's solver, with cubic cells) of E
+ * component ci along b, at the B sample ii: the Yee difference E(ii + e_b) - E(ii) at ii
+ * and at its transverse neighbours, weighted 7/12 at ii, 1/12 at each of the four side
+ * neighbours and 1/48 at each of the four diagonal ones (weights sum to 1, so a field
+ * uniform across b gives the Yee difference: no dispersion along the axes at c dt = dx).
+ * Used for Faraday's law only; Ampere's law keeps the Yee difference. */
+static double ck_diff(const orc_sim *s, int ci, const int ii[3], int b)
+{
+    int t1 = (b + 1) % 3, t2 = (b + 2) % 3;
+    double acc = 0.0;
+    for (int o1 = -1; o1 <= 1; ++o1)
+        for (int o2 = -1; o2 <= 1; ++o2) {
+            int nside = (o1 != 0) + (o2 != 0);
+            double w = nside == 0 ? 7.0 / 12.0 : (nside == 1 ? 1.0 / 12.0 : 1.0 / 48.0);
+            int p[3] = {ii[0], ii[1], ii[2]};
+            p[t1] += o1;
+            p[t2] += o2;
+            int q[3] = {p[0], p[1], p[2]};
+            q[b] += 1;
+            acc += w * (total_at(s, ci, q) - total_at(s, ci, p));
+        }
+    return acc;
+}
+
+/* Binomial filter of the deposited current (App. A): J_a <- sum over the 3^dim
+ * neighbours o of prod_d (1/4, 1/2, 1/4)[o_d] J_a(ii + o), once per pass; samples outside
+ * J_a's extent count as zero and are not written. */
+void orc_filter_current(orc_sim *s)
+{
+    int dim = s->p.dim;
+    double *tmp = (double *)calloc(s->nsamp, sizeof(double));
+    for (int pass = 0; pass < s->p.filter_passes; ++pass)
+        for (int a = 0; a < 3; ++a) {
+            int nv[3];
+            for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(a, d));
+            for (int k = 0; k < nv[2]; ++k)
+            for (int j = 0; j < nv[1]; ++j)
+            for (int i = 0; i < nv[0]; ++i) {
+                double acc = 0.0;
+                for (int oz = (dim == 3 ? -1 : 0); oz <= (dim == 3 ? 1 : 0); ++oz)
+                for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    int p[3] = {i + ox, j + oy, k + oz};
+                    if (!in_range(s, a, p)) continue;
+                    double w = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (dim == 3 ? (oz ? 0.25 : 0.5) : 1.0);
+                    acc += w * s->J[a][idx3(s, p[0], p[1], p[2])];
+                }
+                tmp[idx3(s, i, j, k)] = acc;
+            }
+            for (int k = 0; k < nv[2]; ++k)
+            for (int j = 0; j < nv[1]; ++j)
+            for (int i = 0; i < nv[0]; ++i) s->J[a][idx3(s, i, j, k)] = tmp[idx3(s, i, j, k)];
+        }
+    free(tmp);
+}
+
 static void advance(orc_sim *s, int is_e, double tau)
 {
     for (int a = 0; a < 3; ++a) {
@@ -551,7 +607,9 @@ static void advance(orc_sim *s, int is_e, double tau)
                 double X[3];
                 sample_pos(c_self, ii, X);
                 double deriv = 0.0;
-                if (b < s->p.dim) {
+                if (b < s->p.dim && !is_e && s->p.solver == 1) {
+                    deriv = ck_diff(s, ci, ii, b) / s->p.dx[b];
+                } else if (b < s->p.dim) {
                     int ip[3] = {i, j, k}, im[3] = {i, j, k};
                     if (is_e) { im[b] -= 1; }  /* B_c sits half a cell off along b */
                     else { ip[b] += 1; }       /* E_c sits half a cell off along b */
@@ -608,7 +666,7 @@ void orc_deposit_into(orc_sim *s, const double X0[3], const double X1[3], double
  *  1. per particle: gather E^n, B^n at X^n (totals), Boris push (if enabled),
  *     X^{n+1} = X^n + dt u/gamma, Esirkepov deposit of X^n -> X^{n+1};
  *     particles ending outside the PEC box are removed after depositing;
- *  2. J <- alpha J (Eq. alpha / mode);
+ *  2. J <- alpha J (Eq. alpha / mode), after the binomial filter when it is on;
  *  3. B += dt/2 from E^n; E += dt from B^{n+1/2} and alpha J; B += dt/2 from E^{n+1}. */
 void orc_step(orc_sim *s, int nsteps)
 {
@@ -644,6 +702,7 @@ void orc_step(orc_sim *s, int nsteps)
             ++keep;
         }
         s->np = keep;
+        if (s->p.filter_passes > 0) orc_filter_current(s);
         damp_current(s);
         advance(s, 0, 0.5 * s->p.dt);
         advance(s, 1, s->p.dt);

@@ -21,6 +21,8 @@ typedef struct {
     double sigma_coef[3][16];/* sigma_d/eps0 = sum_k coef[d][k] (depth/L)^k */
     int push;                /* 1: gather + Boris; 0: momenta kept (ballistic) */
     double charge, mass;     /* per unit weight */
+    int solver;              /* 0: Yee; 1: Cole-Karkkainen in Faraday's law (3D, cubic cells) */
+    int filter_passes;       /* binomial passes over the deposited current (0: none) */
 } orc_params;
 
 typedef struct {
@@ -57,6 +59,7 @@ void orc_set_current(orc_sim *s, const double *in);
 void orc_get_rho_static(const orc_sim *s, double *out);
 void orc_set_rho_static(orc_sim *s, const double *in);
 void orc_gather(const orc_sim *s, const double X[3], double EB[6]);
+void orc_filter_current(orc_sim *s);
 void orc_boris(double qdt_2m, const double E[3], const double B[3], double u[3]);
 void orc_deposit(orc_sim *s, const double X0[3], const double X1[3], double vz, double qw, double *const J[3]);
 void orc_deposit_into(orc_sim *s, const double X0[3], const double X1[3], double vz, double qw);

@@ -38,6 +38,8 @@ class SimConfig:
     sort_interval: int = 0
     tile: tuple = (0, 0, 0)
     max_particles: int = 0
+    solver: int = 0                     # 0 Yee; 1 Cole-Karkkainen in Faraday's law (3D, cubic cells)
+    filter_passes: int = 0              # binomial passes over the deposited current (3D)
 
     def total_cells(self) -> int:
         t = 1
