@@ -64,6 +64,8 @@ def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
         return cells * (6 + 6 + 3) * esz + pml * 4 * nsplit_e * esz
     if phase == "clear_current":
         return cells * 3 * esz
+    if phase == "filter_current":   # J r+w
+        return cells * 6 * esz
     return None
 
 
@@ -168,9 +170,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 2000 beam2d, 100 beam3d, 600 batch)")
+                    help="timed steps (default: 2000 beam2d, 100 beam3d, 600 batch, 300 sp3d)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch"], default="beam2d")
+    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch", "sp3d"], default="beam2d")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -198,7 +200,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.steps is None:
-        args.steps = {"beam2d": 2000, "beam3d": 100, "batch": 600}[args.workload]
+        args.steps = {"beam2d": 2000, "beam3d": 100, "batch": 600, "sp3d": 300}[args.workload]
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "beam2d":
@@ -206,11 +208,16 @@ def main():
         parts = W.beam2d_particles(cfg)
         wl = {"workload": "beam2d", "grid": "1024x1024+16pml", "particles": len(parts),
               "shape_order": 2, "steps_total": args.warmup + args.steps}
-    else:
+    elif args.workload == "beam3d":
         cfg = W.beam3d_config(precision=args.precision)
         parts = W.beam3d_particles(cfg)
         wl = {"workload": "beam3d", "grid": "256^3+12pml", "particles": len(parts),
               "shape_order": 1, "steps_total": args.warmup + args.steps}
+    else:   # the 3D single-particle numerics of App. A: CK at c dt = dx, cubic shape, filter
+        cfg = W.single_particle_3d_config(precision=args.precision)
+        parts = W.single_particle(cfg, beta=0.9)
+        wl = {"workload": "sp3d", "grid": "128^3+8pml", "particles": 1, "shape_order": 3,
+              "solver": "CK", "filter_passes": 1, "steps_total": args.warmup + args.steps}
     print("bench: %s, %d particles, %d cells, fp%d; warmup %d, timed %d" %
           (args.workload, len(parts), cfg.total_cells(), args.precision, args.warmup, args.steps),
           file=sys.stderr, flush=True)
@@ -219,8 +226,9 @@ def main():
     esz = 4 if args.precision == 32 else 8
     cells = cfg.total_cells()
     ms_per_step = 1e3 * elapsed / args.steps
-    value = pushes / elapsed
-    print("bench: %.3f ms/step, %.3e pushes/s, phases %s" % (ms_per_step, value, phases),
+    per_cell = args.workload == "sp3d"   # one particle: the field update is the work
+    value = cells * args.steps / elapsed if per_cell else pushes / elapsed
+    print("bench: %.3f ms/step, %.3e %s, phases %s" % (ms_per_step, value, "cell-updates/s" if per_cell else "pushes/s", phases),
           file=sys.stderr, flush=True)
 
     # dominant kernel: the phase with the largest total time
@@ -240,16 +248,19 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        n_cpu = args.cpu_steps
+        n_cpu = 2 if per_cell else args.cpu_steps
         v, secs = cpu_baseline(cfg, parts, n_cpu)
-        cpu = {"value": v, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+        if per_cell:
+            v = v / len(parts) * cells
+        cpu = {"value": v, "unit": "cell-updates/s" if per_cell else "particle-pushes/s", "cores": 1,
+               "kind": "oracle",
                "sample": "%d steps of the same workload from its initial state (%d particles), "
                          "FP64 single-threaded C oracle, %.1f s" % (n_cpu, len(parts), secs)}
 
     out = {
         "metric": "PIC particle-pushes/s & Yee+PML cell-updates/s; FP32 vs FP64 at stated err",
         "value": value,
-        "unit": "particle-pushes/s",
+        "unit": "cell-updates/s" if per_cell else "particle-pushes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,

@@ -76,7 +76,7 @@ typedef struct {
     int32_t n[3];               /* physical cells per axis (ignored beyond dim) */
     int32_t pml[3][2];          /* PML cells per axis, low / high face; 0 = bare PEC wall */
     double dx[3];               /* cell sizes */
-    double dt;                  /* time step; c dt < 1/sqrt(sum 1/dx_d^2) */
+    double dt;                  /* time step; c dt < 1/sqrt(sum 1/dx_d^2) (Yee), c dt <= dx (CK) */
     int32_t shape_order;        /* particle shape: 1 linear, 2 quadratic, 3 cubic */
     int32_t alpha_mode;         /* PML_ALPHA_ZERO / ONE / DAMPED / WEIGHT */
     double damping_scale;       /* 1/v of Eq. (alpha): alpha = exp(-damping_scale * int sigma/eps0) */
@@ -91,7 +91,19 @@ typedef struct {
     int32_t flags;              /* PML_PIC_FLAG_* */
     int32_t adjoint_segment;    /* steps per checkpoint segment of the adjoint; 0 = no adjoint storage */
     int32_t adjoint_checkpoints;/* checkpoints kept by pml_pic_forward_ckpt (segments per run) */
+    int32_t solver;             /* PML_PIC_SOLVER_YEE, or PML_PIC_SOLVER_CK: the Cole-Karkkainen
+                                   solver the paper's single-particle runs use (App. A): 3D,
+                                   cubic cells, c dt <= dx; Faraday's law takes the Yee
+                                   difference averaged over its transverse neighbours with
+                                   weights 7/12 (itself), 1/12 (the four side neighbours), 1/48
+                                   (the four diagonal ones); Ampere's law stays Yee */
+    int32_t filter_passes;      /* 3D: passes of the binomial filter (App. A) over the deposited
+                                   current before the field update: each sample becomes the
+                                   (1/4, 1/2, 1/4)^3-weighted sum of its 27 neighbours (samples
+                                   outside the component's extent count as 0); 0..4 */
 } pml_pic_params;
+
+enum { PML_PIC_SOLVER_YEE = 0, PML_PIC_SOLVER_CK = 1 };
 
 typedef struct {
     double u_interior;   /* 1/2 sum (E^2 + B^2) dV over samples inside the physical box (FP64 sum) */
@@ -139,7 +151,8 @@ enum {
     PML_PIC_PHASE_UPDATE_B = 5,    /* update_yee_pml, the two B half steps */
     PML_PIC_PHASE_UPDATE_E = 6,    /* update_yee_pml, the E step (with alpha J) */
     PML_PIC_PHASE_UPDATE_FIELDS = 7, /* update_yee_pml in one pass (2D default) */
-    PML_PIC_NUM_PHASES = 8
+    PML_PIC_PHASE_FILTER_J = 8,    /* the binomial filter of the deposited current (3D) */
+    PML_PIC_NUM_PHASES = 9
 };
 
 /* Same work as pml_pic_step, with a pair of HIP events on the handle's stream around

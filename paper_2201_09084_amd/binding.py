@@ -32,7 +32,7 @@ EXPORTED = [
     "pml_pic_backward",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
-          "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml"]
+          "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
 
 
 class Params(C.Structure):
@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("sort_interval", C.c_int32), ("tile", C.c_int32 * 3), ("max_particles", C.c_int64),
         ("charge", C.c_double), ("mass", C.c_double), ("flags", C.c_int32),
         ("adjoint_segment", C.c_int32), ("adjoint_checkpoints", C.c_int32),
+        ("solver", C.c_int32), ("filter_passes", C.c_int32),
     ]
 
 
@@ -138,6 +139,8 @@ def make_params(cfg, max_particles=None, flags=0, adjoint=(0, 0)) -> Params:
     p.flags = int(flags)
     p.adjoint_segment = int(adjoint[0])
     p.adjoint_checkpoints = int(adjoint[1])
+    p.solver = int(getattr(cfg, "solver", 0))
+    p.filter_passes = int(getattr(cfg, "filter_passes", 0))
     return p
 
 
@@ -250,10 +253,10 @@ class PmlPic:
 
     def step_profiled(self, n: int = 1):
         """Steps with HIP events around every kernel phase: {phase: (total ms, launches)}."""
-        ms = np.zeros(8)
-        calls = np.zeros(8, np.int64)
+        ms = np.zeros(len(PHASES))
+        calls = np.zeros(len(PHASES), np.int64)
         self._check(load_library().pml_pic_step_profiled(self._h, int(n), _dp(ms), _lp(calls)))
-        return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(8) if calls[k] > 0}
+        return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(len(PHASES)) if calls[k] > 0}
 
     # ---------------------------------------------------------------- adjoint
     def forward_ckpt(self, n: int) -> float:
@@ -364,10 +367,10 @@ class PmlPicBatch:
 
     def step_profiled(self, n: int = 1):
         """Eager steps with HIP events around every kernel: {phase: (total ms, launches)}."""
-        ms = np.zeros(8)
-        calls = np.zeros(8, np.int64)
+        ms = np.zeros(len(PHASES))
+        calls = np.zeros(len(PHASES), np.int64)
         self._check(load_library().pml_pic_batch_step_profiled(self._h, int(n), _dp(ms), _lp(calls)))
-        return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(8) if calls[k] > 0}
+        return {PHASES[k]: (float(ms[k]), int(calls[k])) for k in range(len(PHASES)) if calls[k] > 0}
 
     def set_launch(self, block_x: int, grid_blocks: int = 0):
         self._check(load_library().pml_pic_batch_set_launch(self._h, int(block_x), int(grid_blocks)))

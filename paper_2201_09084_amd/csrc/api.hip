@@ -28,6 +28,7 @@ struct Layout {
   size_t off_field[15] = {};   // E0-2, B0-2, Ea0-2, Ba0-2, J0-2
   size_t off_alt[12] = {};     // second set of E, B, Ea, Ba for the out-of-place 2D update
   size_t off_altj[3] = {};     // second current buffer (2D one-pass runs, by step parity)
+  size_t off_jtmp = 0;         // 3D current filter: scratch copy of the three J arrays
   bool has_alt = false;
   size_t off_tab = 0;
   size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_lam[2] = {}, off_id[2] = {};
@@ -98,7 +99,18 @@ int validate(const pml_pic_params *p, std::string *err) {
   if (p->dim == 2 && (M0 > 65533 || M1 > 65533)) return fail(err, PML_PIC_E_INVALID_ARG, "2D grid too large");
   if (p->dim == 3 && (M0 > 2045 || M1 > 2045 || M2 > 1021)) return fail(err, PML_PIC_E_INVALID_ARG, "3D grid too large");
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(err, PML_PIC_E_INVALID_ARG, "dt must be > 0");
-  if (!(p->dt < 1.0 / std::sqrt(s2))) return fail(err, PML_PIC_E_CFL, "c dt violates the Yee CFL limit");
+  if (p->solver != PML_PIC_SOLVER_YEE && p->solver != PML_PIC_SOLVER_CK)
+    return fail(err, PML_PIC_E_INVALID_ARG, "solver must be PML_PIC_SOLVER_YEE or PML_PIC_SOLVER_CK");
+  if (p->solver == PML_PIC_SOLVER_CK) {
+    if (p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "the CK solver is 3D");
+    if (std::fabs(p->dx[1] - p->dx[0]) > 1e-12 * p->dx[0] || std::fabs(p->dx[2] - p->dx[0]) > 1e-12 * p->dx[0])
+      return fail(err, PML_PIC_E_INVALID_ARG, "the CK solver needs cubic cells");
+    if (!(p->dt <= p->dx[0] * (1.0 + 1e-12))) return fail(err, PML_PIC_E_CFL, "c dt exceeds the CK limit dx");
+  } else if (!(p->dt < 1.0 / std::sqrt(s2))) {
+    return fail(err, PML_PIC_E_CFL, "c dt violates the Yee CFL limit");
+  }
+  if (p->filter_passes < 0 || p->filter_passes > 4) return fail(err, PML_PIC_E_INVALID_ARG, "filter_passes must be in [0,4]");
+  if (p->filter_passes > 0 && p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "the current filter is 3D");
   if (p->shape_order < 1 || p->shape_order > 3) return fail(err, PML_PIC_E_INVALID_ARG, "shape_order must be 1, 2 or 3");
   if (p->alpha_mode < 0 || p->alpha_mode > 3) return fail(err, PML_PIC_E_INVALID_ARG, "alpha_mode must be 0, 1, 2 or 3");
   if (!(p->damping_scale >= 0.0) || !std::isfinite(p->damping_scale))
@@ -157,6 +169,7 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   for (int a = 0; a < 15; ++a) L.off_field[a] = take(L.esz * (size_t)L.nelem);
   // the one-pass 2D field update reads one set of arrays and writes the other
   L.has_alt = p.dim == 2 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS);
+  if (p.filter_passes > 0) L.off_jtmp = take(3 * L.esz * (size_t)L.nelem);
   if (L.has_alt) {
     for (int a = 0; a < 12; ++a) L.off_alt[a] = take(L.esz * (size_t)L.nelem);
     for (int a = 0; a < 3; ++a) L.off_altj[a] = take(L.esz * (size_t)L.nelem);
@@ -259,6 +272,7 @@ struct pml_pic_handle {
     g.sy = L.sy; g.sz = L.sz; g.base = L.base; g.nelem = L.nelem;
     g.dt = (T)p.dt;
     g.qdt_2m = (T)(p.charge * p.dt / (2.0 * p.mass));
+    g.solver = p.solver;
     for (int a = 0; a < 3; ++a) {
       const int b = (a + 1) % 3, c = (a + 2) % 3;
       const double ib = b < p.dim ? 1.0 / p.dx[b] : 1.0, ic = c < p.dim ? 1.0 / p.dx[c] : 1.0;
@@ -633,7 +647,9 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const bool fused = !(fl & PML_PIC_FLAG_UNFUSED);
   const bool sep_damp = (fl & PML_PIC_FLAG_SEPARATE_DAMP) != 0;
   const bool one_pass = h->L.has_alt;
-  const bool keep_j = (fl & PML_PIC_FLAG_KEEP_CURRENT) != 0 || one_pass;
+  // The E update zeroes J only where it updates E; the filter also reads the samples on
+  // the PEC walls, so with the filter J is cleared before every deposit instead.
+  const bool keep_j = (fl & PML_PIC_FLAG_KEEP_CURRENT) != 0 || one_pass || h->p.filter_passes > 0;
   const int ns = (int)h->n_slots;
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
@@ -686,6 +702,11 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       pt.begin(s);
       launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, s);
       pt.end(s, PML_PIC_PHASE_DEPOSIT);
+    }
+    if (h->p.filter_passes > 0) {
+      pt.begin(s);
+      launch_filter_current<T>(g, F, h->at<T>(h->L.off_jtmp), h->p.filter_passes, s);
+      pt.end(s, PML_PIC_PHASE_FILTER_J);
     }
     if (it < (int)h->snap_J.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_J[it], F.J[0], h->L.J_bytes, hipMemcpyDeviceToDevice, s));
@@ -1409,6 +1430,8 @@ int check_adjoint(pml_pic_handle *h) {
     return fail(&h->err, PML_PIC_E_INVALID_ARG, "alpha_mode 0 is not differentiable in the profile");
   if (h->p.alpha_mode == PML_ALPHA_WEIGHT)
     return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint does not cover per-particle weight damping");
+  if (h->p.solver != PML_PIC_SOLVER_YEE || h->p.filter_passes > 0)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint covers the Yee solver without current filter");
   return PML_PIC_OK;
 }
 

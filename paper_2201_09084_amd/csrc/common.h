@@ -62,6 +62,7 @@ struct Grid {
   T dt;
   T inv_dx[3];
   T qdt_2m;            // charge dt / (2 mass)
+  int solver;          // PML_PIC_SOLVER_YEE / _CK (Faraday's law)
   T jcoef[3];          // Esirkepov factor of J_a: (1/dx_b)(1/dx_c)/dt over the other two axes
                        // (1/dx = 1 on the invariant axis of a 2D run)
   T charge;
@@ -221,6 +222,10 @@ void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool half, hipStream_
 template <typename T>
 void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode, bool consume,
                      hipStream_t s);
+// binomial filter of J (3D), out of place into tmp (three arrays of nelem), then copied
+// back; `passes` times
+template <typename T>
+void launch_filter_current(const Grid<T> &g, const Fields<T> &F, T *tmp, int passes, hipStream_t s);
 template <typename T>
 void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
 template <typename T>

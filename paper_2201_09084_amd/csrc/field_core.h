@@ -18,9 +18,23 @@ __device__ __forceinline__ long stride_of(const Grid<T> &g, int axis) {
   return axis == 0 ? 1L : (axis == 1 ? g.sy : g.sz);
 }
 
+// Cole-Karkkainen difference (the paper's solver, App. A; 3D, cubic cells) of e along
+// axis AX at sample q: the Yee difference e(q + e_AX) - e(q) at q and at its transverse
+// neighbours, weighted 7/12 (q), 1/12 (each side neighbour), 1/48 (each diagonal one).
+template <typename T, int AX>
+__device__ __forceinline__ T ck_diff(const Grid<T> &g, const T *e, long q) {
+  constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+  const long sa = stride_of<T, 3>(g, AX), s1 = stride_of<T, 3>(g, T1), s2 = stride_of<T, 3>(g, T2);
+  auto d = [&](long o) { return e[q + o + sa] - e[q + o]; };
+  const T side = (d(s1) + d(-s1)) + (d(s2) + d(-s2));
+  const T diag = (d(s1 + s2) + d(s1 - s2)) + (d(-s1 + s2) + d(-s1 - s2));
+  return T(7.0 / 12.0) * d(0) + T(1.0 / 12.0) * side + T(1.0 / 48.0) * diag;
+}
+
 // B_A half step at node (i,j,k) -> sample B_A(i,j,k).  Written as FMA chains on the
 // raw neighbour differences so that each part takes three roundings per update.
-template <typename T, int DIM, int A>
+// CK: Cole-Karkkainen differences instead of the Yee ones (3D only).
+template <typename T, int DIM, int A, bool CK = false>
 __device__ __forceinline__ void update_B_comp(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
                                               long q) {
   constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
@@ -30,8 +44,13 @@ __device__ __forceinline__ void update_B_comp(const Grid<T> &g, const Fields<T> 
   if (Cx < DIM && id[Cx] > g.M[Cx] - 1) return;
   // part b: -d_b E_c ; part c: +d_c E_b
   T Db = T(0), Dc = T(0);
-  if (Bx < DIM) Db = F.E[Cx][q + stride_of<T, DIM>(g, Bx)] - F.E[Cx][q];
-  if (Cx < DIM) Dc = F.E[Bx][q + stride_of<T, DIM>(g, Cx)] - F.E[Bx][q];
+  if constexpr (CK && DIM == 3) {
+    Db = ck_diff<T, Bx>(g, F.E[Cx], q);
+    Dc = ck_diff<T, Cx>(g, F.E[Bx], q);
+  } else {
+    if (Bx < DIM) Db = F.E[Cx][q + stride_of<T, DIM>(g, Bx)] - F.E[Cx][q];
+    if (Cx < DIM) Dc = F.E[Bx][q + stride_of<T, DIM>(g, Cx)] - F.E[Bx][q];
+  }
   if constexpr (DIM == 2 && (Bx == 2 || Cx == 2)) {
     constexpr int P = (Bx == 2) ? Cx : Bx;   // the in-plane derivative (and damping) axis
     const T e = g.tb(P, T_EH_C, id[P]), gk = g.tb(P, T_GHK_C, id[P]);

@@ -15,6 +15,7 @@
 // Memory-bound stencils: one thread per node, x fastest, coalesced rows.
 #include <algorithm>
 
+#include "pml_pic.h"
 #include "field_core.h"
 #include "fused2d.h"
 
@@ -49,7 +50,7 @@ void launch_jbox_clear(const Grid<T> &g, const JClear<T> &jc, hipStream_t s) {
 template void launch_jbox_clear<float>(const Grid<float> &, const JClear<float> &, hipStream_t);
 template void launch_jbox_clear<double>(const Grid<double> &, const JClear<double> &, hipStream_t);
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool CK = false>
 __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -57,9 +58,9 @@ __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
   if (i > g.M[0] || j > g.M[1]) return;
   const int id[3] = {i, j, k};
   const long q = g.at(i, j, k);
-  update_B_comp<T, DIM, 0>(g, F, id, q);
-  update_B_comp<T, DIM, 1>(g, F, id, q);
-  update_B_comp<T, DIM, 2>(g, F, id, q);
+  update_B_comp<T, DIM, 0, CK>(g, F, id, q);
+  update_B_comp<T, DIM, 1, CK>(g, F, id, q);
+  update_B_comp<T, DIM, 2, CK>(g, F, id, q);
 }
 
 template <typename T, int DIM>
@@ -126,6 +127,7 @@ template <typename T>
 void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool /*half*/, hipStream_t s) {
   dim3 blk, grd = node_grid(g, blk);
   if (g.dim == 2) hipLaunchKernelGGL((k_update_B<T, 2>), grd, blk, 0, s, g, F);
+  else if (g.solver == PML_PIC_SOLVER_CK) hipLaunchKernelGGL((k_update_B<T, 3, true>), grd, blk, 0, s, g, F);
   else hipLaunchKernelGGL((k_update_B<T, 3>), grd, blk, 0, s, g, F);
 }
 
@@ -137,6 +139,55 @@ void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int 
   if (g.dim == 2) hipLaunchKernelGGL((k_update_E<T, 2>), grd, blk, 0, s, g, F, fa, consume);
   else hipLaunchKernelGGL((k_update_E<T, 3>), grd, blk, 0, s, g, F, fa, consume);
 }
+
+// Binomial filter of the deposited current (App. A), 3D: tmp_A(i,j,k) = sum over the 27
+// neighbours o of (1/4, 1/2, 1/4)^3[o] J_A(i+o), neighbours outside J_A's extent (length
+// M along A, M + 1 across) counting as 0; every sample of the extent is written, the rest
+// of tmp is left 0.  One thread per node, three components.
+template <typename T>
+__global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, Fields<T> F, T *tmp) {
+  const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
+  const int j = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int k = (int)blockIdx.z;
+  if (i > g.M[0] || j > g.M[1] || k > g.M[2]) return;
+  const int id[3] = {i, j, k};
+  const long q = g.at(i, j, k);
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    if (id[A] > g.M[A] - 1) continue;   // outside J_A's extent
+    const T *J = F.J[A];
+    T acc = T(0);
+    for (int oz = -1; oz <= 1; ++oz) {
+      const int kk = k + oz;
+      if (kk < 0 || kk > g.M[2] - (A == 2)) continue;
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int jj = j + oy;
+        if (jj < 0 || jj > g.M[1] - (A == 1)) continue;
+        T row = T(0);
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int ii = i + ox;
+          if (ii < 0 || ii > g.M[0] - (A == 0)) continue;
+          row += (ox ? T(0.25) : T(0.5)) * J[q + ox + oy * g.sy + oz * g.sz];
+        }
+        acc += (oz ? T(0.25) : T(0.5)) * (oy ? T(0.25) : T(0.5)) * row;
+      }
+    }
+    tmp[(long)A * g.nelem + q] = acc;
+  }
+}
+
+template <typename T>
+void launch_filter_current(const Grid<T> &g, const Fields<T> &F, T *tmp, int passes, hipStream_t s) {
+  if (g.dim != 3 || passes <= 0) return;
+  dim3 blk(256), grd((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, g.M[2] + 1);
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL((k_filter_J<T>), grd, blk, 0, s, g, F, tmp);
+    for (int a = 0; a < 3; ++a)   // samples outside the extents come back as 0
+      (void)hipMemcpyAsync(F.J[a], tmp + (size_t)a * g.nelem, sizeof(T) * (size_t)g.nelem, hipMemcpyDeviceToDevice, s);
+  }
+}
+template void launch_filter_current<float>(const Grid<float> &, const Fields<float> &, float *, int, hipStream_t);
+template void launch_filter_current<double>(const Grid<double> &, const Fields<double> &, double *, int, hipStream_t);
 
 template <typename T>
 void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s) {

@@ -113,6 +113,16 @@ def single_particle(cfg: SimConfig, beta: float = 0.9, theta_deg: float = 0.0,
     return Particles(x=x, u=u, w=np.array([w]))
 
 
+def single_particle_3d_config(precision: int = 64, n: int = 128, pml: int = 8) -> SimConfig:
+    """The 3D single-particle runs of App. A: n^3 cubic cells, pml-cell PML on every face
+    with the quadratic conductivity of App. A (scale 6 cells), Cole-Karkkainen Faraday
+    update at c dt = dx, cubic shape, one binomial pass over the deposited current."""
+    return SimConfig(dim=3, n=(n, n, n), pml=((pml, pml),) * 3, dt=1.0, shape_order=3,
+                     alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
+                     sigma_coef=paper_conductivity_profile(pml), push=1, precision=precision,
+                     solver=1, filter_passes=1)
+
+
 # ---------------------------------------------------------------- workload 2
 def beam2d_config(precision: int = 32, n: int = 1024, pml: int = 16) -> SimConfig:
     """2D 1024x1024 grid, 16-cell PML, quadratic shape, c dt = 0.7, FP32."""

@@ -75,6 +75,31 @@ def test_parameter_validation_codes(lib):
     assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
 
 
+def test_ck_solver_and_filter_validation(lib):
+    """The Cole-Karkkainen solver is 3D with cubic cells and c dt <= dx (App. A); the
+    binomial current filter is 3D with 0..4 passes."""
+    cfg3 = W.SimConfig(dim=3, n=(16, 16, 16), pml=((4, 4),) * 3, dx=(1.0, 1.0, 1.0), dt=0.9,
+                       sigma_coef=W.cubic_profile(3.2), max_particles=4)
+    assert _size(cfg3, dt=0.9)[0] == -2                   # beyond the 3D Yee limit 1/sqrt(3)
+    assert _size(cfg3, solver=1)[0] == 0
+    assert _size(cfg3, solver=1, dt=1.0)[0] == 0          # the CK limit c dt = dx
+    assert _size(cfg3, solver=1, dt=1.01)[0] == -2
+    assert _size(cfg3, solver=2)[0] == -1
+    p = B.make_params(cfg3, max_particles=4)
+    p.solver = 1
+    p.dx[2] = 1.1                                         # not cubic
+    n = C.c_size_t()
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
+    assert b"cubic" in lib.pml_pic_last_error(None)
+    cfg2 = W.single_particle_config()
+    assert _size(cfg2, solver=1)[0] == -1                 # 2D
+    assert _size(cfg2, filter_passes=1)[0] == -1          # 2D
+    assert _size(cfg3, dt=0.5, filter_passes=5)[0] == -1
+    rc0, n0 = _size(cfg3, dt=0.5)
+    rc1, n1 = _size(cfg3, dt=0.5, filter_passes=1)
+    assert rc0 == 0 and rc1 == 0 and n1 > n0              # the filter's scratch copy of J
+
+
 def test_create_rejects_small_or_missing_workspace(lib):
     p = B.make_params(W.single_particle_config(), max_particles=4)
     h = C.c_void_p()
