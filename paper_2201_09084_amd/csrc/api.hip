@@ -255,6 +255,8 @@ struct pml_pic_handle {
   // while set, step k of step_t copies the 12 field arrays before the step to
   // snap_state[k] and the undamped current after the deposit to snap_J[k]
   std::vector<char *> snap_state, snap_J;
+  // the last step's filtered current lives in the filter's scratch arrays (odd passes)
+  bool j_in_tmp = false;
 
   template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
   double tab(int axis, int kind, int i) const { return tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G]; }
@@ -526,7 +528,8 @@ int get_current_t(pml_pic_handle *h, double *out) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int a = 0; a < 3; ++a) {
     // 2D one-pass runs: the buffer of the last step (the parity flipped after it)
-    T *src = L.has_alt ? h->jbuf<T>(1 - h->fset, a) : h->at<T>(L.off_field[12 + a]);
+    T *src = L.has_alt ? h->jbuf<T>(1 - h->fset, a)
+                       : (h->j_in_tmp ? h->at<T>(L.off_jtmp) + (size_t)a * L.nelem : h->at<T>(L.off_field[12 + a]));
     HIPCHK(h, hipMemcpy(buf.data(), src, sizeof(T) * L.nelem, hipMemcpyDeviceToHost));
     for (int k = 0; k < L.nn[2]; ++k)
       for (int j = 0; j < L.nn[1]; ++j)
@@ -705,7 +708,9 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (h->p.filter_passes > 0) {
       pt.begin(s);
-      launch_filter_current<T>(g, F, h->at<T>(h->L.off_jtmp), h->p.filter_passes, s);
+      T *jf = launch_filter_current<T>(g, F.J[0], h->at<T>(h->L.off_jtmp), h->p.filter_passes, s);
+      for (int a = 0; a < 3; ++a) F.J[a] = jf + (size_t)a * h->L.nelem;   // the rest of the step reads it
+      h->j_in_tmp = jf != h->at<T>(h->L.off_field[12]);
       pt.end(s, PML_PIC_PHASE_FILTER_J);
     }
     if (it < (int)h->snap_J.size())

@@ -222,10 +222,10 @@ void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool half, hipStream_
 template <typename T>
 void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int alpha_mode, bool consume,
                      hipStream_t s);
-// binomial filter of J (3D), out of place into tmp (three arrays of nelem), then copied
-// back; `passes` times
+// `passes` binomial filter passes over J (3D), alternating between J and tmp (three
+// adjacent arrays of nelem each); returns the one holding the filtered current
 template <typename T>
-void launch_filter_current(const Grid<T> &g, const Fields<T> &F, T *tmp, int passes, hipStream_t s);
+T *launch_filter_current(const Grid<T> &g, T *J, T *tmp, int passes, hipStream_t s);
 template <typename T>
 void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
 template <typename T>

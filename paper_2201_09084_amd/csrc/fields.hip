@@ -140,54 +140,66 @@ void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int 
   else hipLaunchKernelGGL((k_update_E<T, 3>), grd, blk, 0, s, g, F, fa, consume);
 }
 
-// Binomial filter of the deposited current (App. A), 3D: tmp_A(i,j,k) = sum over the 27
-// neighbours o of (1/4, 1/2, 1/4)^3[o] J_A(i+o), neighbours outside J_A's extent (length
-// M along A, M + 1 across) counting as 0; every sample of the extent is written, the rest
-// of tmp is left 0.  One thread per node, three components.
+// Binomial filter of the deposited current (App. A), 3D, one pass: dst_A(i,j,k) = sum
+// over the 27 neighbours o of w(o_x) w(o_y) w(o_z) src_A(i+o), w = (1/4, 1/2, 1/4), with
+// neighbours outside J_A's extent (M_A samples along A, M + 1 across) counting as 0.  The
+// weights factor per axis, so each thread owns one (i, j) column of a chunk of FILT_KZ
+// planes and keeps the x-y filtered value of three consecutive planes in registers: a
+// plane is read once per chunk (with one halo plane on each side), and only samples of
+// the extent are written.
+constexpr int FILT_KZ = 16;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, Fields<T> F, T *tmp) {
+__global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, const T *src, T *dst, int nchunk) {
+  const int A = (int)blockIdx.z / nchunk, chunk = (int)blockIdx.z % nchunk;
+  const int ext0 = g.M[0] + (A != 0), ext1 = g.M[1] + (A != 1), ext2 = g.M[2] + (A != 2);
   const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
   const int j = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int k = (int)blockIdx.z;
-  if (i > g.M[0] || j > g.M[1] || k > g.M[2]) return;
-  const int id[3] = {i, j, k};
-  const long q = g.at(i, j, k);
-#pragma unroll
-  for (int A = 0; A < 3; ++A) {
-    if (id[A] > g.M[A] - 1) continue;   // outside J_A's extent
-    const T *J = F.J[A];
-    T acc = T(0);
-    for (int oz = -1; oz <= 1; ++oz) {
-      const int kk = k + oz;
-      if (kk < 0 || kk > g.M[2] - (A == 2)) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int jj = j + oy;
-        if (jj < 0 || jj > g.M[1] - (A == 1)) continue;
-        T row = T(0);
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int ii = i + ox;
-          if (ii < 0 || ii > g.M[0] - (A == 0)) continue;
-          row += (ox ? T(0.25) : T(0.5)) * J[q + ox + oy * g.sy + oz * g.sz];
-        }
-        acc += (oz ? T(0.25) : T(0.5)) * (oy ? T(0.25) : T(0.5)) * row;
-      }
-    }
-    tmp[(long)A * g.nelem + q] = acc;
+  const int k0 = chunk * FILT_KZ, k1 = min(k0 + FILT_KZ, ext2);
+  if (i >= ext0 || j >= ext1 || k0 >= k1) return;
+  const T *J = src + (size_t)A * g.nelem;
+  T *out = dst + (size_t)A * g.nelem;
+  const bool xl = i > 0, xr = i + 1 < ext0, yl = j > 0, yr = j + 1 < ext1;
+  auto row = [&](long q) {
+    T r = T(0.5) * J[q];
+    if (xl) r += T(0.25) * J[q - 1];
+    if (xr) r += T(0.25) * J[q + 1];
+    return r;
+  };
+  auto plane = [&](int k) {
+    if (k < 0 || k >= ext2) return T(0);
+    const long q = g.at(i, j, k);
+    T p = T(0.5) * row(q);
+    if (yl) p += T(0.25) * row(q - g.sy);
+    if (yr) p += T(0.25) * row(q + g.sy);
+    return p;
+  };
+  T pm = plane(k0 - 1), p0 = plane(k0);
+  for (int k = k0; k < k1; ++k) {
+    const T pp = plane(k + 1);
+    out[g.at(i, j, k)] = T(0.25) * pm + T(0.5) * p0 + T(0.25) * pp;
+    pm = p0;
+    p0 = pp;
   }
 }
 
+// passes alternate between J and tmp (the three components of each are adjacent); returns
+// the one that holds the result.  Samples outside the extents of tmp are never written
+// (the workspace starts zeroed).
 template <typename T>
-void launch_filter_current(const Grid<T> &g, const Fields<T> &F, T *tmp, int passes, hipStream_t s) {
-  if (g.dim != 3 || passes <= 0) return;
-  dim3 blk(256), grd((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, g.M[2] + 1);
+T *launch_filter_current(const Grid<T> &g, T *J, T *tmp, int passes, hipStream_t s) {
+  if (g.dim != 3 || passes <= 0) return J;
+  const int nchunk = (g.M[2] + 1 + FILT_KZ - 1) / FILT_KZ;
+  dim3 blk(256), grd((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, 3 * nchunk);
+  T *a = J, *b = tmp;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_filter_J<T>), grd, blk, 0, s, g, F, tmp);
-    for (int a = 0; a < 3; ++a)   // samples outside the extents come back as 0
-      (void)hipMemcpyAsync(F.J[a], tmp + (size_t)a * g.nelem, sizeof(T) * (size_t)g.nelem, hipMemcpyDeviceToDevice, s);
+    hipLaunchKernelGGL((k_filter_J<T>), grd, blk, 0, s, g, a, b, nchunk);
+    std::swap(a, b);
   }
+  return a;
 }
-template void launch_filter_current<float>(const Grid<float> &, const Fields<float> &, float *, int, hipStream_t);
-template void launch_filter_current<double>(const Grid<double> &, const Fields<double> &, double *, int, hipStream_t);
+template float *launch_filter_current<float>(const Grid<float> &, float *, float *, int, hipStream_t);
+template double *launch_filter_current<double>(const Grid<double> &, double *, double *, int, hipStream_t);
 
 template <typename T>
 void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s) {
