@@ -33,7 +33,7 @@ class OrcParams(C.Structure):
         ("alpha_mode", C.c_int), ("damping_scale", C.c_double), ("n_sigma_coef", C.c_int),
         ("sigma_coef", (C.c_double * 16) * 3), ("push", C.c_int),
         ("charge", C.c_double), ("mass", C.c_double),
-        ("solver", C.c_int), ("filter_passes", C.c_int),
+        ("solver", C.c_int), ("filter_passes", C.c_int), ("alpha_face", (C.c_int * 2) * 3),
     ]
 
 
@@ -85,6 +85,10 @@ def lib():
             "orc_rho": (None, [vp, dp]),
             "orc_get_lambda": (None, [vp, dp]),
             "orc_path_sigma": (d, [vp, dp, dp, d]),
+            "orc_set_conductor": (i, [vp, P(C.c_ubyte)]),
+            "orc_sample_in_conductor": (i, [vp, i, i, i, i]),
+            "orc_set_source": (i, [vp, l, dp, dp, dp, i]),
+            "orc_slab_moments": (None, [vp, i, i, dp, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -149,6 +153,10 @@ def make_params(cfg) -> OrcParams:
     p.mass = float(cfg.mass)
     p.solver = int(getattr(cfg, "solver", 0))
     p.filter_passes = int(getattr(cfg, "filter_passes", 0))
+    faces = getattr(cfg, "alpha_face", ((0, 0), (0, 0), (0, 0)))
+    for d in range(3):
+        for side in range(2):
+            p.alpha_face[d][side] = int(faces[d][side])
     return p
 
 
@@ -186,6 +194,37 @@ class OracleSim:
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
         w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
         lib().orc_set_particles(self._h, len(w), _lp(ids), _dp(X), _dp(u), _dp(w))
+
+    def set_conductor(self, cells):
+        """Conductor cells: uint8 array of shape (M_z, M_y, M_x) (cells including the PML),
+        nonzero = conductor; the fields inside are zeroed now and after every update."""
+        if cells is None:
+            rc = lib().orc_set_conductor(self._h, None)
+        else:
+            c = np.ascontiguousarray(cells, dtype=np.uint8).reshape(self.M[2], self.M[1], self.M[0])
+            self._cond = c
+            rc = lib().orc_set_conductor(self._h, c.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        if rc:
+            raise ValueError("oracle: conductors are 3D")
+
+    def sample_in_conductor(self, comp, i, j, k) -> bool:
+        return bool(lib().orc_sample_in_conductor(self._h, int(comp), int(i), int(j), int(k)))
+
+    def set_source(self, x, u, w, axis=2):
+        """Beam source: particles at the present time (physical x, u, w) injected when their
+        ballistic path reaches the outer wall of the low layer of `axis`."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, self.dim)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        if lib().orc_set_source(self._h, len(w), _dp(x), _dp(u), _dp(w), int(axis)):
+            raise ValueError("oracle: a source particle never enters the box")
+
+    def slab_moments(self, axis, edges) -> np.ndarray:
+        """(nslab, 5): count, sum w, sum w u_x, sum w u_y, sum w u_z per slab of `axis`."""
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        out = np.zeros((len(e) - 1, 5))
+        lib().orc_slab_moments(self._h, int(axis), len(e) - 1, _dp(e), _dp(out))
+        return out
 
     @property
     def num_particles(self) -> int:

@@ -114,22 +114,37 @@ double orc_alpha_axis(const orc_sim *s, int d, double X)
     return exp(-s->p.damping_scale * phi_of_depth(s, d, del, L));
 }
 
+/* Mode of the layer that grid coordinate X lies in along axis d: the face's own mode
+ * when one is set, else the global one.  Per-face modes are the combination the paper
+ * proposes for a beam that enters through one PML and leaves through the other (end of
+ * Sec. IV.A): undamped deposition (mode 1) where particles enter, Eq. (alpha) where
+ * they leave. */
+static int face_mode(const orc_sim *s, int d, double X)
+{
+    int side = X < (double)s->p.pml[d][0] ? 0 : 1;
+    int f = s->p.alpha_face[d][side];
+    return f > 0 ? f - 1 : s->p.alpha_mode;
+}
+
 /* Current-damping factor at a sample with grid coordinates X[3] (in-plane axes only).
  *   mode 0: alpha = 0 anywhere in the PML (standard Berenger PML, no source there);
  *   mode 1: alpha = 1 (undamped deposition);
  *   mode 2: Eq. (alpha); in edges and corners the product of the per-axis factors
  *           (reading: reduces to Eq. (alpha) on a face);
  *   mode 3: alpha = 1 in the field equations, each particle's weight damped instead
- *           (Sec. II.C, discussion of the velocity limitation; see path_sigma). */
+ *           (Sec. II.C, discussion of the velocity limitation; see path_sigma).
+ * With per-face modes each axis contributes the factor of the face the sample lies in
+ * (0, 1 or its exp(-Phi/v)), so a corner takes the product of its faces' factors. */
 double orc_alpha(const orc_sim *s, const double X[3])
 {
-    int mode = s->p.alpha_mode;
-    if (mode == 1 || mode == 3) return 1.0;
+    if (s->p.alpha_mode == 3) return 1.0;
     double a = 1.0;
     for (int d = 0; d < s->p.dim; ++d) {
         double L, del = depth(s, d, X[d], &L);
-        if (mode == 0) { if (del > 0.0) return 0.0; }
-        else a *= exp(-s->p.damping_scale * phi_of_depth(s, d, del, L));
+        if (del <= 0.0) continue;
+        int mode = face_mode(s, d, X[d]);
+        if (mode == 0) return 0.0;
+        if (mode == 2) a *= exp(-s->p.damping_scale * phi_of_depth(s, d, del, L));
     }
     return a;
 }
@@ -254,6 +269,7 @@ void orc_destroy(orc_sim *s)
     for (int q = 0; q < NPART; ++q) free(s->F[q]);
     for (int a = 0; a < 3; ++a) free(s->J[a]);
     free(s->rho_static); free(s->X); free(s->U); free(s->W); free(s->LAM); free(s->id);
+    free(s->cond); free(s->SX); free(s->SU); free(s->SW); free(s->sstep); free(s->sid);
     free(s);
 }
 
@@ -582,6 +598,63 @@ void orc_filter_current(orc_sim *s)
     free(tmp);
 }
 
+/* ---------------------------------------------------------------- conductors */
+
+/* Conductor cells (the cavity run of App. A.2 models the cavity walls by setting E and B
+ * to zero in the cells the walls cover).  Reading: a field sample is held at zero when it
+ * lies in the closed extent of any conductor cell, i.e. along each axis the one cell it is
+ * inside (half-integer coordinate) or the two cells it borders (integer coordinate).  On a
+ * wall between a vacuum cell and a conductor cell this zeroes the tangential E and the
+ * normal B, the perfect-conductor conditions of the staircase wall. */
+int orc_sample_in_conductor(const orc_sim *s, int c, int i, int j, int k)
+{
+    if (!s->cond) return 0;
+    int ii[3] = {i, j, k}, lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        if (stag_of(c, d)) { lo[d] = ii[d]; hi[d] = ii[d]; }
+        else { lo[d] = ii[d] - 1; hi[d] = ii[d]; }
+        if (lo[d] < 0) lo[d] = 0;
+        if (hi[d] > s->M[d] - 1) hi[d] = s->M[d] - 1;
+    }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+    for (int x = lo[0]; x <= hi[0]; ++x)
+        if (s->cond[((size_t)z * s->M[1] + y) * s->M[0] + x]) return 1;
+    return 0;
+}
+
+/* zeroes both split parts of every field sample inside a conductor */
+static void apply_conductor(orc_sim *s)
+{
+    if (!s->cond) return;
+    for (int c = 0; c < 6; ++c) {
+        int nv[3];
+        for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(c, d));
+        for (int k = 0; k < nv[2]; ++k)
+        for (int j = 0; j < nv[1]; ++j)
+        for (int i = 0; i < nv[0]; ++i)
+            if (orc_sample_in_conductor(s, c, i, j, k)) {
+                size_t q = idx3(s, i, j, k);
+                s->F[2 * c][q] = 0.0;
+                s->F[2 * c + 1][q] = 0.0;
+            }
+    }
+}
+
+/* Sets the conductor cells (3D only; NULL removes them) and zeroes the fields inside. */
+int orc_set_conductor(orc_sim *s, const unsigned char *cells)
+{
+    if (s->p.dim != 3) return -1;
+    free(s->cond);
+    s->cond = NULL;
+    if (!cells) return 0;
+    size_t nc = (size_t)s->M[0] * s->M[1] * s->M[2];
+    s->cond = (unsigned char *)malloc(nc);
+    memcpy(s->cond, cells, nc);
+    apply_conductor(s);
+    return 0;
+}
+
 static void advance(orc_sim *s, int is_e, double tau)
 {
     for (int a = 0; a < 3; ++a) {
@@ -629,6 +702,7 @@ static void advance(orc_sim *s, int is_e, double tau)
             }
         }
     }
+    apply_conductor(s);
 }
 
 /* J_a <- alpha J_a at J_a's samples (Eq. MaxwellE source term alpha j). */
@@ -662,17 +736,89 @@ void orc_deposit_into(orc_sim *s, const double X0[3], const double X1[3], double
     orc_deposit(s, X0, X1, vz, qw, s->J);
 }
 
+/* ---------------------------------------------------------------- beam source */
+
+/* Beam source (the cavity run of Sec. IV.A: a long beam injected continuously on one side
+ * of the box, through that side's PML).  Each particle is given at the present time by its
+ * physical position x (dim values), momentum u = gamma v and weight w, and moves
+ * ballistically until the first step start t = (step + m) dt, m >= 0, at which its
+ * position x + m dt v lies at or beyond the outer wall of the low layer of `axis`; it is
+ * added then, at that position (so its first move starts inside the box), with no static
+ * partner.  Ids follow the given order after those already assigned.  Fails (-1) for a
+ * particle that never reaches the box or reaches it outside the box along another axis. */
+int orc_set_source(orc_sim *s, long n, const double *x, const double *u, const double *w, int axis)
+{
+    int dim = s->p.dim;
+    if (axis < 0 || axis >= dim) return -1;
+    free(s->SX); free(s->SU); free(s->SW); free(s->sstep); free(s->sid);
+    s->SX = (double *)malloc(sizeof(double) * 3 * (n + 1));
+    s->SU = (double *)malloc(sizeof(double) * 3 * (n + 1));
+    s->SW = (double *)malloc(sizeof(double) * (n + 1));
+    s->sstep = (long *)malloc(sizeof(long) * (n + 1));
+    s->sid = (long *)malloc(sizeof(long) * (n + 1));
+    s->nsrc = 0;
+    s->src_next = 0;
+    double wall = -(double)s->p.pml[axis][0] * s->p.dx[axis];
+    s->next_id += n;
+    for (long t = 0; t < n; ++t) {
+        const double *ut = u + 3 * t;
+        double gam = sqrt(1.0 + ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+        double va = ut[axis] / gam;
+        double xa = x[dim * t + axis];
+        long m = 0;
+        if (xa < wall) {
+            if (!(va > 0.0)) { s->nsrc = 0; return -1; }
+            m = (long)ceil((wall - xa) / (va * s->p.dt));
+            if (m < 1) m = 1;
+            while (xa + (double)m * s->p.dt * va < wall) ++m;
+            while (m > 1 && xa + (double)(m - 1) * s->p.dt * va >= wall) --m;
+        }
+        long q = s->nsrc++;
+        for (int d = 0; d < 3; ++d) {
+            double Xd = 0.0;
+            if (d < dim) {
+                double xd = x[dim * t + d] + (double)m * s->p.dt * (ut[d] / gam);
+                Xd = xd / s->p.dx[d] + s->p.pml[d][0];
+                if (!(Xd >= 0.0 && Xd < (double)s->M[d])) { s->nsrc = 0; return -1; }
+            }
+            s->SX[3 * q + d] = Xd;
+            s->SU[3 * q + d] = ut[d];
+        }
+        s->SW[q] = w[t];
+        s->sstep[q] = s->step + m;
+        s->sid[q] = s->next_id - n + t;
+    }
+    return 0;
+}
+
+/* adds the source particles whose injection step is the present one */
+static void inject(orc_sim *s)
+{
+    for (long q = 0; q < s->nsrc; ++q) {
+        if (s->sstep[q] != s->step) continue;
+        reserve(s, s->np + 1);
+        long t = s->np++;
+        for (int d = 0; d < 3; ++d) { s->X[3 * t + d] = s->SX[3 * q + d]; s->U[3 * t + d] = s->SU[3 * q + d]; }
+        s->W[t] = s->SW[q];
+        s->LAM[t] = 0.0;
+        s->id[t] = s->sid[q];
+    }
+}
+
 /* One PIC step: E^n, B^n, X^n, u^{n-1/2}  ->  E^{n+1}, B^{n+1}, X^{n+1}, u^{n+1/2}.
+ *  0. source particles due at t^n are added (beam source, see orc_set_source);
  *  1. per particle: gather E^n, B^n at X^n (totals), Boris push (if enabled),
  *     X^{n+1} = X^n + dt u/gamma, Esirkepov deposit of X^n -> X^{n+1};
  *     particles ending outside the PEC box are removed after depositing;
  *  2. J <- alpha J (Eq. alpha / mode), after the binomial filter when it is on;
- *  3. B += dt/2 from E^n; E += dt from B^{n+1/2} and alpha J; B += dt/2 from E^{n+1}. */
+ *  3. B += dt/2 from E^n; E += dt from B^{n+1/2} and alpha J; B += dt/2 from E^{n+1};
+ *     after each of the three, samples inside conductor cells are set to zero. */
 void orc_step(orc_sim *s, int nsteps)
 {
     int dim = s->p.dim;
     double qdt_2m = s->p.charge * s->p.dt / (2.0 * s->p.mass);
     for (int it = 0; it < nsteps; ++it) {
+        inject(s);
         orc_zero_current(s);
         long keep = 0;
         for (long t = 0; t < s->np; ++t) {
@@ -778,4 +924,25 @@ void orc_rho(const orc_sim *s, double *rho)
 {
     memset(rho, 0, sizeof(double) * s->nsamp);
     for (long t = 0; t < s->np; ++t) deposit_rho(s, &s->X[3 * t], s->p.charge * particle_weight(s, t), 1.0, rho);
+}
+
+/* Beam moments per slab along `axis` (the deflection diagnostic of Sec. IV.A, the change
+ * of <u_x> = <p_x>/mc between planes): for slab k = [edges[k], edges[k+1]) in physical
+ * coordinates, out[5k .. 5k+4] = (number of particles, sum w, sum w u_x, sum w u_y,
+ * sum w u_z) over the particles whose position lies in it. */
+void orc_slab_moments(const orc_sim *s, int axis, int nslab, const double *edges, double *out)
+{
+    for (int k = 0; k < 5 * nslab; ++k) out[k] = 0.0;
+    for (long t = 0; t < s->np; ++t) {
+        double xa = (s->X[3 * t + axis] - s->p.pml[axis][0]) * s->p.dx[axis];
+        for (int k = 0; k < nslab; ++k) {
+            if (xa >= edges[k] && xa < edges[k + 1]) {
+                double w = s->W[t];
+                out[5 * k + 0] += 1.0;
+                out[5 * k + 1] += w;
+                for (int d = 0; d < 3; ++d) out[5 * k + 2 + d] += w * s->U[3 * t + d];
+                break;
+            }
+        }
+    }
 }

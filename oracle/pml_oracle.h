@@ -23,6 +23,8 @@ typedef struct {
     double charge, mass;     /* per unit weight */
     int solver;              /* 0: Yee; 1: Cole-Karkkainen in Faraday's law (3D, cubic cells) */
     int filter_passes;       /* binomial passes over the deposited current (0: none) */
+    int alpha_face[3][2];    /* per-face alpha mode, low / high side: 0 = alpha_mode,
+                                else 1 + mode (modes 0, 1, 2 only) */
 } orc_params;
 
 typedef struct {
@@ -38,6 +40,10 @@ typedef struct {
     double *LAM;             /* mode 3: int sigma/eps0 dt along each particle's path */
     long *id;
     long step;
+    unsigned char *cond;     /* conductor cells (M0 x M1 x M2, x fastest), NULL if none */
+    long nsrc, src_next;     /* beam source: entries sorted by injection step */
+    double *SX, *SU, *SW;    /* grid coordinates at injection, u, w */
+    long *sstep, *sid;
 } orc_sim;
 
 double orc_shape(int order, double d);
@@ -72,5 +78,9 @@ void orc_diagnose(const orc_sim *s, double out[7]);
 void orc_rho(const orc_sim *s, double *rho);
 void orc_get_lambda(const orc_sim *s, double *lam);
 double orc_path_sigma(const orc_sim *s, const double X0[3], const double X1[3], double tau);
+int orc_set_conductor(orc_sim *s, const unsigned char *cells);
+int orc_sample_in_conductor(const orc_sim *s, int c, int i, int j, int k);
+int orc_set_source(orc_sim *s, long n, const double *x, const double *u, const double *w, int axis);
+void orc_slab_moments(const orc_sim *s, int axis, int nslab, const double *edges, double *out);
 
 #endif

@@ -40,6 +40,7 @@ class SimConfig:
     max_particles: int = 0
     solver: int = 0                     # 0 Yee; 1 Cole-Karkkainen in Faraday's law (3D, cubic cells)
     filter_passes: int = 0              # binomial passes over the deposited current (3D)
+    alpha_face: tuple = ((0, 0), (0, 0), (0, 0))   # per face (low, high): 0 = alpha_mode, else 1 + mode
 
     def total_cells(self) -> int:
         t = 1
