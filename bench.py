@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("particles.hip", "fields.hip", "batch.hip", "api.hip", "common.h", "field_core.h", "fused2d.h",
-              "particle_core.h"):
+    for f in ("particles.hip", "fields.hip", "batch.hip", "api.hip", "beam.hip", "common.h", "field_core.h",
+              "fused2d.h", "particle_core.h"):
         with open(os.path.join(ROOT, "paper_2201_09084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

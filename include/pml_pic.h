@@ -101,6 +101,15 @@ typedef struct {
                                    current before the field update: each sample becomes the
                                    (1/4, 1/2, 1/4)^3-weighted sum of its 27 neighbours (samples
                                    outside the component's extent count as 0); 0..4 */
+    int32_t alpha_face[3][2];   /* per-face damping mode (low / high side of each axis):
+                                   0 = alpha_mode; 1 + PML_ALPHA_ZERO / ONE / DAMPED for that
+                                   face's layer.  The paper's suggestion for a beam entering
+                                   through one PML and leaving through the other (end of Sec.
+                                   IV.A): undamped where it enters, Eq. (alpha) where it
+                                   leaves.  A sample in an edge or corner takes the product of
+                                   its faces' factors.  Not with PML_ALPHA_WEIGHT. */
+    int32_t conductor;          /* 1: reserve a conductor mask (pml_pic_set_conductor); 3D */
+    int64_t max_source;         /* capacity of the beam source (pml_pic_set_source), particles */
 } pml_pic_params;
 
 enum { PML_PIC_SOLVER_YEE = 0, PML_PIC_SOLVER_CK = 1 };
@@ -190,6 +199,39 @@ int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count);
 /* Static partner charge density at the nodes (n_samples doubles). */
 int pml_pic_get_rho_static(pml_pic_handle *h, double *host, int64_t count);
 int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count);
+
+/* ------------------------------------------------------------------ beam transport
+ * The pieces of the paper's cavity run (Sec. IV.A, App. A.2): conductor cells, a beam
+ * injected continuously through the entry PML, and the beam's momentum moments per slab
+ * (the <u_x> deflection diagnostic). */
+
+/* Conductor cells (3D; needs params.conductor = 1).  cells: host array of M_0 M_1 M_2
+ * bytes (cells including the PML, x fastest), nonzero = conductor, or NULL to remove
+ * them.  The paper models the cavity walls by setting E and B to zero in the cells they
+ * cover; here every field sample lying in the closed extent of a conductor cell (on a
+ * wall between a vacuum and a conductor cell too) is set to zero now and after each field
+ * update, which on a wall zeroes the tangential E and the normal B.  Particles are not
+ * affected by conductors.  Synchronises. */
+int pml_pic_set_conductor(pml_pic_handle *h, const uint8_t *cells);
+
+/* Beam source (Sec. IV.A: a long beam injected on one side of the box through that
+ * side's PML).  x (n x dim, physical), u (n x 3), w (n): host arrays giving each
+ * particle's state at the present time; it moves ballistically until the first step
+ * start t = (step + m) dt, m >= 0, at which x + m dt v lies at or beyond the outer wall
+ * of the low layer of `axis`, and is added then at that position (no static partner;
+ * ids follow those already given, in the order given).  Replaces an earlier source.
+ * Needs n <= params.max_source and room for n more particles (max_particles).  Returns
+ * PML_PIC_E_INVALID_ARG if a particle never reaches the wall or reaches it outside the
+ * box along another axis.  Synchronises. */
+int pml_pic_set_source(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w,
+                       int32_t axis);
+
+/* Beam moments per slab along `axis`: edges (n_slabs + 1 increasing physical
+ * coordinates, host); out (host, n_slabs x 5 doubles) receives for each slab
+ * [edges[k], edges[k+1]) the number of live particles in it, sum w, sum w u_x,
+ * sum w u_y and sum w u_z (FP64 sums).  <u_x> = out[2] / out[1] per slab gives the
+ * deflection diagnostic of Sec. IV.A.  1 <= n_slabs <= 64.  Synchronises. */
+int pml_pic_slab_moments(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const double *edges, double *out);
 
 /* Live particle count (synchronises). */
 int pml_pic_num_particles(pml_pic_handle *h, int64_t *n);

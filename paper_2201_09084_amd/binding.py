@@ -29,7 +29,7 @@ EXPORTED = [
     "pml_pic_batch_workspace_size", "pml_pic_batch_create", "pml_pic_batch_run",
     "pml_pic_batch_set_launch", "pml_pic_batch_step", "pml_pic_batch_last_error",
     "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
-    "pml_pic_backward",
+    "pml_pic_backward", "pml_pic_set_conductor", "pml_pic_set_source", "pml_pic_slab_moments",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("charge", C.c_double), ("mass", C.c_double), ("flags", C.c_int32),
         ("adjoint_segment", C.c_int32), ("adjoint_checkpoints", C.c_int32),
         ("solver", C.c_int32), ("filter_passes", C.c_int32),
+        ("alpha_face", (C.c_int32 * 2) * 3), ("conductor", C.c_int32), ("max_source", C.c_int64),
     ]
 
 
@@ -102,6 +103,9 @@ def load_library():
             "pml_pic_batch_destroy": (None, [vp]),
             "pml_pic_forward_ckpt": (C.c_int, [vp, i32, dp]),
             "pml_pic_backward": (C.c_int, [vp, dp, i64, dp, dp, i32]),
+            "pml_pic_set_conductor": (C.c_int, [vp, P(C.c_uint8)]),
+            "pml_pic_set_source": (C.c_int, [vp, i64, dp, dp, dp, i32]),
+            "pml_pic_slab_moments": (C.c_int, [vp, i32, i32, dp, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -141,6 +145,12 @@ def make_params(cfg, max_particles=None, flags=0, adjoint=(0, 0)) -> Params:
     p.adjoint_checkpoints = int(adjoint[1])
     p.solver = int(getattr(cfg, "solver", 0))
     p.filter_passes = int(getattr(cfg, "filter_passes", 0))
+    faces = getattr(cfg, "alpha_face", ((0, 0), (0, 0), (0, 0)))
+    for d in range(3):
+        for side in range(2):
+            p.alpha_face[d][side] = int(faces[d][side])
+    p.conductor = int(getattr(cfg, "conductor", 0))
+    p.max_source = int(getattr(cfg, "max_source", 0))
     return p
 
 
@@ -218,6 +228,32 @@ class PmlPic:
         u = np.ascontiguousarray(u, dtype=np.float64)
         w = np.ascontiguousarray(w, dtype=np.float64)
         self._check(load_library().pml_pic_add_particles(self._h, len(w), _dp(x), _dp(u), _dp(w)))
+
+    def set_conductor(self, cells):
+        """Conductor cells: uint8 array of shape (M_z, M_y, M_x), nonzero = conductor (None
+        removes them)."""
+        L = load_library()
+        if cells is None:
+            self._check(L.pml_pic_set_conductor(self._h, None))
+            return
+        M = [self.nn[d] - 1 for d in range(3)]
+        c = np.ascontiguousarray(cells, dtype=np.uint8).reshape(M[2], M[1], M[0])
+        self._check(L.pml_pic_set_conductor(self._h, c.ctypes.data_as(C.POINTER(C.c_uint8))))
+
+    def set_source(self, x, u, w, axis=2):
+        """Beam source: particles at the present time, injected when their ballistic path
+        reaches the outer wall of the low layer of `axis`."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(load_library().pml_pic_set_source(self._h, len(w), _dp(x), _dp(u), _dp(w), int(axis)))
+
+    def slab_moments(self, axis, edges) -> np.ndarray:
+        """(nslab, 5): count, sum w, sum w u_x, sum w u_y, sum w u_z per slab of `axis`."""
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        out = np.zeros((len(e) - 1, 5))
+        self._check(load_library().pml_pic_slab_moments(self._h, int(axis), len(e) - 1, _dp(e), _dp(out)))
+        return out
 
     def set_particles(self, ids, X, u, w):
         ids = np.ascontiguousarray(ids, dtype=np.int64)

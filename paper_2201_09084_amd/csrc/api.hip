@@ -39,6 +39,10 @@ struct Layout {
   size_t off_items = 0, max_items = 0, off_jbox = 0, off_jslot = 0;
   size_t off_rflags = 0, off_nitems = 0, max_ranges = 0;
   size_t off_rho = 0, off_rho_static = 0, off_partial = 0, off_result = 0, off_flags = 0;
+  size_t off_cmask = 0;                     // conductor flags per node (params.conductor)
+  size_t off_src_cell = 0, off_src_f[3] = {}, off_src_u[3] = {}, off_src_w = 0, off_src_id = 0;
+  int64_t src_cap = 0;                      // beam source entries (params.max_source)
+  size_t off_slab = 0;                      // slab moments: edges and sums (FP64)
   int nkeys = 0, tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1}, nscan = 0, diag_blocks = 0;
   // adjoint storage (present when adjoint_segment > 0)
   int seg = 0, nckpt = 0;            // segment length, checkpoint slots (incl. the final state)
@@ -81,6 +85,15 @@ void profile(const pml_pic_params &p, int d, double X, double *sigma, double *ph
   }
 }
 
+// The mode the kernels apply: with per-face modes the alpha tables carry each face's
+// factor (0, 1 or Eq. alpha), so the kernels multiply by the tables as in mode 2.
+int kernel_alpha_mode(const pml_pic_params &p) {
+  for (int d = 0; d < 3; ++d)
+    for (int side = 0; side < 2; ++side)
+      if (p.alpha_face[d][side] != 0) return PML_ALPHA_DAMPED;
+  return p.alpha_mode;
+}
+
 int validate(const pml_pic_params *p, std::string *err) {
   if (!p) return fail(err, PML_PIC_E_INVALID_ARG, "params is NULL");
   if (p->dim != 2 && p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "dim must be 2 or 3");
@@ -106,11 +119,23 @@ int validate(const pml_pic_params *p, std::string *err) {
     if (std::fabs(p->dx[1] - p->dx[0]) > 1e-12 * p->dx[0] || std::fabs(p->dx[2] - p->dx[0]) > 1e-12 * p->dx[0])
       return fail(err, PML_PIC_E_INVALID_ARG, "the CK solver needs cubic cells");
     if (!(p->dt <= p->dx[0] * (1.0 + 1e-12))) return fail(err, PML_PIC_E_CFL, "c dt exceeds the CK limit dx");
-  } else if (!(p->dt < 1.0 / std::sqrt(s2))) {
+  } else if (!(p->dt <= (1.0 + 1e-12) / std::sqrt(s2))) {
     return fail(err, PML_PIC_E_CFL, "c dt violates the Yee CFL limit");
   }
   if (p->filter_passes < 0 || p->filter_passes > 4) return fail(err, PML_PIC_E_INVALID_ARG, "filter_passes must be in [0,4]");
   if (p->filter_passes > 0 && p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "the current filter is 3D");
+  bool faces = false;
+  for (int d = 0; d < 3; ++d)
+    for (int side = 0; side < 2; ++side) {
+      const int f = p->alpha_face[d][side];
+      if (f < 0 || f > 3) return fail(err, PML_PIC_E_INVALID_ARG, "alpha_face entries must be 0 (global) or 1 + mode 0..2");
+      faces = faces || f != 0;
+    }
+  if (faces && p->alpha_mode == PML_ALPHA_WEIGHT)
+    return fail(err, PML_PIC_E_INVALID_ARG, "per-face alpha modes do not combine with PML_ALPHA_WEIGHT");
+  if (p->conductor != 0 && p->conductor != 1) return fail(err, PML_PIC_E_INVALID_ARG, "conductor must be 0 or 1");
+  if (p->conductor && p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "conductors are 3D");
+  if (p->max_source < 0) return fail(err, PML_PIC_E_INVALID_ARG, "max_source < 0");
   if (p->shape_order < 1 || p->shape_order > 3) return fail(err, PML_PIC_E_INVALID_ARG, "shape_order must be 1, 2 or 3");
   if (p->alpha_mode < 0 || p->alpha_mode > 3) return fail(err, PML_PIC_E_INVALID_ARG, "alpha_mode must be 0, 1, 2 or 3");
   if (!(p->damping_scale >= 0.0) || !std::isfinite(p->damping_scale))
@@ -211,6 +236,17 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   // slots of the boxes of nodes given current by the 2D deposits, three sets in rotation
   // (this step's, the last step's being cleared, the next step's being emptied)
   L.off_jslot = take(3 * 16 * JSLOTS);
+  if (p.conductor) L.off_cmask = take((size_t)L.nelem);
+  L.src_cap = p.max_source;
+  if (p.max_source > 0) {
+    const size_t ns = (size_t)p.max_source;
+    L.off_src_cell = take(4 * ns);
+    for (int d = 0; d < p.dim; ++d) L.off_src_f[d] = take(L.esz * ns);
+    for (int d = 0; d < 3; ++d) L.off_src_u[d] = take(L.esz * ns);
+    L.off_src_w = take(L.esz * ns);
+    L.off_src_id = take(4 * ns);
+  }
+  L.off_slab = take(8 * (6 * (size_t)SLAB_MAX + 1));
   if (p.adjoint_segment > 0) {
     const size_t fb = L.esz * (size_t)L.nelem;          // one field array (multiple of 256 bytes)
     L.seg = p.adjoint_segment;
@@ -257,6 +293,9 @@ struct pml_pic_handle {
   std::vector<char *> snap_state, snap_J;
   // the last step's filtered current lives in the filter's scratch arrays (odd passes)
   bool j_in_tmp = false;
+  bool has_cond = false;                 // conductor mask set
+  std::vector<int64_t> src_steps;        // injection step of each source entry (sorted)
+  int64_t src_next = 0;                  // first entry not injected yet
 
   template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
   double tab(int axis, int kind, int i) const { return tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G]; }
@@ -285,6 +324,7 @@ struct pml_pic_handle {
     g.ntab = L.ntab;
     g.wdamp = p.alpha_mode == PML_ALPHA_WEIGHT ? 1 : 0;
     g.prof = at<T>(L.off_tab) + 3 * T_NKIND * (size_t)L.ntab;
+    g.cmask = has_cond ? at<uint8_t>(L.off_cmask) : nullptr;
     return g;
   }
   // offset of field array idx (0..11: E, B, Ea, Ba) of set `set`
@@ -316,6 +356,19 @@ struct pml_pic_handle {
     P.w = at<T>(L.off_w[b]);
     P.lam = p.alpha_mode == PML_ALPHA_WEIGHT ? at<T>(L.off_lam[b]) : nullptr;
     P.id = at<int32_t>(L.off_id[b]);
+    return P;
+  }
+  // the beam source entries, in the particle format (no damping integral)
+  template <typename T> Parts<T> src_parts() const {
+    Parts<T> P;
+    P.cell = at<uint32_t>(L.off_src_cell);
+    for (int d = 0; d < 3; ++d) {
+      P.f[d] = d < p.dim ? at<T>(L.off_src_f[d]) : nullptr;
+      P.u[d] = at<T>(L.off_src_u[d]);
+    }
+    P.w = at<T>(L.off_src_w);
+    P.lam = nullptr;
+    P.id = at<int32_t>(L.off_src_id);
     return P;
   }
   template <typename T> Parts<T> old_parts() const {
@@ -422,8 +475,11 @@ void build_tables(pml_pic_handle *h) {
           else { ev[t] = 1.0; gv[t] = taus[t]; }
         }
         double alpha = 1.0;
-        if (p.alpha_mode == PML_ALPHA_ZERO) alpha = dep > 0.0 ? 0.0 : 1.0;
-        else if (p.alpha_mode == PML_ALPHA_DAMPED) alpha = std::exp(-p.damping_scale * phi);
+        // the layer's mode: that of its face when one is set, else the global one
+        const int face = d < 3 ? p.alpha_face[d][X < (double)p.pml[d][0] ? 0 : 1] : 0;
+        const int mode = face ? face - 1 : p.alpha_mode;
+        if (dep > 0.0 && mode == PML_ALPHA_ZERO) alpha = 0.0;
+        else if (mode == PML_ALPHA_DAMPED) alpha = std::exp(-p.damping_scale * phi);
         if (d < p.dim && !in_grid) alpha = 0.0;   // guard samples: no current
         const int k0 = centre ? T_SIG_C : T_SIG_N;
         const double inv_dx = 1.0 / (d < p.dim ? p.dx[d] : 1.0);
@@ -524,7 +580,7 @@ int get_current_t(pml_pic_handle *h, double *out) {
   const Layout &L = h->L;
   const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
   std::vector<T> buf(L.nelem);
-  const bool alpha_in_update = !(h->p.flags & PML_PIC_FLAG_SEPARATE_DAMP) && current_alpha(h->p.alpha_mode);
+  const bool alpha_in_update = !(h->p.flags & PML_PIC_FLAG_SEPARATE_DAMP) && current_alpha(kernel_alpha_mode(h->p));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int a = 0; a < 3; ++a) {
     // 2D one-pass runs: the buffer of the last step (the parity flipped after it)
@@ -653,13 +709,25 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   // The E update zeroes J only where it updates E; the filter also reads the samples on
   // the PEC walls, so with the filter J is cleared before every deposit instead.
   const bool keep_j = (fl & PML_PIC_FLAG_KEEP_CURRENT) != 0 || one_pass || h->p.filter_passes > 0;
-  const int ns = (int)h->n_slots;
+  const int amode = kernel_alpha_mode(h->p);
   hipStream_t s = h->stream;
   const size_t jbytes = sizeof(T) * (size_t)h->L.nelem;
   int *jslot = h->at<int>(h->L.off_jslot);
   for (int it = 0; it < nsteps; ++it) {
     Fields<T> F = h->fields<T>();
     StepCtl ctl = h->ctl();
+    // beam source: the entries due at this step join the particles (sorted in below)
+    int64_t due = 0;
+    while (h->src_next + due < (int64_t)h->src_steps.size() && h->src_steps[h->src_next + due] == h->step) ++due;
+    if (due > 0) {
+      if (h->n_slots + due > h->L.cap)
+        return fail(&h->err, PML_PIC_E_CAPACITY, "max_particles exceeded by the beam source");
+      launch_inject<T>(h->p.dim, h->parts<T>(h->cur), h->src_parts<T>(), ctl.count, h->src_next, (int)due, s);
+      h->src_next += due;
+      h->n_slots += due;
+      h->sort_pending = true;
+    }
+    const int ns = (int)h->n_slots;
     const int ph = h->jphase % 3;
     int *slot_cur = jslot + 4 * JSLOTS * ph;                 // this step's boxes
     JClear<T> jc{{nullptr, nullptr, nullptr}, nullptr, nullptr};
@@ -715,7 +783,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (it < (int)h->snap_J.size())
       HIPCHK(h, hipMemcpyAsync(h->snap_J[it], F.J[0], h->L.J_bytes, hipMemcpyDeviceToDevice, s));
-    if (sep_damp && current_alpha(h->p.alpha_mode)) {
+    if (sep_damp && current_alpha(amode)) {
       pt.begin(s);
       launch_damp_current<T>(g, F, s);
       pt.end(s, PML_PIC_PHASE_DAMP);
@@ -723,7 +791,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     if (one_pass) {
       pt.begin(s);
       launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), slot_cur,
-                             !sep_damp && current_alpha(h->p.alpha_mode), s);
+                             !sep_damp && current_alpha(amode), s);
       pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
       h->fset = 1 - h->fset;
       h->jphase++;
@@ -732,7 +800,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       launch_update_B<T>(g, F, true, s);
       pt.end(s, PML_PIC_PHASE_UPDATE_B);
       pt.begin(s);
-      launch_update_E<T>(g, F, !sep_damp, h->p.alpha_mode, !keep_j, s);
+      launch_update_E<T>(g, F, !sep_damp, amode, !keep_j, s);
       pt.end(s, PML_PIC_PHASE_UPDATE_E);
       pt.begin(s);
       launch_update_B<T>(g, F, true, s);
@@ -918,6 +986,8 @@ int batch_layout(const pml_pic_params *runs, int32_t n, std::vector<Layout> &Ls,
       if (err) *err = "run " + std::to_string(r) + ": " + *err;
       return rc;
     }
+    if (runs[r].conductor || runs[r].max_source > 0)
+      return fail(err, PML_PIC_E_INVALID_ARG, "batched runs have neither conductors nor sources");
     if (runs[r].dim != runs[0].dim || runs[r].shape_order != runs[0].shape_order ||
         runs[r].precision != runs[0].precision)
       return fail(err, PML_PIC_E_INVALID_ARG, "all runs of a batch need the same dim, shape_order and precision");
@@ -952,7 +1022,7 @@ int batch_upload_descs(pml_pic_batch *b) {
     d[r].ctl = h->ctl();
     d[r].n_slots = (int)h->n_slots;
     d[r].push = h->p.push;
-    d[r].alpha_mode = h->p.alpha_mode;
+    d[r].alpha_mode = kernel_alpha_mode(h->p);
     d[r].pad = 0;
     b->slots_seen[r] = h->n_slots;
   }
@@ -1242,6 +1312,175 @@ int pml_pic_add_particles(pml_pic_handle *h, int64_t n, const double *x, const d
   return PML_PIC_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ beam transport
+namespace {
+
+// Conductor flags per node: bit c (E_x, E_y, E_z, B_x, B_y, B_z) when sample c at that
+// node index lies in the closed extent of a conductor cell -- along each axis the one cell
+// a half-integer coordinate is inside, or the cells an integer coordinate borders.
+void conductor_bits(const Layout &L, const uint8_t *cells, std::vector<uint8_t> &bits) {
+  bits.assign((size_t)L.nelem, 0);
+  auto cell_at = [&](int x, int y, int z) { return cells[((size_t)z * L.M[1] + y) * L.M[0] + x] != 0; };
+  for (int k = 0; k <= L.M[2]; ++k)
+    for (int j = 0; j <= L.M[1]; ++j)
+      for (int i = 0; i <= L.M[0]; ++i) {
+        const int id[3] = {i, j, k};
+        uint8_t m = 0;
+        for (int c = 0; c < 6; ++c) {
+          const int a = c % 3;
+          int lo[3], hi[3];
+          bool any_cell = true;
+          for (int d = 0; d < 3; ++d) {
+            const bool half = c < 3 ? d == a : d != a;   // E_a half-integer along a, B_a across a
+            lo[d] = half ? id[d] : id[d] - 1;
+            hi[d] = id[d];
+            lo[d] = std::max(lo[d], 0);
+            hi[d] = std::min(hi[d], L.M[d] - 1);
+            if (lo[d] > hi[d]) any_cell = false;
+          }
+          if (!any_cell) continue;
+          bool in = false;
+          for (int z = lo[2]; z <= hi[2] && !in; ++z)
+            for (int y = lo[1]; y <= hi[1] && !in; ++y)
+              for (int x = lo[0]; x <= hi[0] && !in; ++x) in = cell_at(x, y, z);
+          if (in) m |= (uint8_t)(1u << c);
+        }
+        bits[(size_t)(L.base + i + (long)j * L.sy + (long)k * L.sz)] = m;
+      }
+}
+
+template <typename T>
+int upload_source(pml_pic_handle *h, const std::vector<int64_t> &order, const std::vector<double> &X,
+                  const double *u, const double *w, int64_t first_id) {
+  const Layout &L = h->L;
+  const int dim = h->p.dim;
+  const size_t n = order.size();
+  std::vector<uint32_t> cell(n);
+  std::vector<T> f[3], uu[3], ww(n);
+  std::vector<int32_t> id(n);
+  for (int d = 0; d < 3; ++d) { f[d].resize(n); uu[d].resize(n); }
+  for (size_t q = 0; q < n; ++q) {
+    const int64_t t = order[q];
+    int ic[3];
+    T ff[3];
+    if (!to_cell<T>(L, dim, &X[3 * t], ic, ff)) {
+      h->err = "source particle " + std::to_string(t) + " enters the box outside it along another axis";
+      return PML_PIC_E_INVALID_ARG;
+    }
+    cell[q] = pack_cell(dim, ic[0], ic[1], ic[2]);
+    for (int d = 0; d < 3; ++d) { f[d][q] = ff[d]; uu[d][q] = (T)u[3 * t + d]; }
+    ww[q] = (T)w[t];
+    id[q] = (int32_t)(first_id + t);
+  }
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(h->at<uint32_t>(L.off_src_cell), cell.data(), 4 * n, hipMemcpyHostToDevice, s));
+  for (int d = 0; d < dim; ++d)
+    HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_src_f[d]), f[d].data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  for (int d = 0; d < 3; ++d)
+    HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_src_u[d]), uu[d].data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->at<T>(L.off_src_w), ww.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->at<int32_t>(L.off_src_id), id.data(), 4 * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return PML_PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pml_pic_set_conductor(pml_pic_handle *h, const uint8_t *cells) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  if (!h->p.conductor) return fail(&h->err, PML_PIC_E_INVALID_ARG, "created without params.conductor");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!cells) {
+    h->has_cond = false;
+    return PML_PIC_OK;
+  }
+  std::vector<uint8_t> bits;
+  conductor_bits(h->L, cells, bits);
+  HIPCHK(h, hipMemcpy(h->at<uint8_t>(h->L.off_cmask), bits.data(), bits.size(), hipMemcpyHostToDevice));
+  h->has_cond = true;
+  if (h->p.precision == 64) launch_apply_conductor<double>(h->grid<double>(), h->fields<double>(), h->stream);
+  else launch_apply_conductor<float>(h->grid<float>(), h->fields<float>(), h->stream);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PML_PIC_OK;
+}
+
+int pml_pic_set_source(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w, int32_t axis) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  const int dim = h->p.dim;
+  if (n < 0 || (n > 0 && (!x || !u || !w))) return fail(&h->err, PML_PIC_E_INVALID_ARG, "bad source arrays");
+  if (axis < 0 || axis >= dim) return fail(&h->err, PML_PIC_E_INVALID_ARG, "axis out of range");
+  if (n > h->L.src_cap) return fail(&h->err, PML_PIC_E_CAPACITY, "more source particles than params.max_source");
+  if (h->n_slots + n > h->L.cap) return fail(&h->err, PML_PIC_E_CAPACITY, "max_particles too small for the source");
+  // injection step and position of each particle (FP64): the first step start m >= 0 at
+  // which its ballistic position lies at or beyond the outer wall of the low layer
+  const double wall = -(double)h->p.pml[axis][0] * h->p.dx[axis];
+  const double dt = h->p.dt;
+  std::vector<int64_t> m(n);
+  std::vector<double> X(3 * (size_t)n, 0.0);
+  for (int64_t t = 0; t < n; ++t) {
+    const double *ut = u + 3 * t;
+    const double gam = std::sqrt(1.0 + ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+    const double va = ut[axis] / gam, xa = x[dim * t + axis];
+    if (!std::isfinite(xa) || !std::isfinite(gam) || !std::isfinite(w[t]))
+      return fail(&h->err, PML_PIC_E_INVALID_ARG, "non-finite source particle");
+    int64_t k = 0;
+    if (xa < wall) {
+      if (!(va > 0.0)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "a source particle never reaches the box");
+      const double need = (wall - xa) / (va * dt);
+      if (!(need < 1e15)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "a source particle never reaches the box");
+      k = std::max<int64_t>(1, (int64_t)std::ceil(need));
+      while (xa + (double)k * dt * va < wall) ++k;
+      while (k > 1 && xa + (double)(k - 1) * dt * va >= wall) --k;
+    }
+    m[t] = k;
+    for (int d = 0; d < dim; ++d) {
+      const double xd = x[dim * t + d] + (double)k * dt * (ut[d] / gam);
+      X[3 * t + d] = xd / h->p.dx[d] + h->p.pml[d][0];
+    }
+  }
+  std::vector<int64_t> order(n);
+  for (int64_t t = 0; t < n; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return m[a] < m[b]; });
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const int rc = n == 0 ? 0
+                        : (h->p.precision == 64 ? upload_source<double>(h, order, X, u, w, h->n_added)
+                                                : upload_source<float>(h, order, X, u, w, h->n_added));
+  if (rc) return rc;
+  h->src_steps.resize(n);
+  for (int64_t q = 0; q < n; ++q) h->src_steps[q] = h->step + m[order[q]];
+  h->src_next = 0;
+  h->n_added += n;
+  return PML_PIC_OK;
+}
+
+int pml_pic_slab_moments(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const double *edges, double *out) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  if (axis < 0 || axis >= h->p.dim) return fail(&h->err, PML_PIC_E_INVALID_ARG, "axis out of range");
+  if (n_slabs < 1 || n_slabs > SLAB_MAX) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_slabs must be in [1,64]");
+  if (!edges || !out) return fail(&h->err, PML_PIC_E_INVALID_ARG, "edges and out are required");
+  for (int k = 0; k < n_slabs; ++k)
+    if (!(edges[k] < edges[k + 1])) return fail(&h->err, PML_PIC_E_INVALID_ARG, "edges must increase");
+  double *dev = h->at<double>(h->L.off_slab);
+  double *dsum = dev + SLAB_MAX + 1;
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(dev, edges, sizeof(double) * (n_slabs + 1), hipMemcpyHostToDevice, s));
+  if (h->p.precision == 64)
+    launch_slab_moments<double>(h->grid<double>(), h->parts<double>(h->cur), h->ctl().count, (int)h->n_slots, axis,
+                                h->p.dx[axis], n_slabs, dev, dsum, s);
+  else
+    launch_slab_moments<float>(h->grid<float>(), h->parts<float>(h->cur), h->ctl().count, (int)h->n_slots, axis,
+                               h->p.dx[axis], n_slabs, dev, dsum, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(out, dsum, sizeof(double) * 5 * n_slabs, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return PML_PIC_OK;
+}
+
 int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X, const double *u,
                           const double *w) {
   if (!h) return PML_PIC_E_INVALID_ARG;
@@ -1437,6 +1676,8 @@ int check_adjoint(pml_pic_handle *h) {
     return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint does not cover per-particle weight damping");
   if (h->p.solver != PML_PIC_SOLVER_YEE || h->p.filter_passes > 0)
     return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint covers the Yee solver without current filter");
+  if (kernel_alpha_mode(h->p) != h->p.alpha_mode || h->p.conductor || h->p.max_source > 0)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint covers neither per-face modes, conductors nor sources");
   return PML_PIC_OK;
 }
 

@@ -70,6 +70,8 @@ struct Grid {
   int ntab;
   int wdamp;           // 1: per-particle weight damping (alpha mode 3)
   const T *prof;       // [3][PROF_N]: layer edges, thicknesses and sigma coefficients
+  const uint8_t *cmask;  // conductor: per node, bit c set when sample c (E_x..E_z, B_x..B_z)
+                         // at that node index lies in a conductor cell; null without conductors
 
   __host__ __device__ long at(int i, int j, int k) const { return base + i + j * sy + k * sz; }
   __device__ T tb(int axis, int kind, int i) const {
@@ -228,6 +230,16 @@ template <typename T>
 T *launch_filter_current(const Grid<T> &g, T *J, T *tmp, int passes, hipStream_t s);
 template <typename T>
 void launch_damp_current(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
+// beam transport: conductor mask applied to the fields, source injection, slab moments
+constexpr int SLAB_MAX = 64;
+template <typename T>
+void launch_apply_conductor(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
+template <typename T>
+void launch_inject(int dim, const Parts<T> &P, const Parts<T> &S, int32_t *count, int64_t first, int n,
+                   hipStream_t s);
+template <typename T>
+void launch_slab_moments(const Grid<T> &g, const Parts<T> &P, const int32_t *count, int n_slots, int axis, double dxa,
+                         int nslab, const double *edges, double *out, hipStream_t s);
 template <typename T>
 void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                         StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s);

@@ -70,6 +70,10 @@ __device__ __forceinline__ void update_B_comp(const Grid<T> &g, const Fields<T> 
       F.B[A][q] = fma(-gkb, Db, fma(gkc, Dc, F.B[A][q]));
     }
   }
+  if (DIM == 3 && g.cmask && ((gptr(g.cmask)[q] >> (3 + A)) & 1)) {   // inside a conductor
+    F.B[A][q] = T(0);
+    F.Ba[A][q] = T(0);
+  }
 }
 
 // alpha at J_A's sample (i,j,k): product of per-axis factors (centre along A)
@@ -115,6 +119,10 @@ __device__ __forceinline__ void update_E_comp(const Grid<T> &g, const Fields<T> 
     } else {
       F.E[A][q] = fma(gkb, Db, fma(-gkc, Dc, fma(-g.dt, j, F.E[A][q])));
     }
+  }
+  if (DIM == 3 && g.cmask && ((gptr(g.cmask)[q] >> A) & 1)) {   // inside a conductor
+    F.E[A][q] = T(0);
+    F.Ea[A][q] = T(0);
   }
 }
 

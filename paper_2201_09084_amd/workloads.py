@@ -41,6 +41,8 @@ class SimConfig:
     solver: int = 0                     # 0 Yee; 1 Cole-Karkkainen in Faraday's law (3D, cubic cells)
     filter_passes: int = 0              # binomial passes over the deposited current (3D)
     alpha_face: tuple = ((0, 0), (0, 0), (0, 0))   # per face (low, high): 0 = alpha_mode, else 1 + mode
+    conductor: int = 0                  # 1: the run has conductor cells (3D)
+    max_source: int = 0                 # capacity of the beam source
 
     def total_cells(self) -> int:
         t = 1
@@ -122,6 +124,71 @@ def single_particle_3d_config(precision: int = 64, n: int = 128, pml: int = 8) -
                      alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
                      sigma_coef=paper_conductivity_profile(pml), push=1, precision=precision,
                      solver=1, filter_passes=1)
+
+
+# ---------------------------------------------------------------- cavity (Sec. IV.A)
+# Charge unit of the normalised equations for a cell of 1 mm: eps0 m_e c^2 dx / e, so that
+# a macroparticle of weight w and species charge q (in units of e) carries q w of it.
+CHARGE_UNIT_1MM = 8.8541878128e-12 * 8.1871057769e-14 * 1e-3 / 1.602176634e-19   # C
+PROTON_MASS = 1836.15267343       # in electron masses
+
+
+def cavity_config(precision: int = 32, n=(64, 64, 108), pml: int = 10, max_source: int = 1 << 20,
+                  alpha_face=((0, 0), (0, 0), (2, 3))) -> SimConfig:
+    """The cavity run of App. A.2: 64 x 64 x 108 cubic cells of 1 mm, 10-cell PMLs on
+    both z faces only (the x and y faces are the PEC walls) with sigma = (4/dz)(z/10dz)^2,
+    Yee at the CFL limit c dt = dz/sqrt(3), linear shape with one binomial pass over the
+    current, protons (q = e, m = 1836 m_e).  Default damping per face: undamped
+    deposition in the entry (low z) PML and Eq. (alpha) in the exit one, the
+    combination suggested at the end of Sec. IV.A."""
+    return SimConfig(dim=3, n=tuple(n), pml=((0, 0), (0, 0), (pml, pml)), dt=1.0 / math.sqrt(3.0),
+                     shape_order=1, alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
+                     sigma_coef=paper_conductivity_profile(pml, scale_cells=10.0), push=1,
+                     charge=1.0, mass=PROTON_MASS, precision=precision, filter_passes=1,
+                     alpha_face=alpha_face, conductor=1, max_source=max_source,
+                     max_particles=max_source)
+
+
+def cavity_conductor(cfg: SimConfig, pipe_half: float = 12.0, cavity=(34.0, 74.0)) -> np.ndarray:
+    """Conductor cells (M_z, M_y, M_x) of a square beam pipe of half-width `pipe_half`
+    around the transverse centre, opening into a rectangular cavity that fills the whole
+    cross-section for `cavity[0] <= z <= cavity[1]` (physical mm); the pipe continues
+    through both PMLs.  The paper gives no dimensions: these are a reading."""
+    M = [cfg.n[d] + cfg.pml[d][0] + cfg.pml[d][1] for d in range(3)]
+    xc = (np.arange(M[0]) + 0.5 - cfg.pml[0][0]) * cfg.dx[0]
+    yc = (np.arange(M[1]) + 0.5 - cfg.pml[1][0]) * cfg.dx[1]
+    zc = (np.arange(M[2]) + 0.5 - cfg.pml[2][0]) * cfg.dx[2]
+    cx, cy = cfg.n[0] * cfg.dx[0] / 2.0, cfg.n[1] * cfg.dx[1] / 2.0
+    out_pipe = (np.abs(xc[None, None, :] - cx) > pipe_half) | (np.abs(yc[None, :, None] - cy) > pipe_half)
+    out_cav = (zc[:, None, None] < cavity[0]) | (zc[:, None, None] > cavity[1])
+    return (out_pipe & out_cav).astype(np.uint8)
+
+
+def cavity_beam(cfg: SimConfig, n_macro: int = 1 << 20, seed: int = 1006, charge_nC: float = 40.0,
+                gamma: float = 479.0, sigma_z: float = 18.8, sigma_r: float = 0.2,
+                x_offset: float = 5.0) -> Particles:
+    """The proton beam of App. A.2 as a source: 40 nC, gamma = 479, Gaussian with 18.8 mm
+    rms length and 0.2 mm rms transverse size, +5 mm offset in x; its centre starts three
+    rms lengths before the entry wall (positions truncated to lie upstream of it), moving
+    along +z."""
+    rng = np.random.default_rng(seed)
+    wall = -cfg.pml[2][0] * cfg.dx[2]
+    zc = wall - 3.0 * sigma_z
+    z = rng.normal(zc, sigma_z, n_macro)
+    z = np.minimum(z, wall - 1e-3)
+    x = np.stack([rng.normal(cfg.n[0] * cfg.dx[0] / 2.0 + x_offset, sigma_r, n_macro),
+                  rng.normal(cfg.n[1] * cfg.dx[1] / 2.0, sigma_r, n_macro), z], axis=1)
+    u = np.zeros((n_macro, 3))
+    u[:, 2] = math.sqrt(gamma * gamma - 1.0)
+    w = np.full(n_macro, charge_nC * 1e-9 / CHARGE_UNIT_1MM / n_macro)
+    return Particles(x=x, u=u, w=w)
+
+
+def deflection_planes(cfg: SimConfig):
+    """The planes of the deflection diagnostic of Sec. IV.A (z = -54, -35, +35, +54 mm
+    about the box centre), in the box's physical coordinates."""
+    c = cfg.n[2] * cfg.dx[2] / 2.0
+    return [c - 54.0, c - 35.0, c + 35.0, c + 54.0]
 
 
 # ---------------------------------------------------------------- workload 2

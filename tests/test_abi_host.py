@@ -100,6 +100,33 @@ def test_ck_solver_and_filter_validation(lib):
     assert rc0 == 0 and rc1 == 0 and n1 > n0              # the filter's scratch copy of J
 
 
+def test_beam_transport_validation(lib):
+    """Per-face alpha entries 0..3 and not with weight damping; conductors 3D; the cavity
+    run's Yee time step at the CFL limit itself is accepted."""
+    cav = W.cavity_config(precision=32, max_source=1000)
+    assert _size(cav, max_particles=1000)[0] == 0                     # c dt = dz / sqrt(3)
+    rc0, n0 = _size(cav.replace(conductor=0, max_source=0), max_particles=1000)
+    rc1, n1 = _size(cav, max_particles=1000)
+    assert rc0 == 0 and n1 > n0                            # mask and source storage
+    p = B.make_params(cav, max_particles=1000)
+    p.dt = 1.0001 / 3 ** 0.5
+    n = C.c_size_t()
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -2
+    cfg2 = W.single_particle_config()
+    assert _size(cfg2, conductor=1)[0] == -1               # conductors are 3D
+    p = B.make_params(cfg2)
+    p.alpha_face[0][1] = 4
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
+    p = B.make_params(cfg2.replace(alpha_mode=W.ALPHA_WEIGHT))
+    p.alpha_face[0][1] = 2
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
+    assert b"WEIGHT" in lib.pml_pic_last_error(None)
+    p = B.make_params(cfg2)
+    p.alpha_face[1][0] = 3
+    assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == 0
+    assert _size(cfg2, max_source=-1)[0] == -1
+
+
 def test_create_rejects_small_or_missing_workspace(lib):
     p = B.make_params(W.single_particle_config(), max_particles=4)
     h = C.c_void_p()
