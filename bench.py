@@ -69,7 +69,7 @@ def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
     return None
 
 
-def run_gpu(args, cfg, parts):
+def run_gpu(args, cfg, parts, setup=None):
     """Timed region: args.steps plain steps between two synchronisations.  Then a
     shorter pass of the same steps with HIP events around every kernel phase on the
     library's stream gives the per-kernel durations (the events add a little idle
@@ -77,8 +77,11 @@ def run_gpu(args, cfg, parts):
     import torch
     from paper_2201_09084_amd import binding as B
 
-    sim = B.PmlPic(cfg, max_particles=len(parts))
-    sim.add_particles(parts.x, parts.u, parts.w)
+    sim = B.PmlPic(cfg, max_particles=max(len(parts), int(cfg.max_particles)))
+    if setup is not None:
+        setup(sim)
+    else:
+        sim.add_particles(parts.x, parts.u, parts.w)
     torch.cuda.synchronize()
     if args.warmup:
         sim.step(args.warmup)
@@ -155,10 +158,12 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(cfg, parts, n_steps):
+def cpu_baseline(cfg, parts, n_steps, cells=None):
     import oracle
     oracle.build_library(force=False)
     o = oracle.OracleSim(cfg.replace(precision=64))
+    if cells is not None:
+        o.set_conductor(cells)
     o.add_particles(parts.x, parts.u, parts.w)
     t0 = time.perf_counter()
     o.step(n_steps)
@@ -166,13 +171,27 @@ def cpu_baseline(cfg, parts, n_steps):
     return len(parts) * n_steps / (t1 - t0), t1 - t0
 
 
+def cavity_sample(cfg, parts, steps):
+    """The source particles that have crossed the entry wall after `steps` steps, at their
+    ballistic positions (a sample of the cavity workload for the CPU baseline)."""
+    import numpy as np
+    gam = np.sqrt(1.0 + np.sum(parts.u ** 2, axis=1))
+    x = parts.x + steps * cfg.dt * parts.u / gam[:, None]
+    lo = -cfg.pml[2][0] * cfg.dx[2]
+    hi = (cfg.n[2] + cfg.pml[2][1]) * cfg.dx[2]
+    keep = (x[:, 2] >= lo + 1.0) & (x[:, 2] < hi - 1.0)
+    from paper_2201_09084_amd import workloads as W
+    return W.Particles(x=x[keep], u=parts.u[keep], w=parts.w[keep])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 2000 beam2d, 100 beam3d, 600 batch, 300 sp3d)")
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch", "sp3d"], default="beam2d")
+                    help="timed steps (default: 2000 beam2d, 100 beam3d, 600 batch, 300 sp3d, 200 cavity)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 10; cavity: 150, so that the beam fills the box)")
+    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch", "sp3d", "cavity"], default="beam2d")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -200,7 +219,9 @@ def main():
 
     torch.cuda.set_device(0)
     if args.steps is None:
-        args.steps = {"beam2d": 2000, "beam3d": 100, "batch": 600, "sp3d": 300}[args.workload]
+        args.steps = {"beam2d": 2000, "beam3d": 100, "batch": 600, "sp3d": 300, "cavity": 200}[args.workload]
+    if args.warmup is None:
+        args.warmup = 150 if args.workload == "cavity" else 10
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "beam2d":
@@ -213,6 +234,17 @@ def main():
         parts = W.beam3d_particles(cfg)
         wl = {"workload": "beam3d", "grid": "256^3+12pml", "particles": len(parts),
               "shape_order": 1, "steps_total": args.warmup + args.steps}
+    elif args.workload == "cavity":   # the beam through the cavity of Sec. IV.A / App. A.2
+        cfg = W.cavity_config(precision=args.precision)
+        parts = W.cavity_beam(cfg)
+        cond_cells = W.cavity_conductor(cfg)
+        wl = {"workload": "cavity", "grid": "64x64x108+10pml(z)", "source_particles": len(parts),
+              "shape_order": 1, "filter_passes": 1, "alpha_faces": "z: undamped entry, Eq. alpha exit",
+              "steps_total": args.warmup + args.steps}
+
+        def setup(sim, cells=cond_cells, parts=parts):
+            sim.set_conductor(cells)
+            sim.set_source(parts.x, parts.u, parts.w, axis=2)
     else:   # the 3D single-particle numerics of App. A: CK at c dt = dx, cubic shape, filter
         cfg = W.single_particle_3d_config(precision=args.precision)
         parts = W.single_particle(cfg, beta=0.9)
@@ -222,7 +254,8 @@ def main():
           (args.workload, len(parts), cfg.total_cells(), args.precision, args.warmup, args.steps),
           file=sys.stderr, flush=True)
 
-    sim, elapsed, pushes, phases, d0, d1, n_prof, prof_pushes = run_gpu(args, cfg, parts)
+    sim, elapsed, pushes, phases, d0, d1, n_prof, prof_pushes = run_gpu(
+        args, cfg, parts, setup if args.workload == "cavity" else None)
     esz = 4 if args.precision == 32 else 8
     cells = cfg.total_cells()
     ms_per_step = 1e3 * elapsed / args.steps
@@ -249,13 +282,20 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         n_cpu = 2 if per_cell else args.cpu_steps
-        v, secs = cpu_baseline(cfg, parts, n_cpu)
+        sample_parts = parts
+        if args.workload == "cavity":
+            n_cpu = 1
+            sample_parts = cavity_sample(cfg, parts, args.warmup)
+        v, secs = cpu_baseline(cfg, sample_parts, n_cpu, cond_cells if args.workload == "cavity" else None)
         if per_cell:
             v = v / len(parts) * cells
         cpu = {"value": v, "unit": "cell-updates/s" if per_cell else "particle-pushes/s", "cores": 1,
                "kind": "oracle",
-               "sample": "%d steps of the same workload from its initial state (%d particles), "
-                         "FP64 single-threaded C oracle, %.1f s" % (n_cpu, len(parts), secs)}
+               "sample": ("%d steps of the same workload from its initial state (%d particles), "
+                          "FP64 single-threaded C oracle, %.1f s" % (n_cpu, len(sample_parts), secs))
+               if args.workload != "cavity" else
+               ("%d oracle steps (FP64, single-threaded C) of the cavity with the %d beam particles that "
+                "have entered after the warm-up, placed on their ballistic paths, with the conductor, %.1f s" % (n_cpu, len(sample_parts), secs))}
 
     out = {
         "metric": "PIC particle-pushes/s & Yee+PML cell-updates/s; FP32 vs FP64 at stated err",

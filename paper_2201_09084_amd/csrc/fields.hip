@@ -143,19 +143,18 @@ void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int 
 // Binomial filter of the deposited current (App. A), 3D, one pass: dst_A(i,j,k) = sum
 // over the 27 neighbours o of w(o_x) w(o_y) w(o_z) src_A(i+o), w = (1/4, 1/2, 1/4), with
 // neighbours outside J_A's extent (M_A samples along A, M + 1 across) counting as 0.  The
-// weights factor per axis, so each thread owns one (i, j) column of a chunk of FILT_KZ
-// planes and keeps the x-y filtered value of three consecutive planes in registers: a
-// plane is read once per chunk (with one halo plane on each side), and only samples of
-// the extent are written.
-constexpr int FILT_KZ = 16;
-
+// weights factor per axis, so each thread owns one (i, j) column of a chunk of kz planes
+// and keeps the x-y filtered value of three consecutive planes in registers: a plane is
+// read once per chunk (with one halo plane on each side), and only samples of the extent
+// are written.  kz is 16 on large grids and shrinks on small ones so that the launch
+// still has a few thousand workgroups.
 template <typename T>
-__global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, const T *src, T *dst, int nchunk) {
+__global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, const T *src, T *dst, int nchunk, int kz) {
   const int A = (int)blockIdx.z / nchunk, chunk = (int)blockIdx.z % nchunk;
   const int ext0 = g.M[0] + (A != 0), ext1 = g.M[1] + (A != 1), ext2 = g.M[2] + (A != 2);
   const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
   const int j = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int k0 = chunk * FILT_KZ, k1 = min(k0 + FILT_KZ, ext2);
+  const int k0 = chunk * kz, k1 = min(k0 + kz, ext2);
   if (i >= ext0 || j >= ext1 || k0 >= k1) return;
   const T *J = src + (size_t)A * g.nelem;
   T *out = dst + (size_t)A * g.nelem;
@@ -189,11 +188,14 @@ __global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, const T *src, T *ds
 template <typename T>
 T *launch_filter_current(const Grid<T> &g, T *J, T *tmp, int passes, hipStream_t s) {
   if (g.dim != 3 || passes <= 0) return J;
-  const int nchunk = (g.M[2] + 1 + FILT_KZ - 1) / FILT_KZ;
-  dim3 blk(256), grd((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, 3 * nchunk);
+  const int gx = (g.M[0] + 1 + 63) / 64, gy = (g.M[1] + 1 + 3) / 4;
+  const int want = (4096 + 3 * gx * gy - 1) / (3 * gx * gy);   // chunks for ~4096 workgroups
+  const int kz = std::max(2, std::min(16, (g.M[2] + 1 + want - 1) / want));
+  const int nchunk = (g.M[2] + 1 + kz - 1) / kz;
+  dim3 blk(256), grd(gx, gy, 3 * nchunk);
   T *a = J, *b = tmp;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_filter_J<T>), grd, blk, 0, s, g, a, b, nchunk);
+    hipLaunchKernelGGL((k_filter_J<T>), grd, blk, 0, s, g, a, b, nchunk, kz);
     std::swap(a, b);
   }
   return a;
