@@ -988,6 +988,8 @@ int batch_layout(const pml_pic_params *runs, int32_t n, std::vector<Layout> &Ls,
     }
     if (runs[r].conductor || runs[r].max_source > 0)
       return fail(err, PML_PIC_E_INVALID_ARG, "batched runs have neither conductors nor sources");
+    if (runs[r].solver != PML_PIC_SOLVER_YEE || runs[r].filter_passes > 0)
+      return fail(err, PML_PIC_E_INVALID_ARG, "batched runs use the Yee solver without current filter");
     if (runs[r].dim != runs[0].dim || runs[r].shape_order != runs[0].shape_order ||
         runs[r].precision != runs[0].precision)
       return fail(err, PML_PIC_E_INVALID_ARG, "all runs of a batch need the same dim, shape_order and precision");

@@ -18,39 +18,18 @@ __device__ __forceinline__ long stride_of(const Grid<T> &g, int axis) {
   return axis == 0 ? 1L : (axis == 1 ? g.sy : g.sz);
 }
 
-// Cole-Karkkainen difference (the paper's solver, App. A; 3D, cubic cells) of e along
-// axis AX at sample q: the Yee difference e(q + e_AX) - e(q) at q and at its transverse
-// neighbours, weighted 7/12 (q), 1/12 (each side neighbour), 1/48 (each diagonal one).
-template <typename T, int AX>
-__device__ __forceinline__ T ck_diff(const Grid<T> &g, const T *e, long q) {
-  constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
-  const long sa = stride_of<T, 3>(g, AX), s1 = stride_of<T, 3>(g, T1), s2 = stride_of<T, 3>(g, T2);
-  auto d = [&](long o) { return e[q + o + sa] - e[q + o]; };
-  const T side = (d(s1) + d(-s1)) + (d(s2) + d(-s2));
-  const T diag = (d(s1 + s2) + d(s1 - s2)) + (d(-s1 + s2) + d(-s1 - s2));
-  return T(7.0 / 12.0) * d(0) + T(1.0 / 12.0) * side + T(1.0 / 48.0) * diag;
-}
-
-// B_A half step at node (i,j,k) -> sample B_A(i,j,k).  Written as FMA chains on the
-// raw neighbour differences so that each part takes three roundings per update.
-// CK: Cole-Karkkainen differences instead of the Yee ones (3D only).
-template <typename T, int DIM, int A, bool CK = false>
-__device__ __forceinline__ void update_B_comp(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
-                                              long q) {
+// The rest of the B_A half step at sample B_A(i,j,k) once its two differences are known
+// (part b: -Db, the difference along b = A+1 of E_c; part c: +Dc, along c = A+2 of E_b);
+// returns at samples outside B_A's extent.  FMA chains on the raw differences so that each
+// part takes three roundings per update.
+template <typename T, int DIM, int A>
+__device__ __forceinline__ void update_B_apply(const Grid<T> &g, const Fields<T> &F, const int (&id)[3], long q,
+                                               T Db, T Dc) {
   constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
   // extent: along A up to M_A (node), across up to M-1 (centre)
   if (A < DIM && id[A] > g.M[A]) return;
   if (Bx < DIM && id[Bx] > g.M[Bx] - 1) return;
   if (Cx < DIM && id[Cx] > g.M[Cx] - 1) return;
-  // part b: -d_b E_c ; part c: +d_c E_b
-  T Db = T(0), Dc = T(0);
-  if constexpr (CK && DIM == 3) {
-    Db = ck_diff<T, Bx>(g, F.E[Cx], q);
-    Dc = ck_diff<T, Cx>(g, F.E[Bx], q);
-  } else {
-    if (Bx < DIM) Db = F.E[Cx][q + stride_of<T, DIM>(g, Bx)] - F.E[Cx][q];
-    if (Cx < DIM) Dc = F.E[Bx][q + stride_of<T, DIM>(g, Cx)] - F.E[Bx][q];
-  }
   if constexpr (DIM == 2 && (Bx == 2 || Cx == 2)) {
     constexpr int P = (Bx == 2) ? Cx : Bx;   // the in-plane derivative (and damping) axis
     const T e = g.tb(P, T_EH_C, id[P]), gk = g.tb(P, T_GHK_C, id[P]);
@@ -76,6 +55,21 @@ __device__ __forceinline__ void update_B_comp(const Grid<T> &g, const Fields<T> 
   }
 }
 
+// B_A half step at node (i,j,k) -> sample B_A(i,j,k) with the Yee differences (the
+// Cole-Karkkainen form is k_update_B_ck in fields.hip).
+template <typename T, int DIM, int A>
+__device__ __forceinline__ void update_B_comp(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
+                                              long q) {
+  constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
+  if (A < DIM && id[A] > g.M[A]) return;
+  if (Bx < DIM && id[Bx] > g.M[Bx] - 1) return;
+  if (Cx < DIM && id[Cx] > g.M[Cx] - 1) return;
+  T Db = T(0), Dc = T(0);
+  if (Bx < DIM) Db = F.E[Cx][q + stride_of<T, DIM>(g, Bx)] - F.E[Cx][q];
+  if (Cx < DIM) Dc = F.E[Bx][q + stride_of<T, DIM>(g, Cx)] - F.E[Bx][q];
+  update_B_apply<T, DIM, A>(g, F, id, q, Db, Dc);
+}
+
 // alpha at J_A's sample (i,j,k): product of per-axis factors (centre along A)
 template <typename T, int DIM, int A>
 __device__ __forceinline__ T alpha_at(const Grid<T> &g, const int (&id)[3]) {
@@ -85,17 +79,17 @@ __device__ __forceinline__ T alpha_at(const Grid<T> &g, const int (&id)[3]) {
   return a;
 }
 
+// The rest of the E_A step at sample E_A(i,j,k) once its two differences are known (part
+// b: +Db, the difference along b = A+1 of B_c; part c: -Dc, along c = A+2 of B_b), with the
+// source -alpha J; returns at samples outside E_A's extent and on the PEC walls.
 template <typename T, int DIM, int A>
-__device__ __forceinline__ void update_E_comp(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
-                                              long q, bool fuse_alpha, bool consume) {
+__device__ __forceinline__ void update_E_apply(const Grid<T> &g, const Fields<T> &F, const int (&id)[3], long q,
+                                               T Db, T Dc, bool fuse_alpha, bool consume) {
   constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
   if (A < DIM && id[A] > g.M[A] - 1) return;
   if (Bx < DIM && (id[Bx] < 1 || id[Bx] > g.M[Bx] - 1)) return;   // PEC: tangential E = 0
   if (Cx < DIM && (id[Cx] < 1 || id[Cx] > g.M[Cx] - 1)) return;
-  // part b: +d_b B_c ; part c: -d_c B_b ; source -alpha J split by the damping rates
-  T Db = T(0), Dc = T(0);
-  if (Bx < DIM) Db = F.B[Cx][q] - F.B[Cx][q - stride_of<T, DIM>(g, Bx)];
-  if (Cx < DIM) Dc = F.B[Bx][q] - F.B[Bx][q - stride_of<T, DIM>(g, Cx)];
+  // source -alpha J split by the damping rates
   T j = F.J[A][q];
   if (consume && j != T(0)) F.J[A][q] = T(0);   // leaves J zero for the next deposit
   if (fuse_alpha) j *= alpha_at<T, DIM, A>(g, id);
@@ -124,6 +118,19 @@ __device__ __forceinline__ void update_E_comp(const Grid<T> &g, const Fields<T> 
     F.E[A][q] = T(0);
     F.Ea[A][q] = T(0);
   }
+}
+
+template <typename T, int DIM, int A>
+__device__ __forceinline__ void update_E_comp(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
+                                              long q, bool fuse_alpha, bool consume) {
+  constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
+  if (A < DIM && id[A] > g.M[A] - 1) return;
+  if (Bx < DIM && (id[Bx] < 1 || id[Bx] > g.M[Bx] - 1)) return;
+  if (Cx < DIM && (id[Cx] < 1 || id[Cx] > g.M[Cx] - 1)) return;
+  T Db = T(0), Dc = T(0);
+  if (Bx < DIM) Db = F.B[Cx][q] - F.B[Cx][q - stride_of<T, DIM>(g, Bx)];
+  if (Cx < DIM) Dc = F.B[Bx][q] - F.B[Bx][q - stride_of<T, DIM>(g, Cx)];
+  update_E_apply<T, DIM, A>(g, F, id, q, Db, Dc, fuse_alpha, consume);
 }
 
 }  // namespace pmlpic

@@ -50,7 +50,7 @@ void launch_jbox_clear(const Grid<T> &g, const JClear<T> &jc, hipStream_t s) {
 template void launch_jbox_clear<float>(const Grid<float> &, const JClear<float> &, hipStream_t);
 template void launch_jbox_clear<double>(const Grid<double> &, const JClear<double> &, hipStream_t);
 
-template <typename T, int DIM, bool CK = false>
+template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -58,9 +58,94 @@ __global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
   if (i > g.M[0] || j > g.M[1]) return;
   const int id[3] = {i, j, k};
   const long q = g.at(i, j, k);
-  update_B_comp<T, DIM, 0, CK>(g, F, id, q);
-  update_B_comp<T, DIM, 1, CK>(g, F, id, q);
-  update_B_comp<T, DIM, 2, CK>(g, F, id, q);
+  update_B_comp<T, DIM, 0>(g, F, id, q);
+  update_B_comp<T, DIM, 1>(g, F, id, q);
+  update_B_comp<T, DIM, 2>(g, F, id, q);
+}
+
+// Cole-Karkkainen B half step (3D), marching along z.  Each CK difference is a weighted
+// sum over the plane normal to its axis: along z, the difference of the 9-point in-plane
+// averages P(k) of two consecutive planes; along x or y, a 3-point row average of the Yee
+// differences in plane k plus a lighter one in planes k - 1 and k + 1.  A thread owns one
+// (i, j) column of a chunk of planes and keeps these per-plane sums for planes k - 1, k,
+// k + 1 in registers, so each E plane is read once per chunk (27 loads per node and plane,
+// neighbours from the same cache lines) instead of 108 scattered ones per node.
+template <typename T>
+struct CkPlane {
+  T S0, S1;   // x-rows of d_y E_z (weights 1/12 7/12 1/12 in the plane, 1/48 1/12 1/48 beside it)
+  T W0, W1;   // the same of d_y E_x
+  T U0, U1;   // y-rows of d_x E_z
+  T V0, V1;   // the same of d_x E_y
+  T P, Q;     // 9-point averages of E_y and E_x (7/12 centre, 1/12 sides, 1/48 corners)
+};
+
+template <typename T>
+__device__ __forceinline__ CkPlane<T> ck_plane(const Grid<T> &g, const Fields<T> &F, int i, int j, int k) {
+  const T a0 = T(7.0 / 12.0), a1 = T(1.0 / 12.0), a2 = T(1.0 / 48.0);
+  const long q = g.at(i, j, k);
+  T ex[3][3], ey[3][3], ez[3][3];   // [y - j + 1][x - i + 1]
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const long o = q + (dy - 1) * g.sy + (dx - 1);
+      ex[dy][dx] = F.E[0][o];
+      ey[dy][dx] = F.E[1][o];
+      ez[dy][dx] = F.E[2][o];
+    }
+  CkPlane<T> r;
+  auto xrows = [&](T (&e)[3][3], T &w0, T &w1) {   // d_y along the x-row of row j
+    const T m = e[2][0] - e[1][0], c = e[2][1] - e[1][1], p = e[2][2] - e[1][2];
+    w0 = a0 * c + a1 * (m + p);
+    w1 = a1 * c + a2 * (m + p);
+  };
+  auto yrows = [&](T (&e)[3][3], T &w0, T &w1) {   // d_x along the y-column of column i
+    const T m = e[0][2] - e[0][1], c = e[1][2] - e[1][1], p = e[2][2] - e[2][1];
+    w0 = a0 * c + a1 * (m + p);
+    w1 = a1 * c + a2 * (m + p);
+  };
+  auto nine = [&](T (&e)[3][3]) {
+    return a0 * e[1][1] + a1 * ((e[0][1] + e[2][1]) + (e[1][0] + e[1][2])) +
+           a2 * ((e[0][0] + e[0][2]) + (e[2][0] + e[2][2]));
+  };
+  xrows(ez, r.S0, r.S1);
+  xrows(ex, r.W0, r.W1);
+  yrows(ez, r.U0, r.U1);
+  yrows(ey, r.V0, r.V1);
+  r.P = nine(ey);
+  r.Q = nine(ex);
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_update_B_ck(Grid<T> g, Fields<T> F, int kz) {
+  const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
+  const int j = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int k0 = (int)blockIdx.z * kz, k1 = min(k0 + kz, g.M[2] + 1);
+  if (i > g.M[0] || j > g.M[1] || k0 >= k1) return;
+  CkPlane<T> pm = ck_plane(g, F, i, j, k0 - 1), p0 = ck_plane(g, F, i, j, k0);
+  for (int k = k0; k < k1; ++k) {
+    const CkPlane<T> pp = ck_plane(g, F, i, j, k + 1);
+    const int id[3] = {i, j, k};
+    const long q = g.at(i, j, k);
+    // B_x: b = y (E_z), c = z (E_y); B_y: b = z (E_x), c = x (E_z); B_z: b = x (E_y), c = y (E_x)
+    update_B_apply<T, 3, 0>(g, F, id, q, p0.S0 + (pm.S1 + pp.S1), pp.P - p0.P);
+    update_B_apply<T, 3, 1>(g, F, id, q, pp.Q - p0.Q, p0.U0 + (pm.U1 + pp.U1));
+    update_B_apply<T, 3, 2>(g, F, id, q, p0.V0 + (pm.V1 + pp.V1), p0.W0 + (pm.W1 + pp.W1));
+    pm = p0;
+    p0 = pp;
+  }
+}
+
+// planes per chunk: 16 on large grids, fewer on small ones so that a launch keeps a few
+// thousand workgroups
+static int zchunk(const int M[3], int per_plane_groups_mult, int &nchunk) {
+  const int gx = (M[0] + 1 + 63) / 64, gy = (M[1] + 1 + 3) / 4;
+  const int mult = per_plane_groups_mult * gx * gy;
+  const int want = (4096 + mult - 1) / mult;
+  const int kz = std::max(2, std::min(16, (M[2] + 1 + want - 1) / want));
+  nchunk = (M[2] + 1 + kz - 1) / kz;
+  return kz;
 }
 
 template <typename T, int DIM>
@@ -127,7 +212,11 @@ template <typename T>
 void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool /*half*/, hipStream_t s) {
   dim3 blk, grd = node_grid(g, blk);
   if (g.dim == 2) hipLaunchKernelGGL((k_update_B<T, 2>), grd, blk, 0, s, g, F);
-  else if (g.solver == PML_PIC_SOLVER_CK) hipLaunchKernelGGL((k_update_B<T, 3, true>), grd, blk, 0, s, g, F);
+  else if (g.solver == PML_PIC_SOLVER_CK) {
+    int nchunk;
+    const int kz = zchunk(g.M, 1, nchunk);
+    hipLaunchKernelGGL((k_update_B_ck<T>), dim3(grd.x, grd.y, nchunk), dim3(256), 0, s, g, F, kz);
+  }
   else hipLaunchKernelGGL((k_update_B<T, 3>), grd, blk, 0, s, g, F);
 }
 
@@ -188,11 +277,9 @@ __global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, const T *src, T *ds
 template <typename T>
 T *launch_filter_current(const Grid<T> &g, T *J, T *tmp, int passes, hipStream_t s) {
   if (g.dim != 3 || passes <= 0) return J;
-  const int gx = (g.M[0] + 1 + 63) / 64, gy = (g.M[1] + 1 + 3) / 4;
-  const int want = (4096 + 3 * gx * gy - 1) / (3 * gx * gy);   // chunks for ~4096 workgroups
-  const int kz = std::max(2, std::min(16, (g.M[2] + 1 + want - 1) / want));
-  const int nchunk = (g.M[2] + 1 + kz - 1) / kz;
-  dim3 blk(256), grd(gx, gy, 3 * nchunk);
+  int nchunk;
+  const int kz = zchunk(g.M, 3, nchunk);
+  dim3 blk(256), grd((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, 3 * nchunk);
   T *a = J, *b = tmp;
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL((k_filter_J<T>), grd, blk, 0, s, g, a, b, nchunk, kz);
