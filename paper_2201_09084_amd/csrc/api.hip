@@ -296,6 +296,7 @@ struct pml_pic_handle {
   bool has_cond = false;                 // conductor mask set
   std::vector<int64_t> src_steps;        // injection step of each source entry (sorted)
   int64_t src_next = 0;                  // first entry not injected yet
+  int64_t tail_n = 0;                    // particles injected since the last sort (unsorted tail)
 
   template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
   double tab(int axis, int kind, int i) const { return tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G]; }
@@ -722,10 +723,13 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     if (due > 0) {
       if (h->n_slots + due > h->L.cap)
         return fail(&h->err, PML_PIC_E_CAPACITY, "max_particles exceeded by the beam source");
-      launch_inject<T>(h->p.dim, h->parts<T>(h->cur), h->src_parts<T>(), ctl.count, h->src_next, (int)due, s);
+      // appended after the live particles; until the next sort they form an unsorted tail
+      // that the tiled push leaves to the per-particle kernel
+      launch_inject<T>(h->p.dim, h->parts<T>(h->cur), h->src_parts<T>(), ctl.count, h->src_next, (int)due,
+                       ctl.count + 1, h->tail_n == 0, s);
       h->src_next += due;
       h->n_slots += due;
-      h->sort_pending = true;
+      h->tail_n += due;
     }
     const int ns = (int)h->n_slots;
     const int ph = h->jphase % 3;
@@ -753,6 +757,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       h->cur = 1 - h->cur;
       h->since_sort = 0;
       h->sort_pending = false;
+      h->tail_n = 0;
     }
     const bool tiled = fused && use_sort && ns > 0;
     if (one_pass && !tiled) {   // the tiled deposit clears the other buffer itself
@@ -766,8 +771,12 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     const Parts<T> P = h->parts<T>(h->cur);
     pt.begin(s);
-    if (fused && use_sort) launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);
-    else launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
+    if (fused && use_sort) {
+      launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);
+      if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
+    } else {
+      launch_gather_push<T>(g, F, P, h->old_parts<T>(), ctl, ns, h->p.push, fused, s);
+    }
     pt.end(s, PML_PIC_PHASE_PUSH);
     if (!fused) {
       pt.begin(s);

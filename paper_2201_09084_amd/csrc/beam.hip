@@ -39,7 +39,8 @@ template void launch_apply_conductor<double>(const Grid<double> &, const Fields<
 // Appends entries [first, first + n) of the source (already in the particle format, at
 // their injection positions) after the live slots: slot count + t for entry first + t.
 // Every thread reads the count before any thread of the next launch changes it; the
-// count itself is raised by k_count_add afterwards.
+// count itself is raised by k_count_add afterwards, which on the first injection since
+// the last sort also records where the unsorted tail starts.
 template <typename T>
 __global__ void __launch_bounds__(256) k_inject(int dim, Parts<T> P, Parts<T> S, const int32_t *count, int64_t first,
                                                 int n) {
@@ -55,21 +56,25 @@ __global__ void __launch_bounds__(256) k_inject(int dim, Parts<T> P, Parts<T> S,
   if (P.lam) P.lam[dst] = T(0);
 }
 
-__global__ void k_count_add(int32_t *count, int n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *count += n;
+__global__ void k_count_add(int32_t *count, int n, int32_t *tail_start, int mark) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int32_t c = *count;
+    if (mark) *tail_start = c;
+    *count = c + n;
+  }
 }
 
 template <typename T>
 void launch_inject(int dim, const Parts<T> &P, const Parts<T> &S, int32_t *count, int64_t first, int n,
-                   hipStream_t s) {
+                   int32_t *tail_start, bool mark, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL((k_inject<T>), dim3((n + 255) / 256), dim3(256), 0, s, dim, P, S, count, first, n);
-  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, count, n);
+  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, count, n, tail_start, mark ? 1 : 0);
 }
 template void launch_inject<float>(int, const Parts<float> &, const Parts<float> &, int32_t *, int64_t, int,
-                                   hipStream_t);
+                                   int32_t *, bool, hipStream_t);
 template void launch_inject<double>(int, const Parts<double> &, const Parts<double> &, int32_t *, int64_t, int,
-                                    hipStream_t);
+                                    int32_t *, bool, hipStream_t);
 
 // ------------------------------------------------------------------ slab moments
 // Per slab [edges[k], edges[k+1]) of physical coordinate along `axis`: number of live

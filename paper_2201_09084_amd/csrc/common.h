@@ -236,13 +236,17 @@ template <typename T>
 void launch_apply_conductor(const Grid<T> &g, const Fields<T> &F, hipStream_t s);
 template <typename T>
 void launch_inject(int dim, const Parts<T> &P, const Parts<T> &S, int32_t *count, int64_t first, int n,
-                   hipStream_t s);
+                   int32_t *tail_start, bool mark, hipStream_t s);
 template <typename T>
 void launch_slab_moments(const Grid<T> &g, const Parts<T> &P, const int32_t *count, int n_slots, int axis, double dxa,
                          int nslab, const double *edges, double *out, hipStream_t s);
 template <typename T>
 void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                         StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s);
+// the same over slots [*start, count) (the unsorted tail of a tiled run), n_upper >= its length
+template <typename T>
+void launch_gather_push_tail(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+                             const int32_t *start, int n_upper, int n_slots, int push, hipStream_t s);
 // Work decomposition of the tiled particle step: after every sort, each tile's range
 // of cell-sorted particles is cut into chunks of at most `chunk` particles, listed as
 // work items (full chunks first, then each tile's partial chunk).

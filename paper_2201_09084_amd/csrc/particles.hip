@@ -22,8 +22,9 @@ namespace pmlpic {
 // per particle slot
 template <typename T, int DIM, int ORDER>
 __global__ void __launch_bounds__(256) k_gather_push(Grid<T> g, Fields<T> F, Parts<T> P, Parts<T> old,
-                                                      StepCtl ctl, int n_slots, int push, bool fused) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+                                                      StepCtl ctl, int n_slots, int push, bool fused,
+                                                      const int32_t *start) {
+  const int p = (start ? *start : 0) + (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int count = *ctl.count;
   bool active = false;
   int rng[4] = {0, -1, 0, -1};
@@ -435,9 +436,25 @@ void launch_gather_push(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P,
                         StepCtl ctl, int n_slots, int push, bool fused, hipStream_t s) {
   if (n_slots <= 0) return;
   dim3 blk(256), grd((n_slots + 255) / 256);
-  if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
-  else { PMLPIC_DISPATCH_ORDER(3, k_gather_push, g, F, P, old, ctl, n_slots, push, fused) }
+  const int32_t *start = nullptr;
+  if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_gather_push, g, F, P, old, ctl, n_slots, push, fused, start) }
+  else { PMLPIC_DISPATCH_ORDER(3, k_gather_push, g, F, P, old, ctl, n_slots, push, fused, start) }
 }
+
+template <typename T>
+void launch_gather_push_tail(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl,
+                             const int32_t *start, int n_upper, int n_slots, int push, hipStream_t s) {
+  if (n_upper <= 0 || n_slots <= 0) return;
+  dim3 blk(256), grd((n_upper + 255) / 256);
+  const Parts<T> old = P;   // not read by the fused form
+  const bool fused = true;
+  if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_gather_push, g, F, P, old, ctl, n_slots, push, fused, start) }
+  else { PMLPIC_DISPATCH_ORDER(3, k_gather_push, g, F, P, old, ctl, n_slots, push, fused, start) }
+}
+template void launch_gather_push_tail<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
+                                             StepCtl, const int32_t *, int, int, int, hipStream_t);
+template void launch_gather_push_tail<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
+                                              StepCtl, const int32_t *, int, int, int, hipStream_t);
 
 template <typename T>
 void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, JClear<T> jc,

@@ -128,6 +128,31 @@ def test_source_injection_matches_oracle(push, sort_interval):
     assert g.num_particles > 0
 
 
+@pytest.mark.parametrize("sort_interval", [0, 5])
+def test_source_injection_2d_one_pass(sort_interval):
+    """2D (one-pass field update, current boxes): a source entering through the low x PML;
+    between sorts the injected particles are an unsorted tail pushed on their own."""
+    ns = 300
+    cfg = W.SimConfig(dim=2, n=(40, 24, 1), pml=((7, 8), (0, 0), (0, 0)), dt=0.6, shape_order=2,
+                      alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.cubic_profile(3.0), push=1, charge=1.0,
+                      mass=2.0, precision=64, sort_interval=sort_interval, max_source=ns,
+                      alpha_face=((ONE, DAMPED), (0, 0), (0, 0)))
+    rng = np.random.default_rng(750 + sort_interval)
+    x = np.stack([rng.uniform(-30.0, -7.2, ns), rng.uniform(3.0, 21.0, ns)], axis=1)
+    u = np.stack([rng.uniform(1.0, 5.0, ns), rng.normal(0.0, 0.1, ns), rng.normal(0.0, 0.1, ns)], axis=1)
+    w = rng.uniform(0.5, 1.5, ns) * 0.05
+    g, o = both(cfg, max_particles=ns, flags=B.FLAG_KEEP_CURRENT)
+    g.set_source(x, u, w, axis=0)
+    o.set_source(x, u, w, axis=0)
+    for N in (2, 7, 16, 33, 60):
+        g.step(N - o.step_count)
+        o.step(N - o.step_count)
+        compare_particles(g, o, 1e-10, 1e-10, "step %d" % N)
+        compare_fields(g, o, cfg, 1e-10, "step %d" % N)
+        compare_current(g, o, 1e-10, "J step %d" % N)
+    assert g.num_particles > 50
+
+
 def test_source_rejected_and_replaced():
     cfg, (x, u, w) = _source_case(0, seed=731, ns=50)
     g, o = both(cfg, max_particles=60)
