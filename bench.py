@@ -25,8 +25,10 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
+    """Hash of the kernel and launcher sources (the host control in api.hip launches them but
+    does not change what one launch moves)."""
     h = hashlib.sha256()
-    for f in ("particles.hip", "fields.hip", "batch.hip", "api.hip", "beam.hip", "common.h", "field_core.h",
+    for f in ("particles.hip", "fields.hip", "batch.hip", "beam.hip", "common.h", "field_core.h",
               "fused2d.h", "particle_core.h"):
         with open(os.path.join(ROOT, "paper_2201_09084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())

@@ -730,6 +730,9 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       h->src_next += due;
       h->n_slots += due;
       h->tail_n += due;
+      // a beam's injected particles crowd few cells, where the per-particle kernel's global
+      // atomics collide: past a few thousand it is cheaper to sort them in right away
+      if (h->tail_n > 4096) h->sort_pending = true;
     }
     const int ns = (int)h->n_slots;
     const int ph = h->jphase % 3;
