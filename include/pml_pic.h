@@ -175,6 +175,13 @@ int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, 
  * *out filled) if a field value is not finite. */
 int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out);
 
+/* Eq. (error) of Sec. III against a reference run `ref` (same dim, precision, cell size and
+ * low-side PML, covering h's physical box; e.g. the box extended beyond the face the particle
+ * leaves through): *num = sum over the E and B samples inside h's physical box of
+ * (F - F_ref)^2, *den = sum of F_ref^2 (FP64 device reductions); the relative error is
+ * num / den.  Both handles must live on the current device.  Synchronises both streams. */
+int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den);
+
 /* Number of sample positions per field component: nn[d] = cells + 1 along each
  * in-plane axis, 1 along the invariant axis; n_samples = nn0 * nn1 * nn2. */
 int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples);

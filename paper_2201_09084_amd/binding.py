@@ -30,6 +30,7 @@ EXPORTED = [
     "pml_pic_batch_set_launch", "pml_pic_batch_step", "pml_pic_batch_last_error",
     "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
     "pml_pic_backward", "pml_pic_set_conductor", "pml_pic_set_source", "pml_pic_slab_moments",
+    "pml_pic_field_error",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
@@ -106,6 +107,7 @@ def load_library():
             "pml_pic_set_conductor": (C.c_int, [vp, P(C.c_uint8)]),
             "pml_pic_set_source": (C.c_int, [vp, i64, dp, dp, dp, i32]),
             "pml_pic_slab_moments": (C.c_int, [vp, i32, i32, dp, dp]),
+            "pml_pic_field_error": (C.c_int, [vp, vp, dp, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -247,6 +249,12 @@ class PmlPic:
         u = np.ascontiguousarray(u, dtype=np.float64)
         w = np.ascontiguousarray(w, dtype=np.float64)
         self._check(load_library().pml_pic_set_source(self._h, len(w), _dp(x), _dp(u), _dp(w), int(axis)))
+
+    def field_error(self, ref) -> float:
+        """Eq. (error) against the reference run `ref` over this run's physical box."""
+        num, den = C.c_double(), C.c_double()
+        self._check(load_library().pml_pic_field_error(self._h, ref._h, C.byref(num), C.byref(den)))
+        return num.value / den.value if den.value > 0 else num.value
 
     def slab_moments(self, axis, edges) -> np.ndarray:
         """(nslab, 5): count, sum w, sum w u_x, sum w u_y, sum w u_z per slab of `axis`."""

@@ -1543,6 +1543,32 @@ int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, 
   return rc;
 }
 
+int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
+  if (!h || !ref || !num || !den) return PML_PIC_E_INVALID_ARG;
+  const pml_pic_params &a = h->p, &b = ref->p;
+  if (a.dim != b.dim || a.precision != b.precision)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "the reference needs the same dim and precision");
+  for (int d = 0; d < a.dim; ++d)
+    if (a.dx[d] != b.dx[d] || a.pml[d][0] != b.pml[d][0] || b.n[d] + b.pml[d][1] < a.n[d])
+      return fail(&h->err, PML_PIC_E_INVALID_ARG,
+                  "the reference needs the same cells and low PML and must cover the physical box");
+  HIPCHK(h, hipStreamSynchronize(ref->stream));
+  const DiagWork dw = h->diagwork();
+  if (a.precision == 64)
+    launch_field_error<double>(h->grid<double>(), h->fields<double>(), ref->grid<double>(), ref->fields<double>(),
+                               dw.partial, dw.result, h->stream);
+  else
+    launch_field_error<float>(h->grid<float>(), h->fields<float>(), ref->grid<float>(), ref->fields<float>(),
+                              dw.partial, dw.result, h->stream);
+  HIPCHK(h, hipGetLastError());
+  double r[2];
+  HIPCHK(h, hipMemcpyAsync(r, dw.result, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *num = r[0];
+  *den = r[1];
+  return PML_PIC_OK;
+}
+
 int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out) {
   if (!h || !out) return PML_PIC_E_INVALID_ARG;
   return h->p.precision == 64 ? diagnose_t<double>(h, out) : diagnose_t<float>(h, out);

@@ -290,6 +290,11 @@ template <typename T>
 void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, SortWork sw,
                  StepCtl ctl, int n_slots, hipStream_t s);
 
+// Eq. (error) sums against a reference run (out[0] = sum (F - F_ref)^2, out[1] = sum F_ref^2
+// over g's physical box); partial holds two doubles per workgroup of g's node grid
+template <typename T>
+void launch_field_error(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr, const Fields<T> &R, double *partial,
+                        double *out, hipStream_t s);
 struct DiagWork {
   double *rho;           // nelem
   const double *rho_static;

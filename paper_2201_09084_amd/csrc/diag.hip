@@ -215,6 +215,65 @@ void launch_diag(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCt
   hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, s, dw.partial, nb, rmaxp, nrb, dw.result);
 }
 
+// Eq. (error) of Sec. III against a reference run: partial[2*b] = sum over the samples of
+// g's physical box of (F - F_ref)^2, partial[2*b + 1] = sum of F_ref^2 (E and B, the six
+// totals).  The reference grid has the same cell size and low PML and covers g's physical
+// box, so a sample has the same index in both.  Then one block sums the partials.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(RB) k_field_error(Grid<T> g, Fields<T> F, Grid<T> gr, Fields<T> R,
+                                                    double *partial) {
+  __shared__ double sh[RB];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  double num = 0.0, den = 0.0;
+  if (i <= g.M[0] && j <= g.M[1]) {
+    const long q = g.at(i, j, k), qr = gr.at(i, j, k);
+    const int id[3] = {i, j, k};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int a = c % 3;
+      bool phys = true;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const bool stag = (c < 3) ? (d == a) : (d != a);
+        phys = phys && in_box(g, id[d] + (stag ? 0.5 : 0.0), d);
+      }
+      if (!phys) continue;
+      const double v = (double)(c < 3 ? F.E[a] : F.B[a])[q];
+      const double r = (double)(c < 3 ? R.E[a] : R.B[a])[qr];
+      num += (v - r) * (v - r);
+      den += r * r;
+    }
+  }
+  const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const double sn = block_sum(num, sh);
+  const double sd = block_sum(den, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) { partial[2 * b] = sn; partial[2 * b + 1] = sd; }
+}
+
+__global__ void __launch_bounds__(RB) k_sum_pairs(const double *partial, int nb, double *out) {
+  __shared__ double sh[RB];
+  double a = 0.0, c = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RB) { a += partial[2 * b]; c += partial[2 * b + 1]; }
+  a = block_sum(a, sh);
+  c = block_sum(c, sh);
+  if (threadIdx.x == 0) { out[0] = a; out[1] = c; }
+}
+
+template <typename T>
+void launch_field_error(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr, const Fields<T> &R, double *partial,
+                        double *out, hipStream_t s) {
+  dim3 blk(64, 4, 1), grd((g.M[0] + 1 + 63) / 64, (g.M[1] + 1 + 3) / 4, g.dim == 3 ? g.M[2] + 1 : 1);
+  if (g.dim == 2) hipLaunchKernelGGL((k_field_error<T, 2>), grd, blk, 0, s, g, F, gr, R, partial);
+  else hipLaunchKernelGGL((k_field_error<T, 3>), grd, blk, 0, s, g, F, gr, R, partial);
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RB), 0, s, partial, (int)(grd.x * grd.y * grd.z), out);
+}
+template void launch_field_error<float>(const Grid<float> &, const Fields<float> &, const Grid<float> &,
+                                        const Fields<float> &, double *, double *, hipStream_t);
+template void launch_field_error<double>(const Grid<double> &, const Fields<double> &, const Grid<double> &,
+                                         const Fields<double> &, double *, double *, hipStream_t);
+
 template void launch_diag<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &, StepCtl, int,
                                  DiagWork, hipStream_t);
 template void launch_diag<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &, StepCtl,

@@ -11,9 +11,10 @@ progressively damped weight (Sec. II.C) lowers the error of slow particles.
 Measured (FP64): damped 7.7e-3 at 0 deg, 7.9e-2 at 45, 0.18 at 75 (undamped 0.76 / 0.54 /
 0.22, standard 1.04 / 0.87 / 0.56); at gamma beta = 0.1 damped 0.099 and weight damping 0.037,
 at 1 and 10 both below 0.014."""
+import numpy as np
 import pytest
 
-from gpu_helpers import say
+from gpu_helpers import both, say
 from paper_2201_09084_amd import exit_error as X
 from paper_2201_09084_amd import workloads as W
 
@@ -45,3 +46,42 @@ def test_velocity_sweep_fig3():
     assert errs[0.1][WGT] < 0.6 * errs[0.1][DAMP]           # the damped weight recovers part of it
     for gb in (1.0, 10.0):
         assert errs[gb][DAMP] < 0.02 and errs[gb][WGT] < 0.02
+
+
+def _oracle_error(o, oref, cfg):
+    """Eq. (error) over the physical box from the oracles' fields (plain numpy)."""
+    F, R = o.fields(), oref.fields()
+    nz, ny, nx = F.shape[1:]
+    R = R[:, :nz, :ny, :nx]
+    num = den = 0.0
+    for c in range(6):
+        a = c % 3
+        inside = np.ones(F.shape[1:], bool)
+        for d, m in zip(range(cfg.dim), (nx, ny, nz)):
+            half = (d == a) if c < 3 else (d != a)
+            X = np.arange(m) + (0.5 if half else 0.0)
+            ok = (X >= cfg.pml[d][0]) & (X <= cfg.pml[d][0] + cfg.n[d])
+            shape = [1, 1, 1]
+            shape[2 - d] = m
+            inside &= ok.reshape(shape)
+        num += float(np.sum((F[c] - R[c])[inside] ** 2))
+        den += float(np.sum(R[c][inside] ** 2))
+    return num / den
+
+
+@pytest.mark.parametrize("mode", [STD, DAMP])
+def test_field_error_matches_oracle(mode):
+    """pml_pic_field_error (FP64 device reduction) against Eq. (error) from the oracle's own
+    run and reference run, 2D, the particle leaving through the +x PML."""
+    cfg = W.single_particle_config(precision=64, alpha_mode=mode, n=40, pml=8, push=0)
+    ref_cfg = W.single_particle_config(precision=64, alpha_mode=mode, n=40, pml=8, push=0, extend_x=2)
+    p = W.single_particle(cfg)
+    g, o = both(cfg, p)
+    gr, orf = both(ref_cfg, p)
+    for s in (g, o, gr, orf):
+        s.step(40)
+    e_gpu = g.field_error(gr)
+    e_orc = _oracle_error(o, orf, cfg)
+    say("field error", mode, e_gpu, e_orc)
+    assert e_orc > 1e-6
+    assert abs(e_gpu - e_orc) <= 1e-9 * e_orc
