@@ -1506,6 +1506,7 @@ int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, cons
                                           : write_particles<float>(h, 0, n, ids, X, nullptr, u, w));
   if (rc) return rc;
   h->n_slots = n;
+  h->tail_n = 0;   // the sort below takes every particle
   for (int64_t t = 0; t < n; ++t) h->n_added = std::max<int64_t>(h->n_added, ids[t] + 1);
   rc = write_count(h, (int32_t)n);
   if (rc) return rc;
