@@ -210,3 +210,55 @@ def test_mini_cavity_all_pieces():
         assert np.array_equal(mg[:, 0], mo[:, 0])
         assert np.allclose(mg[:, 1:], mo[:, 1:], rtol=1e-9, atol=1e-12)
     assert g.num_particles > 100
+
+
+def test_all_pieces_with_ck_and_filter_fp64():
+    """Cole-Karkkainen at c dt = dx, two filter passes, a conductor block, per-face damping
+    and a source entering through the low z PML, together with random fields and particles:
+    FP64 against the oracle."""
+    ns = 200
+    cfg = W.SimConfig(dim=3, n=(12, 10, 14), pml=((3, 4), (4, 3), (5, 5)), dx=(1.0, 1.0, 1.0), dt=1.0,
+                      shape_order=2, alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.paper_conductivity_profile(5),
+                      push=1, charge=1.0, mass=4.0, precision=64, solver=1, filter_passes=2, conductor=1,
+                      max_source=ns, alpha_face=((0, ZERO), (0, 0), (ONE, DAMPED)), sort_interval=3)
+    parts = W.random_particles(cfg, 150, seed=901, margin=2.0, umax=1.5)
+    fields = W.random_split_fields(cfg, seed=902, amp=0.2)
+    rng = np.random.default_rng(903)
+    x = np.stack([rng.uniform(2.0, 10.0, ns), rng.uniform(2.0, 8.0, ns), rng.uniform(-20.0, -5.2, ns)], axis=1)
+    u = np.stack([rng.normal(0.0, 0.1, ns), rng.normal(0.0, 0.1, ns), rng.uniform(1.0, 4.0, ns)], axis=1)
+    w = rng.uniform(0.5, 1.5, ns) * 0.05
+    g, o = both(cfg, parts, fields, max_particles=len(parts) + ns, flags=B.FLAG_KEEP_CURRENT)
+    cells = np.zeros((o.M[2], o.M[1], o.M[0]), np.uint8)
+    cells[8:13, :, 10:] = 1
+    for s in (g, o):
+        s.set_conductor(cells)
+        s.set_source(x, u, w, axis=2)
+    for N in (2, 6, 15, 30):
+        g.step(N - o.step_count)
+        o.step(N - o.step_count)
+        compare_fields(g, o, cfg, 1e-9, "step %d" % N)
+        compare_current(g, o, 1e-9, "J step %d" % N)
+        compare_particles(g, o, 1e-9, 1e-9, "step %d" % N)
+
+
+def test_source_injection_fp32():
+    """FP32 against the FP64 oracle with a source: relative L2 error 1e-5 per field
+    component, measured against the norm of the largest component (B_z, driven by the
+    small transverse currents of a beam moving along z, has a norm far below that of E,
+    and rounding errors of the large components reach it in absolute terms)."""
+    cfg64, (x, u, w) = _source_case(1, seed=960)
+    cfg64 = cfg64.replace(dt=float(np.float32(0.5)))
+    cfg32 = cfg64.replace(precision=32)
+    g, _ = both(cfg32, max_particles=len(w))
+    _, o = both(cfg64, max_particles=len(w))
+    g.set_source(x, u, w, axis=2)
+    o.set_source(x, u, w, axis=2)
+    g.step(30)
+    o.step(30)
+    Fg, Fo = g.fields(), o.fields()
+    big = max(np.linalg.norm(Fo[c]) for c in range(6))
+    for c in range(6):
+        e = np.linalg.norm(Fg[c] - Fo[c]) / big
+        say("fp32 source component", c, e, np.linalg.norm(Fo[c]) / big)
+        assert e <= 1e-5, (c, e)
+    compare_particles(g, o, 1e-4, 1e-4, "fp32 source")
