@@ -85,3 +85,15 @@ def test_field_error_matches_oracle(mode):
     say("field error", mode, e_gpu, e_orc)
     assert e_orc > 1e-6
     assert abs(e_gpu - e_orc) <= 1e-9 * e_orc
+
+
+def test_field_error_rejects_mismatched_reference():
+    cfg = W.single_particle_config(precision=64, n=40, pml=8, push=0)
+    g, _ = both(cfg, W.single_particle(cfg))
+    for bad in (W.single_particle_config(precision=32, n=40, pml=8, push=0),   # precision
+                W.single_particle_config(precision=64, n=40, pml=6, push=0),   # low PML
+                W.single_particle_config(precision=64, n=20, pml=8, push=0)):  # does not cover the box
+        r, _ = both(bad, W.single_particle(bad))
+        with pytest.raises(Exception):
+            g.field_error(r)
+    assert g.field_error(g) == 0.0
