@@ -262,3 +262,19 @@ def test_source_injection_fp32():
         say("fp32 source component", c, e, np.linalg.norm(Fo[c]) / big)
         assert e <= 1e-5, (c, e)
     compare_particles(g, o, 1e-4, 1e-4, "fp32 source")
+
+
+def test_source_capacity_is_checked_before_injecting():
+    """Room for the source is checked when it is set; particles added afterwards can take that
+    room, and the step that would inject past max_particles fails with E_CAPACITY instead of
+    writing beyond the particle buffers."""
+    cfg, (x, u, w) = _source_case(0, seed=980, ns=100)
+    g, _ = both(cfg, max_particles=100)
+    g.set_source(x, u, w, axis=2)
+    extra = W.random_particles(cfg, 30, seed=981, margin=2.0, umax=0.1)
+    g.add_particles(extra.x, extra.u, extra.w)
+    with pytest.raises(B.PmlPicError) as e:
+        g.step(60)
+    assert e.value.code == -6
+    with pytest.raises(B.PmlPicError):
+        g.set_source(x, u, w, axis=2)          # 30 + 100 > 100
