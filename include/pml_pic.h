@@ -73,7 +73,11 @@ enum {
 
 typedef struct {
     int32_t dim;                /* 2 (x-y plane, 2D3V) or 3 */
-    int32_t n[3];               /* physical cells per axis (ignored beyond dim) */
+    int32_t n[3];               /* physical cells per axis (ignored beyond dim).  Limits, with
+                                   M = n + both PML thicknesses: 2D M <= 65533 per axis and
+                                   (M_x + 9 rounded up to 64) (M_y + 9) < 2^31 samples; 3D
+                                   M <= 2045, 2045, 1021; the grid rounded up to whole sort
+                                   tiles < 2^31 cells */
     int32_t pml[3][2];          /* PML cells per axis, low / high face; 0 = bare PEC wall */
     double dx[3];               /* cell sizes */
     double dt;                  /* time step; c dt < 1/sqrt(sum 1/dx_d^2) (Yee), c dt <= dx (CK) */

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -158,6 +159,20 @@ int validate(const pml_pic_params *p, std::string *err) {
   if (p->sort_interval < 0) return fail(err, PML_PIC_E_INVALID_ARG, "sort_interval must be >= 0");
   for (int d = 0; d < 3; ++d)
     if (p->tile[d] < 0) return fail(err, PML_PIC_E_INVALID_ARG, "tile must be >= 0");
+  {
+    // the 2D kernels address samples with 32-bit offsets, and the sort counts cell keys
+    // (the grid rounded up to whole tiles) in 32-bit integers
+    const int64_t Ms[3] = {M0, M1, M2};
+    const int64_t px = ((int64_t)M0 + 1 + 2 * G + 63) / 64 * 64;
+    if (p->dim == 2 && px * ((int64_t)M1 + 1 + 2 * G) > (int64_t)INT32_MAX)
+      return fail(err, PML_PIC_E_INVALID_ARG, "2D grid too large for 32-bit sample offsets");
+    int64_t keys = 1;
+    for (int d = 0; d < p->dim; ++d) {
+      const int64_t t = p->tile[d] > 0 ? p->tile[d] : (p->dim == 2 ? 16 : 8);
+      keys *= (Ms[d] + t - 1) / t * t;
+      if (keys > (int64_t)INT32_MAX) return fail(err, PML_PIC_E_INVALID_ARG, "grid too large for 32-bit sort keys");
+    }
+  }
   if (!(p->mass > 0.0) || !std::isfinite(p->charge)) return fail(err, PML_PIC_E_INVALID_ARG, "need mass > 0, finite charge");
   return PML_PIC_OK;
 }

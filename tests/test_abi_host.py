@@ -75,6 +75,32 @@ def test_parameter_validation_codes(lib):
     assert lib.pml_pic_workspace_size(C.byref(p), C.byref(n)) == -1
 
 
+def test_grid_size_limits(lib):
+    """Grids whose padded arrays pass 2^31 samples (2D: 32-bit sample offsets) or whose
+    tile-rounded cell count passes 2^31 (the sort's keys) are rejected before anything is
+    allocated; the largest grids inside both limits are accepted."""
+    def size2(n, pml=0):
+        cfg = W.SimConfig(dim=2, n=(n, n), pml=((pml, pml),) * 2, dt=0.5, max_particles=4)
+        return _size(cfg)
+
+    assert size2(46000)[0] == 0                           # 46016 x 46009 samples < 2^31
+    rc, _ = size2(46400)                                  # 46464 x 46409 > 2^31
+    assert rc == -1 and b"32-bit sample offsets" in lib.pml_pic_last_error(None)
+
+    def size3(nz, tile=(0, 0, 0)):
+        cfg = W.SimConfig(dim=3, n=(2045, 2045, nz), pml=((0, 0),) * 3, dt=0.5, max_particles=4)
+        p = B.make_params(cfg, max_particles=4)
+        for d in range(3):
+            p.tile[d] = tile[d]
+        n = C.c_size_t()
+        return lib.pml_pic_workspace_size(C.byref(p), C.byref(n))
+
+    assert size3(504) == 0                                # 2048 x 2048 x 504 keys < 2^31
+    assert size3(505) == -1                               # 2048 x 2048 x 512 = 2^31
+    assert b"sort keys" in lib.pml_pic_last_error(None)
+    assert size3(100, tile=(1 << 20, 8, 8)) == -1         # a huge tile rounds the key range up
+
+
 def test_ck_solver_and_filter_validation(lib):
     """The Cole-Karkkainen solver is 3D with cubic cells and c dt <= dx (App. A); the
     binomial current filter is 3D with 0..4 passes."""
