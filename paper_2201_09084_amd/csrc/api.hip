@@ -1293,9 +1293,6 @@ void pml_pic_batch_destroy(pml_pic_batch *b) {
 
 }  // extern "C"
 
-namespace {
-}  // namespace
-
 // ===================================================================== C ABI
 extern "C" {
 
