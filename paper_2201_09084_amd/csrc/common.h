@@ -268,7 +268,7 @@ void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s)
 // the next sort (allowance in the LDS fit test)
 void launch_range_items(const TileWork &tw, const uint32_t *cell, const int32_t *count, int order, int max_ranges,
                         int drift, hipStream_t s);
-constexpr int RANGE_SPLIT_MAX = 4;                      // items per range at most
+constexpr int RANGE_SPLIT_MAX = 8;                      // items per range at most
 int tiled_chunk(int dim);   // particles per chunk of the tiled step
 int tiled_nodes(int dim);   // LDS nodes per current component of one chunk's box
 template <typename T>
