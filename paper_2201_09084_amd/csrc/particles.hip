@@ -259,13 +259,13 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
 
 // 2D work list, built after every sort: fixed ranges of `chunk` sorted particles.  A
 // range whose node box does not fit in LDS (sparse particles: its deposits go to
-// global memory, about forty atomics per particle) is split into RANGE_SPLIT items,
-// and those items come first: the workgroups of the pieces start together and land on
-// different compute units, so no unit issues all of a range's global atomics while
-// its other workgroups wait behind them, and a piece whose own box fits uses LDS.  The
-// workgroups of the later ranges start as earlier ones finish.  (A work queue with an
-// atomic counter was slower: atomics on one word from every workgroup serialise across
-// the chip.  On the 2D beam 8 pieces beat 1, 2, 4 and 16.)
+// global memory, about forty atomics per particle) is split into RANGE_SPLIT items, so
+// that no compute unit issues all of a range's global atomics and a piece whose own box
+// fits uses LDS, and those items come last: the ranges that fit take the first round
+// of workgroup slots, and the pieces, short, fill slots as they free up.  (Listed
+// first, the pieces held slots that whole ranges then had to wait for.  A work queue
+// with an atomic counter was slower: atomics on one word from every workgroup
+// serialise across the chip.  On the 2D beam 8 pieces beat 1, 2, 4 and 16.)
 constexpr int RANGE_SPLIT = RANGE_SPLIT_MAX;
 
 // per range: 1 if its box (cells at the sort plus the deposit window and the drift
@@ -300,7 +300,7 @@ __global__ void k_range_classify(TileWork tw, const uint32_t *cell, const int32_
   }
 }
 
-// one workgroup: heavy ranges first (RANGE_SPLIT items each), then the others in order;
+// one workgroup: the ranges that fit in order, then the heavy ones (RANGE_SPLIT items each);
 // the item count goes to *n_items
 constexpr int ITEMS_TPB = 1024;
 __global__ void __launch_bounds__(ITEMS_TPB) k_range_items(TileWork tw, const int32_t *count) {
@@ -337,13 +337,13 @@ __global__ void __launch_bounds__(ITEMS_TPB) k_range_items(TileWork tw, const in
     if (c < nch) {
       const int p0 = c * tw.chunk, p1 = min(p0 + tw.chunk, n);
       if (f) {
-        const int first = (int)((carry_h + (ex >> 16)) * RANGE_SPLIT);
+        const int first = (int)((uint32_t)nch - n_heavy + (carry_h + (ex >> 16)) * RANGE_SPLIT);
         for (int k = 0; k < RANGE_SPLIT; ++k) {
           const int q0 = min(p0 + k * piece, p1), q1 = min(q0 + piece, p1);
           tw.items[first + k] = make_int4(q0, q1, 0, 0);
         }
       } else {
-        tw.items[n_heavy * RANGE_SPLIT + carry_l + (ex & 0xFFFFu)] = make_int4(p0, p1, 0, 0);
+        tw.items[carry_l + (ex & 0xFFFFu)] = make_int4(p0, p1, 0, 0);
       }
     }
     __syncthreads();

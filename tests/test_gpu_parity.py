@@ -345,7 +345,7 @@ def test_weight_damping_matches_oracle(dim, flags, precision):
 def test_dense_and_sparse_ranges_2d():
     """A dense cluster (ranges of 1024 sorted particles whose node box fits in LDS) next
     to a sparse population (ranges whose box does not: split into eight pieces that
-    deposit to global memory, listed first), over several sort intervals."""
+    deposit to global memory, listed last), over several sort intervals."""
     cfg = W.SimConfig(dim=2, n=(120, 100, 1), pml=((10, 10), (10, 10), (0, 0)), dt=0.7, shape_order=2,
                       alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.cubic_profile(3.2), push=1, precision=64,
                       tile=(16, 16, 1), sort_interval=4)
