@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   if (DIM == 2 && jc.prev) jclear_share(g, jc);   // the other current buffer (a different array)
   int p0, p1, t = -1;
   {
-    // by tile: the items of the tiles; else the 2D list (heavy pieces first).  Uniform.
+    // by tile: the items of the tiles; else the 2D list (heavy pieces last).  Uniform.
     // (Giving each XCD a contiguous eighth of the 3D list cut the fetched bytes by 3x
     // but ran 5% slower: the order below spreads the work of every region over all XCDs.)
     const unsigned n_items = BY_TILE ? tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles] : *tw.n_items;
