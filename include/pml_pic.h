@@ -24,7 +24,9 @@
  * below are read or written before the call returns (the call synchronises the
  * stream when it copies to or from the host) and stay owned by the caller.
  *
- * Errors: every call returns a pml_pic_status; no C++ exception crosses the ABI.
+ * Errors: every call returns a pml_pic_status; no C++ exception crosses the ABI (one
+ * thrown inside a call, e.g. std::bad_alloc from a host buffer sized by the caller's
+ * arguments, is caught there and returned as PML_PIC_E_HOST with a message).
  * pml_pic_last_error() gives a message for the last failure on a handle.  A handle is
  * used by one host thread at a time.  Particles that leave through the outer PEC walls
  * are removed and counted; that is not an error.
@@ -46,7 +48,9 @@ typedef enum {
     PML_PIC_E_WORKSPACE = -3,     /* workspace smaller than pml_pic_workspace_size or misaligned */
     PML_PIC_E_HIP = -4,           /* a HIP runtime call failed (message has the HIP error) */
     PML_PIC_E_NONFINITE = -5,     /* pml_pic_diagnose found NaN/Inf in the fields */
-    PML_PIC_E_CAPACITY = -6       /* more particles than max_particles */
+    PML_PIC_E_CAPACITY = -6,      /* more particles than max_particles */
+    PML_PIC_E_HOST = -7           /* host-side failure: out of host memory, or another C++
+                                     exception caught at the ABI (the message says which) */
 } pml_pic_status;
 
 /* current-damping scheme in the PML (the alpha of Eq. MaxwellE) */
@@ -243,6 +247,20 @@ int pml_pic_set_source(pml_pic_handle *h, int64_t n, const double *x, const doub
  * sum w u_y and sum w u_z (FP64 sums).  <u_x> = out[2] / out[1] per slab gives the
  * deflection diagnostic of Sec. IV.A.  1 <= n_slabs <= 64.  Synchronises. */
 int pml_pic_slab_moments(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const double *edges, double *out);
+
+/* sort_particles as its own call (the step also runs it every sort_interval steps and
+ * after particles are added).  Counting sort of the live particles by their cell's
+ * tile-major key, into the other particle buffer; removed particles are dropped.  With
+ * tiles of tile[0] x tile[1] x tile[2] cells (pml_pic_params.tile, or the default: 16 x 16
+ * in 2D, 8 x 8 x 8 in 3D), numbered x fastest over ntile_d = ceil(M_d / tile[d]) tiles per
+ * axis, the key of cell (i, j, k) is
+ *   ((tz ntile_1 + ty) ntile_0 + tx) (tile[0] tile[1] tile[2]) + (lz tile[1] + ly) tile[0] + lx
+ * with t = index / tile and l = index - t tile per axis.  Particles of equal key keep no
+ * particular order.  tile (3 ints, may be NULL) receives the tile shape; *n_keys (may be
+ * NULL) the number of keys; key_start (host, may be NULL, then cap is ignored; else cap >=
+ * n_keys + 1) the first sorted slot of every key followed by the live particle count.
+ * Synchronises.  Not available with PML_PIC_FLAG_NO_SORT. */
+int pml_pic_sort_particles(pml_pic_handle *h, int32_t tile[3], uint32_t *key_start, int64_t cap, int64_t *n_keys);
 
 /* Live particle count (synchronises). */
 int pml_pic_num_particles(pml_pic_handle *h, int64_t *n);

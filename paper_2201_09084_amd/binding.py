@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpmlpic.so")
 
 PML_PIC_OK = 0
 STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_CFL", -3: "E_WORKSPACE", -4: "E_HIP",
-          -5: "E_NONFINITE", -6: "E_CAPACITY"}
+          -5: "E_NONFINITE", -6: "E_CAPACITY", -7: "E_HOST"}
 FLAG_UNFUSED, FLAG_NO_SORT, FLAG_SEPARATE_DAMP, FLAG_KEEP_CURRENT, FLAG_SEPARATE_FIELDS = 1, 2, 4, 8, 16
 
 EXPORTED = [
@@ -30,7 +30,7 @@ EXPORTED = [
     "pml_pic_batch_set_launch", "pml_pic_batch_step", "pml_pic_batch_last_error",
     "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
     "pml_pic_backward", "pml_pic_set_conductor", "pml_pic_set_source", "pml_pic_slab_moments",
-    "pml_pic_field_error",
+    "pml_pic_field_error", "pml_pic_sort_particles",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
@@ -108,6 +108,7 @@ def load_library():
             "pml_pic_set_source": (C.c_int, [vp, i64, dp, dp, dp, i32]),
             "pml_pic_slab_moments": (C.c_int, [vp, i32, i32, dp, dp]),
             "pml_pic_field_error": (C.c_int, [vp, vp, dp, dp]),
+            "pml_pic_sort_particles": (C.c_int, [vp, P(C.c_int32), P(C.c_uint32), i64, P(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,11 +251,28 @@ class PmlPic:
         w = np.ascontiguousarray(w, dtype=np.float64)
         self._check(load_library().pml_pic_set_source(self._h, len(w), _dp(x), _dp(u), _dp(w), int(axis)))
 
+    def sort_particles(self):
+        """Sorts the particles now; returns (tile shape, key_start of n_keys + 1 entries:
+        the first slot of every key, then the particle count)."""
+        L = load_library()
+        tile = (C.c_int32 * 3)()
+        nk = C.c_int64()
+        self._check(L.pml_pic_sort_particles(self._h, tile, None, 0, C.byref(nk)))
+        ks = np.zeros(int(nk.value) + 1, dtype=np.uint32)
+        self._check(L.pml_pic_sort_particles(self._h, tile, ks.ctypes.data_as(C.POINTER(C.c_uint32)), ks.size,
+                                             C.byref(nk)))
+        return (int(tile[0]), int(tile[1]), int(tile[2])), ks
+
     def field_error(self, ref) -> float:
         """Eq. (error) against the reference run `ref` over this run's physical box."""
+        num, den = self.field_error_sums(ref)
+        return num / den if den > 0 else num
+
+    def field_error_sums(self, ref):
+        """(sum (F - F_ref)^2, sum F_ref^2) of Eq. (error)."""
         num, den = C.c_double(), C.c_double()
         self._check(load_library().pml_pic_field_error(self._h, ref._h, C.byref(num), C.byref(den)))
-        return num.value / den.value if den.value > 0 else num.value
+        return num.value, den.value
 
     def slab_moments(self, axis, edges) -> np.ndarray:
         """(nslab, 5): count, sum w, sum w u_x, sum w u_y, sum w u_z per slab of `axis`."""
@@ -270,8 +288,9 @@ class PmlPic:
         w = np.ascontiguousarray(w, dtype=np.float64)
         self._check(load_library().pml_pic_set_particles(self._h, len(w), _lp(ids), _dp(X), _dp(u), _dp(w)))
 
-    def particles(self, cap=None):
-        """(ids, X grid coordinates n x 3, u n x 3, w) of the live particles, sorted by id."""
+    def particles(self, cap=None, device_order=False):
+        """(ids, X grid coordinates n x 3, u n x 3, w) of the live particles, sorted by id
+        (device_order: in their order on the device)."""
         if cap is None:
             cap = max(1, int(self.params.max_particles))
         ids = np.zeros(cap, np.int64)
@@ -282,6 +301,8 @@ class PmlPic:
         self._check(load_library().pml_pic_get_particles(self._h, cap, _lp(ids), _dp(X), _dp(u), _dp(w),
                                                          C.byref(n)))
         n = int(n.value)
+        if device_order:
+            return ids[:n], X[:n], u[:n], w[:n]
         o = np.argsort(ids[:n], kind="stable")
         return ids[:n][o], X[:n][o], u[:n][o], w[:n][o]
 

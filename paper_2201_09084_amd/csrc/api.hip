@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -58,6 +60,32 @@ struct Layout {
 int fail(std::string *err, int code, const std::string &msg) {
   if (err) *err = msg;
   return code;
+}
+
+// Runs the body of an exported call.  A C++ exception (std::bad_alloc from a host vector
+// sized by the caller or the grid, or anything else the standard library throws) becomes
+// PML_PIC_E_HOST with a message instead of crossing the C ABI; setting the message may
+// itself run out of memory, in which case the code alone is returned.
+template <class Body>
+int abi_guard(std::string *err, Body &&body) noexcept {
+  const char *what = "unknown C++ exception";
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    what = "out of host memory";
+  } catch (const std::exception &e) {
+    try {
+      if (err) *err = std::string("C++ exception: ") + e.what();
+    } catch (...) {
+    }
+    return PML_PIC_E_HOST;
+  } catch (...) {
+  }
+  try {
+    if (err) *err = what;
+  } catch (...) {
+  }
+  return PML_PIC_E_HOST;
 }
 
 // depth inside the PML of axis d at grid coordinate X (0 in the physical box) and the
@@ -714,6 +742,24 @@ struct PhaseTimer {
   }
 };
 
+// sort_particles: counting sort of the live particles by tile-major cell key into the
+// other particle buffer (removed ones dropped), then the work list of the tiled push
+template <typename T>
+void sort_now(pml_pic_handle *h, const StepCtl &ctl, int ns) {
+  const Grid<T> g = h->grid<T>();
+  hipStream_t s = h->stream;
+  const bool fused = !(h->p.flags & PML_PIC_FLAG_UNFUSED);
+  launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
+  if (fused && h->p.dim == 3) launch_tile_chunks(h->tilework(), ctl.count, s);
+  if (fused && h->p.dim == 2)
+    launch_range_items(h->tilework(), h->parts<T>(1 - h->cur).cell, ctl.count, h->p.shape_order,
+                       (int)h->L.max_ranges, std::min(h->sort_interval - 1, 2), s);
+  h->cur = 1 - h->cur;
+  h->since_sort = 0;
+  h->sort_pending = false;
+  h->tail_n = 0;
+}
+
 template <typename T>
 int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
   const Grid<T> g = h->grid<T>();
@@ -766,16 +812,8 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       HIPCHK(h, hipMemcpyAsync(h->snap_state[it], F.E[0], h->L.fields_bytes, hipMemcpyDeviceToDevice, s));
     if (use_sort && ns > 0 && (h->sort_pending || h->since_sort >= h->sort_interval)) {
       pt.begin(s);
-      launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
-      if (fused && h->p.dim == 3) launch_tile_chunks(h->tilework(), ctl.count, s);
-      if (fused && h->p.dim == 2)
-        launch_range_items(h->tilework(), h->parts<T>(1 - h->cur).cell, ctl.count, h->p.shape_order,
-                           (int)h->L.max_ranges, std::min(h->sort_interval - 1, 2), s);
+      sort_now<T>(h, ctl, ns);
       pt.end(s, PML_PIC_PHASE_SORT);
-      h->cur = 1 - h->cur;
-      h->since_sort = 0;
-      h->sort_pending = false;
-      h->tail_n = 0;
     }
     const bool tiled = fused && use_sort && ns > 0;
     if (one_pass && !tiled) {   // the tiled deposit clears the other buffer itself
@@ -1172,7 +1210,7 @@ int batch_step_t(pml_pic_batch *b, int n, PhaseTimer *pt = nullptr) {
 
 extern "C" {
 
-int pml_pic_batch_workspace_size(const pml_pic_params *runs, int32_t n_runs, size_t *bytes) {
+static int pml_pic_batch_workspace_size_impl(const pml_pic_params *runs, int32_t n_runs, size_t *bytes) {
   if (!bytes) return PML_PIC_E_INVALID_ARG;
   std::vector<Layout> Ls;
   std::vector<size_t> offs;
@@ -1183,7 +1221,7 @@ int pml_pic_batch_workspace_size(const pml_pic_params *runs, int32_t n_runs, siz
   return PML_PIC_OK;
 }
 
-int pml_pic_batch_create(const pml_pic_params *runs, int32_t n_runs, void *device_workspace, size_t bytes,
+static int pml_pic_batch_create_impl(const pml_pic_params *runs, int32_t n_runs, void *device_workspace, size_t bytes,
                          void *stream, int32_t use_graph, pml_pic_batch **out) {
   if (!out) return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -1241,7 +1279,7 @@ pml_pic_handle *pml_pic_batch_run(pml_pic_batch *b, int32_t run) {
   return b->runs[run];
 }
 
-int pml_pic_batch_set_launch(pml_pic_batch *b, int32_t block_x, int32_t grid_blocks) {
+static int pml_pic_batch_set_launch_impl(pml_pic_batch *b, int32_t block_x, int32_t grid_blocks) {
   if (!b) return PML_PIC_E_INVALID_ARG;
   if (block_x != 32 && block_x != 64 && block_x != 128 && block_x != 256)
     return fail(&b->err, PML_PIC_E_INVALID_ARG, "block_x must be 32, 64, 128 or 256");
@@ -1252,13 +1290,13 @@ int pml_pic_batch_set_launch(pml_pic_batch *b, int32_t block_x, int32_t grid_blo
   return batch_build_items(b, block_x);
 }
 
-int pml_pic_batch_step(pml_pic_batch *b, int32_t n_steps) {
+static int pml_pic_batch_step_impl(pml_pic_batch *b, int32_t n_steps) {
   if (!b) return PML_PIC_E_INVALID_ARG;
   if (n_steps < 0) return fail(&b->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
   return b->prec == 64 ? batch_step_t<double>(b, n_steps) : batch_step_t<float>(b, n_steps);
 }
 
-int pml_pic_batch_step_profiled(pml_pic_batch *b, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
+static int pml_pic_batch_step_profiled_impl(pml_pic_batch *b, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
   if (!b || !phase_ms || !phase_calls) return PML_PIC_E_INVALID_ARG;
   if (n_steps < 0) return fail(&b->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
   PhaseTimer pt;
@@ -1296,7 +1334,7 @@ void pml_pic_batch_destroy(pml_pic_batch *b) {
 // ===================================================================== C ABI
 extern "C" {
 
-int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes) {
+static int pml_pic_workspace_size_impl(const pml_pic_params *params, size_t *bytes) {
   if (!bytes) return PML_PIC_E_INVALID_ARG;
   const int rc = validate(params, &g_create_error);
   if (rc) return rc;
@@ -1306,12 +1344,12 @@ int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes) {
   return PML_PIC_OK;
 }
 
-int pml_pic_create(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream,
+static int pml_pic_create_impl(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream,
                    pml_pic_handle **out) {
   return create_handle(params, device_workspace, bytes, stream, out, &g_create_error);
 }
 
-int pml_pic_add_particles(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w) {
+static int pml_pic_add_particles_impl(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   if (n < 0 || (n > 0 && (!x || !u || !w))) return fail(&h->err, PML_PIC_E_INVALID_ARG, "bad particle arrays");
   if (n == 0) return PML_PIC_OK;
@@ -1416,7 +1454,7 @@ int upload_source(pml_pic_handle *h, const std::vector<int64_t> &order, const st
 
 extern "C" {
 
-int pml_pic_set_conductor(pml_pic_handle *h, const uint8_t *cells) {
+static int pml_pic_set_conductor_impl(pml_pic_handle *h, const uint8_t *cells) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   if (!h->p.conductor) return fail(&h->err, PML_PIC_E_INVALID_ARG, "created without params.conductor");
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1435,7 +1473,7 @@ int pml_pic_set_conductor(pml_pic_handle *h, const uint8_t *cells) {
   return PML_PIC_OK;
 }
 
-int pml_pic_set_source(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w, int32_t axis) {
+static int pml_pic_set_source_impl(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w, int32_t axis) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   const int dim = h->p.dim;
   if (n < 0 || (n > 0 && (!x || !u || !w))) return fail(&h->err, PML_PIC_E_INVALID_ARG, "bad source arrays");
@@ -1484,7 +1522,7 @@ int pml_pic_set_source(pml_pic_handle *h, int64_t n, const double *x, const doub
   return PML_PIC_OK;
 }
 
-int pml_pic_slab_moments(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const double *edges, double *out) {
+static int pml_pic_slab_moments_impl(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const double *edges, double *out) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   if (axis < 0 || axis >= h->p.dim) return fail(&h->err, PML_PIC_E_INVALID_ARG, "axis out of range");
   if (n_slabs < 1 || n_slabs > SLAB_MAX) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_slabs must be in [1,64]");
@@ -1507,7 +1545,7 @@ int pml_pic_slab_moments(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const
   return PML_PIC_OK;
 }
 
-int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X, const double *u,
+static int pml_pic_set_particles_impl(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X, const double *u,
                           const double *w) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   if (n < 0 || (n > 0 && (!ids || !X || !u || !w))) return fail(&h->err, PML_PIC_E_INVALID_ARG, "bad particle arrays");
@@ -1526,14 +1564,14 @@ int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, cons
   return PML_PIC_OK;
 }
 
-int pml_pic_step(pml_pic_handle *h, int32_t n_steps) {
+static int pml_pic_step_impl(pml_pic_handle *h, int32_t n_steps) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   if (n_steps < 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
   PhaseTimer pt;
   return h->p.precision == 64 ? step_t<double>(h, n_steps, pt) : step_t<float>(h, n_steps, pt);
 }
 
-int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
+static int pml_pic_step_profiled_impl(pml_pic_handle *h, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
   if (!h || !phase_ms || !phase_calls) return PML_PIC_E_INVALID_ARG;
   if (n_steps < 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
   PhaseTimer pt;
@@ -1556,7 +1594,7 @@ int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, 
   return rc;
 }
 
-int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
+static int field_error_check(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
   if (!h || !ref || !num || !den) return PML_PIC_E_INVALID_ARG;
   const pml_pic_params &a = h->p, &b = ref->p;
   if (a.dim != b.dim || a.precision != b.precision)
@@ -1565,9 +1603,15 @@ int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, dou
     if (a.dx[d] != b.dx[d] || a.pml[d][0] != b.pml[d][0] || b.n[d] + b.pml[d][1] < a.n[d])
       return fail(&h->err, PML_PIC_E_INVALID_ARG,
                   "the reference needs the same cells and low PML and must cover the physical box");
+  return PML_PIC_OK;
+}
+
+static int pml_pic_field_error_impl(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
+  const int rc = field_error_check(h, ref, num, den);
+  if (rc) return rc;
   HIPCHK(h, hipStreamSynchronize(ref->stream));
   const DiagWork dw = h->diagwork();
-  if (a.precision == 64)
+  if (h->p.precision == 64)
     launch_field_error<double>(h->grid<double>(), h->fields<double>(), ref->grid<double>(), ref->fields<double>(),
                                dw.partial, dw.result, h->stream);
   else
@@ -1582,12 +1626,12 @@ int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, dou
   return PML_PIC_OK;
 }
 
-int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out) {
+static int pml_pic_diagnose_impl(pml_pic_handle *h, pml_pic_diag *out) {
   if (!h || !out) return PML_PIC_E_INVALID_ARG;
   return h->p.precision == 64 ? diagnose_t<double>(h, out) : diagnose_t<float>(h, out);
 }
 
-int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples) {
+static int pml_pic_grid_shape_impl(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples) {
   if (!h || !nn || !n_samples) return PML_PIC_E_INVALID_ARG;
   for (int d = 0; d < 3; ++d) nn[d] = h->L.nn[d];
   *n_samples = (int64_t)h->L.nn[0] * h->L.nn[1] * h->L.nn[2];
@@ -1596,25 +1640,25 @@ int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_sample
 
 static int64_t n_samples_of(const pml_pic_handle *h) { return (int64_t)h->L.nn[0] * h->L.nn[1] * h->L.nn[2]; }
 
-int pml_pic_get_fields(pml_pic_handle *h, double *host, int64_t count) {
+static int pml_pic_get_fields_impl(pml_pic_handle *h, double *host, int64_t count) {
   if (!h || !host) return PML_PIC_E_INVALID_ARG;
   if (count < 12 * n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "field buffer too small");
   return h->p.precision == 64 ? get_fields_t<double>(h, host) : get_fields_t<float>(h, host);
 }
 
-int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count) {
+static int pml_pic_set_fields_impl(pml_pic_handle *h, const double *host, int64_t count) {
   if (!h || !host) return PML_PIC_E_INVALID_ARG;
   if (count < 12 * n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "field buffer too small");
   return h->p.precision == 64 ? set_fields_t<double>(h, host) : set_fields_t<float>(h, host);
 }
 
-int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count) {
+static int pml_pic_get_current_impl(pml_pic_handle *h, double *host, int64_t count) {
   if (!h || !host) return PML_PIC_E_INVALID_ARG;
   if (count < 3 * n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "current buffer too small");
   return h->p.precision == 64 ? get_current_t<double>(h, host) : get_current_t<float>(h, host);
 }
 
-int pml_pic_get_rho_static(pml_pic_handle *h, double *host, int64_t count) {
+static int pml_pic_get_rho_static_impl(pml_pic_handle *h, double *host, int64_t count) {
   if (!h || !host) return PML_PIC_E_INVALID_ARG;
   const Layout &L = h->L;
   if (count < n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "buffer too small");
@@ -1628,7 +1672,7 @@ int pml_pic_get_rho_static(pml_pic_handle *h, double *host, int64_t count) {
   return PML_PIC_OK;
 }
 
-int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count) {
+static int pml_pic_set_rho_static_impl(pml_pic_handle *h, const double *host, int64_t count) {
   if (!h || !host) return PML_PIC_E_INVALID_ARG;
   const Layout &L = h->L;
   if (count < n_samples_of(h)) return fail(&h->err, PML_PIC_E_INVALID_ARG, "buffer too small");
@@ -1642,7 +1686,37 @@ int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count)
   return PML_PIC_OK;
 }
 
-int pml_pic_num_particles(pml_pic_handle *h, int64_t *n) {
+static int pml_pic_sort_particles_impl(pml_pic_handle *h, int32_t tile[3], uint32_t *key_start, int64_t cap,
+                                       int64_t *n_keys) {
+  if (!h) return PML_PIC_E_INVALID_ARG;
+  if (key_start && cap < (int64_t)h->L.nkeys + 1)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "key_start needs n_keys + 1 entries");
+  if (h->p.flags & PML_PIC_FLAG_NO_SORT)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "the run was created with PML_PIC_FLAG_NO_SORT");
+  if (tile)
+    for (int d = 0; d < 3; ++d) tile[d] = h->L.tile[d];
+  if (n_keys) *n_keys = h->L.nkeys;
+  const int ns = (int)h->n_slots;
+  if (ns > 0) {
+    if (h->p.precision == 64) sort_now<double>(h, h->ctl(), ns);
+    else sort_now<float>(h, h->ctl(), ns);
+    HIPCHK(h, hipGetLastError());
+  }
+  if (key_start) {
+    const Layout &L = h->L;
+    if (ns > 0) {
+      HIPCHK(h, hipMemcpyAsync(key_start, h->at<uint32_t>(L.off_counts), 4 * (size_t)L.nkeys, hipMemcpyDeviceToHost,
+                               h->stream));
+      HIPCHK(h, hipMemcpyAsync(key_start + L.nkeys, h->at<int32_t>(L.off_count), 4, hipMemcpyDeviceToHost, h->stream));
+    } else {
+      std::fill(key_start, key_start + L.nkeys + 1, 0u);
+    }
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PML_PIC_OK;
+}
+
+static int pml_pic_num_particles_impl(pml_pic_handle *h, int64_t *n) {
   if (!h || !n) return PML_PIC_E_INVALID_ARG;
   pml_pic_diag d;
   const int rc = pml_pic_diagnose(h, &d);
@@ -1651,7 +1725,7 @@ int pml_pic_num_particles(pml_pic_handle *h, int64_t *n) {
   return PML_PIC_OK;
 }
 
-int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, double *u, double *w,
+static int pml_pic_get_particles_impl(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, double *u, double *w,
                           int64_t *n_out) {
   if (!h || !n_out || (cap > 0 && (!ids || !X || !u || !w))) return PML_PIC_E_INVALID_ARG;
   return h->p.precision == 64 ? get_particles_t<double>(h, cap, ids, X, u, w, n_out)
@@ -1920,12 +1994,12 @@ int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double
 
 extern "C" {
 
-int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U) {
+static int pml_pic_forward_ckpt_impl(pml_pic_handle *h, int32_t n_steps, double *U) {
   if (!h || !U) return PML_PIC_E_INVALID_ARG;
   return h->p.precision == 64 ? forward_ckpt_t<double>(h, n_steps, U) : forward_ckpt_t<float>(h, n_steps, U);
 }
 
-int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out,
+static int pml_pic_backward_impl(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out,
                      double *grad_theta, int32_t n_theta) {
   if (!h || !grad_theta) return PML_PIC_E_INVALID_ARG;
   if (n_theta != 16 * h->p.dim + 1) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_theta must be 16 dim + 1");
@@ -1933,6 +2007,120 @@ int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, 
   if (seed && seed_count < 12 * ns) return fail(&h->err, PML_PIC_E_INVALID_ARG, "seed buffer too small");
   return h->p.precision == 64 ? backward_t<double>(h, seed, lambda_out, grad_theta)
                               : backward_t<float>(h, seed, lambda_out, grad_theta);
+}
+
+}  // extern "C"
+
+// ===================================================================== exported entry points
+// Every call runs its body under abi_guard: no C++ exception crosses the C ABI.
+extern "C" {
+
+int pml_pic_batch_workspace_size(const pml_pic_params *runs, int32_t n_runs, size_t *bytes) {
+  return abi_guard(&g_create_error, [&] { return pml_pic_batch_workspace_size_impl(runs, n_runs, bytes); });
+}
+
+int pml_pic_batch_create(const pml_pic_params *runs, int32_t n_runs, void *device_workspace, size_t bytes, void *stream, int32_t use_graph, pml_pic_batch **out) {
+  return abi_guard(&g_create_error, [&] { return pml_pic_batch_create_impl(runs, n_runs, device_workspace, bytes, stream, use_graph, out); });
+}
+
+int pml_pic_batch_set_launch(pml_pic_batch *b, int32_t block_x, int32_t grid_blocks) {
+  return abi_guard(b ? &b->err : &g_create_error, [&] { return pml_pic_batch_set_launch_impl(b, block_x, grid_blocks); });
+}
+
+int pml_pic_batch_step(pml_pic_batch *b, int32_t n_steps) {
+  return abi_guard(b ? &b->err : &g_create_error, [&] { return pml_pic_batch_step_impl(b, n_steps); });
+}
+
+int pml_pic_batch_step_profiled(pml_pic_batch *b, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
+  return abi_guard(b ? &b->err : &g_create_error, [&] { return pml_pic_batch_step_profiled_impl(b, n_steps, phase_ms, phase_calls); });
+}
+
+int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes) {
+  return abi_guard(&g_create_error, [&] { return pml_pic_workspace_size_impl(params, bytes); });
+}
+
+int pml_pic_create(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream, pml_pic_handle **out) {
+  return abi_guard(&g_create_error, [&] { return pml_pic_create_impl(params, device_workspace, bytes, stream, out); });
+}
+
+int pml_pic_add_particles(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_add_particles_impl(h, n, x, u, w); });
+}
+
+int pml_pic_set_conductor(pml_pic_handle *h, const uint8_t *cells) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_set_conductor_impl(h, cells); });
+}
+
+int pml_pic_set_source(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w, int32_t axis) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_set_source_impl(h, n, x, u, w, axis); });
+}
+
+int pml_pic_slab_moments(pml_pic_handle *h, int32_t axis, int32_t n_slabs, const double *edges, double *out) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_slab_moments_impl(h, axis, n_slabs, edges, out); });
+}
+
+int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X, const double *u, const double *w) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_set_particles_impl(h, n, ids, X, u, w); });
+}
+
+int pml_pic_step(pml_pic_handle *h, int32_t n_steps) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_step_impl(h, n_steps); });
+}
+
+int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_step_profiled_impl(h, n_steps, phase_ms, phase_calls); });
+}
+
+int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_field_error_impl(h, ref, num, den); });
+}
+
+int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_diagnose_impl(h, out); });
+}
+
+int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples) {
+  return abi_guard(&g_create_error, [&] { return pml_pic_grid_shape_impl(h, nn, n_samples); });
+}
+
+int pml_pic_get_fields(pml_pic_handle *h, double *host, int64_t count) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_get_fields_impl(h, host, count); });
+}
+
+int pml_pic_set_fields(pml_pic_handle *h, const double *host, int64_t count) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_set_fields_impl(h, host, count); });
+}
+
+int pml_pic_get_current(pml_pic_handle *h, double *host, int64_t count) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_get_current_impl(h, host, count); });
+}
+
+int pml_pic_get_rho_static(pml_pic_handle *h, double *host, int64_t count) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_get_rho_static_impl(h, host, count); });
+}
+
+int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_set_rho_static_impl(h, host, count); });
+}
+
+int pml_pic_sort_particles(pml_pic_handle *h, int32_t tile[3], uint32_t *key_start, int64_t cap, int64_t *n_keys) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_sort_particles_impl(h, tile, key_start, cap, n_keys); });
+}
+
+int pml_pic_num_particles(pml_pic_handle *h, int64_t *n) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_num_particles_impl(h, n); });
+}
+
+int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *X, double *u, double *w, int64_t *n_out) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_get_particles_impl(h, cap, ids, X, u, w, n_out); });
+}
+
+int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_forward_ckpt_impl(h, n_steps, U); });
+}
+
+int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out, double *grad_theta, int32_t n_theta) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_backward_impl(h, seed, seed_count, lambda_out, grad_theta, n_theta); });
 }
 
 }  // extern "C"

@@ -155,15 +155,15 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   LdsSink<T> lsink;
   const bool any = sb[0] <= sb[3];
   // replicas that fit for a box of n nodes per component (0: does not fit)
-  auto reps = [&](int n) {
-    const int st = (3 * n) | 1;
+  auto reps = [&](long n) {
+    const long st = (3 * n) | 1;
     int r = 0;
     while (r < 16 && (r ? 2 * r : 1) * st <= 3 * NODES) r = r ? 2 * r : 1;
     return r;
   };
   int o = 0;   // 0: whole bounding box; 6: clipped box, particles outside it go global
   if (BY_TILE && any) {
-    int full = 1, clip = 1;
+    long full = 1, clip = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       full *= sb[3 + d] - sb[d] + (WHI - WLO) + 1;
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     if (rf == 0 || (rc > rf && 16u * nout <= (unsigned)(p1 - p0))) o = 6;
   }
   int ext[3] = {1, 1, 1}, bmn[3] = {0, 0, 0}, bmx[3] = {0, 0, 0};
-  int total = 1;
+  long total = 1;   // 64-bit: the box of a sparse range can exceed 2^31 nodes
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < DIM) {
@@ -189,13 +189,15 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     }
     total *= ext[d];
   }
-  const int stride = (3 * total) | 1;
-  const bool use_lds = any && stride <= 3 * NODES;
+  const long lstride = (3 * total) | 1;
+  const bool use_lds = any && lstride <= 3 * NODES;
+  // past this point the box sizes are used only when the box fits in LDS (int range)
+  const int stride = use_lds ? (int)lstride : 1;
   int R = 1;
-  while (R < 16 && 2 * R * stride <= 3 * NODES) R *= 2;
+  while (use_lds && R < 16 && 2 * R * stride <= 3 * NODES) R *= 2;
   lsink.e0 = ext[0];
-  lsink.e01 = ext[0] * ext[1];
-  lsink.total = total;
+  lsink.e01 = use_lds ? ext[0] * ext[1] : 0;
+  lsink.total = use_lds ? (int)total : 0;
   if (use_lds) {
     for (int e = tid; e < R * stride; e += TPB) lds[e] = 0.0;
   }
@@ -241,13 +243,14 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   __syncthreads();
   if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
   if (use_lds) {
-    for (int e = tid; e < 3 * total; e += TPB) {
+    const int ntot = lsink.total;
+    for (int e = tid; e < 3 * ntot; e += TPB) {
       double acc = lds[e];
       for (int r = 1; r < R; ++r) acc += lds[r * stride + e];
       const T v = (T)acc;
       if (v == T(0)) continue;
-      const int comp = e / total;
-      int r = e - comp * total;
+      const int comp = e / ntot;
+      int r = e - comp * ntot;
       const int i = r % ext[0];
       r /= ext[0];
       const int j = r % ext[1];

@@ -159,3 +159,31 @@ def test_create_rejects_small_or_missing_workspace(lib):
     assert lib.pml_pic_create(C.byref(p), None, C.c_size_t(0), None, C.byref(h)) == -3
     assert lib.pml_pic_create(C.byref(p), C.c_void_p(256), C.c_size_t(10), None, C.byref(h)) == -3
     assert not h.value
+
+
+_BAD_ALLOC_CHILD = r"""
+import ctypes as C, sys
+sys.path.insert(0, %r)
+from paper_2201_09084_amd import binding as B
+from paper_2201_09084_amd import workloads as W
+L = B.load_library()
+p = B.make_params(W.single_particle_config(), max_particles=16)
+n = C.c_size_t(0)
+# 2^31 - 1 runs: the per-run layout table alone would need terabytes of host memory;
+# only the first run is read before that allocation
+rc = L.pml_pic_batch_workspace_size(C.byref(p), 2**31 - 1, C.byref(n))
+print("rc", rc, L.pml_pic_batch_last_error(None).decode(), flush=True)
+"""
+
+
+def test_host_allocation_failure_is_a_status_code(lib):
+    """A host allocation sized by the caller's arguments that fails (std::bad_alloc) is
+    caught inside the call and returned as PML_PIC_E_HOST with a message; without the
+    guard the exception would cross the C ABI and abort the process (run in a child)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _BAD_ALLOC_CHILD % root], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr[-2000:])
+    assert "rc -7 out of host memory" in r.stdout, r.stdout
