@@ -131,7 +131,7 @@ def _energy_error(a, r, nx, ny, L):
     return num / den
 
 
-@pytest.mark.parametrize("theta", [0.0, 30.0])
+@pytest.mark.parametrize("theta", [0.0, 30.0, 60.0])
 def test_single_particle_exit_error_ordering(theta):
     """Sec. III protocol: reference box doubled (here tripled) along the exit axis,
     error of Eq. (error) 60 steps after the crossing.  Ordering of Fig. 2:
@@ -149,3 +149,136 @@ def test_single_particle_exit_error_ordering(theta):
         errs[mode] = _energy_error(a, ref, nx, ny, L)
     assert errs[W.ALPHA_DAMPED] < 0.8 * errs[W.ALPHA_ONE]
     assert errs[W.ALPHA_ONE] < 0.5 * errs[W.ALPHA_ZERO]
+
+
+# ------------------------------------------------------------------ App. B: the fields of the method
+# A charge moving at constant velocity along +x (normal incidence on the +x face) from the
+# physical-box interior into the PML; 3D, Yee at c dt = 0.5, cubic shape and one binomial pass
+# (App. A's particle numerics: the smooth shape keeps the grid-scale transient of the
+# impulsive start small), ballistic (the derivation of App. B assumes constant v).
+P9_BETA, P9_NX, P9_NY, P9_BACK, P9_DEPTH, P9_DT = 0.5, 24, 24, 16, 5, 0.5
+
+
+def _p9_run(L, ext, mode=W.ALPHA_DAMPED, damping_scale=1.0 / P9_BETA):
+    cfg = W.SimConfig(dim=3, n=(P9_NX * ext, P9_NY, P9_NY), pml=((L, L),) * 3, dt=P9_DT, shape_order=3,
+                      alpha_mode=mode, damping_scale=damping_scale, sigma_coef=W.cubic_profile(3.2), push=0,
+                      filter_passes=1)
+    p = W.single_particle(cfg, beta=P9_BETA, start=(P9_NX - P9_BACK, P9_NY / 2, P9_NY / 2))
+    sim = oracle.OracleSim(cfg)
+    sim.add_particles(p.x, p.u, p.w)
+    sim.step(int(round((P9_BACK + P9_DEPTH) / P9_BETA / P9_DT)))
+    return cfg, sim
+
+
+def _sample_grid(comp, shape):
+    """Grid coordinates (node-index units) of the samples of component comp (E_x..B_z)."""
+    a = comp % 3
+    ax = []
+    for d, m in enumerate((shape[2], shape[1], shape[0])):
+        half = (d == a) if comp < 3 else (d != a)
+        ax.append(np.arange(m) + (0.5 if half else 0.0))
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return X, Y, Z
+
+
+def _ansatz_deviation(L, mode=W.ALPHA_DAMPED, damping_scale=1.0 / P9_BETA, radius=6.0, ref=None):
+    """Relative L2 distance, over the E and B samples inside the +x PML within `radius`
+    cells of the particle, between the PML run and alpha(x) times the run in a box doubled
+    along x (Eq. PMLfield of App. B: in the PML the field is alpha(z) times the vacuum field)."""
+    cfg, a = _p9_run(L, 1, mode, damping_scale)
+    if ref is None:
+        ref = _p9_run(L, 2, mode, damping_scale)[1]
+    Fa, Fr = a.fields(), ref.fields()
+    Fr = Fr[:, :Fa.shape[1], :Fa.shape[2], :Fa.shape[3]]
+    t = round((P9_BACK + P9_DEPTH) / P9_BETA / P9_DT) * P9_DT
+    cp = (L + P9_NX - P9_BACK + P9_BETA * t, L + P9_NY / 2, L + P9_NY / 2)
+    num = den = 0.0
+    for c in range(6):
+        X, Y, Z = _sample_grid(c, Fa.shape[1:])
+        alpha = np.array([a.alpha_axis(0, x) for x in X[0, 0, :]])[None, None, :]
+        m = ((X - cp[0]) ** 2 + (Y - cp[1]) ** 2 + (Z - cp[2]) ** 2 <= radius ** 2) & (X > L + P9_NX)
+        num += np.sum((Fa[c] - alpha * Fr[c])[m] ** 2)
+        den += np.sum((alpha * Fr[c])[m] ** 2)
+    return math.sqrt(num / den), ref
+
+
+@pytest.fixture(scope="module")
+def p9_reference():
+    """The run in the box doubled along x, L = 12 (the particle never reaches a layer)."""
+    return _p9_run(12, 2)
+
+
+@pytest.mark.slow
+def test_pml_field_is_alpha_times_vacuum_field(p9_reference):
+    """App. B, Eq. PMLfield: with Eq. (alpha) at the particle's own speed (v = 0.5c), the
+    field inside the PML near the particle, 5 cells deep, is alpha(x) times the vacuum field
+    (the run in the doubled box).  The Ansatz is exact for the continuous equations; the
+    discrete scheme approaches it as the profile is resolved: at the same sigma_max, a
+    12-cell layer (gentler grading per cell) is closer than an 8-cell one by about the square
+    of the thickness ratio (second order).  Undamped deposition (alpha = 1) and Eq. (alpha)
+    with v = c (too little damping for the slow particle) do not reach it.  Measured: 1.8%
+    (L = 12), 4.0% (L = 8), 48% undamped, 23% with v = c; the bounds leave about 1.5x room."""
+    d12, _ = _ansatz_deviation(12, ref=p9_reference[1])
+    d8, _ = _ansatz_deviation(8)
+    d_und, _ = _ansatz_deviation(12, mode=W.ALPHA_ONE, ref=p9_reference[1])
+    d_vc, _ = _ansatz_deviation(12, damping_scale=1.0, ref=p9_reference[1])
+    print("ansatz deviation: L=12 %.4f, L=8 %.4f, undamped %.4f, v=c %.4f" % (d12, d8, d_und, d_vc))
+    assert d12 < 0.03
+    assert d8 < 0.06
+    assert d12 < d8 / 1.6                      # second order in the profile's resolution
+    assert d_und > 0.25 and d_und > 10 * d12   # the Ansatz needs the damped current
+    assert d_vc > 0.10 and d_vc > 5 * d12      # ... with alpha at the particle's speed
+
+
+def _moving_charge_field(comp, X, Y, Z, xp, x0, yc, zc, beta, q=-1.0):
+    """App. B, Eq. physicalfield (c = eps0 = 1): E = q gamma R / (4 pi (gamma^2 X^2 + Y^2 +
+    Z^2)^(3/2)) of the charge at (xp, yc, zc) moving along +x, B = beta x-hat cross E; plus
+    the static field of the motionless partner -q at the start (x0, yc, zc) (App. A.1)."""
+    g = 1.0 / math.sqrt(1.0 - beta * beta)
+    dx, dy, dz = X - xp, Y - yc, Z - zc
+    d3 = (g * g * dx * dx + dy * dy + dz * dz) ** 1.5
+    Em = [q * g * dx / (4 * math.pi * d3), q * g * dy / (4 * math.pi * d3), q * g * dz / (4 * math.pi * d3)]
+    ex, ey, ez = X - x0, Y - yc, Z - zc
+    r3 = (ex * ex + ey * ey + ez * ez) ** 1.5
+    Ep = [-q * ex / (4 * math.pi * r3), -q * ey / (4 * math.pi * r3), -q * ez / (4 * math.pi * r3)]
+    if comp < 3:
+        return Em[comp] + Ep[comp]
+    return [0.0 * X, -beta * Em[2], beta * Em[1]][comp - 3]
+
+
+@pytest.mark.slow
+def test_interior_field_is_the_moving_charge_field(p9_reference):
+    """App. B, Eq. physicalfield: inside the sphere the start event's light front has passed,
+    the field of a charge moving uniformly since t = 0 with its motionless partner (E = B = 0
+    at t = 0, App. A.1) is the Lorentz-contracted Coulomb field of the moving charge plus the
+    static field of the partner, and B = v x E for the moving part.  The oracle's run in the
+    doubled box (the charge 29 cells in, 19 from the +x layer) is compared with it over the
+    shell 4-8 cells from the charge (beyond the smoothed shape, 4 cells wide with the filter,
+    and before the transverse layers 12 cells off axis): measured 2.7%, from the grid-scale
+    transient of the impulsive start and the finite-difference error at a few cells.  A wrong
+    current magnitude, sign, or time centring (a quarter-cell offset) gives several times
+    that."""
+    cfg, r = p9_reference
+    F = r.fields()
+    L = 12
+    t = round((P9_BACK + P9_DEPTH) / P9_BETA / P9_DT) * P9_DT
+    x0 = P9_NX - P9_BACK
+    xp = x0 + P9_BETA * t
+    yc = zc = P9_NY / 2
+    ids, Xp, up, wp = r.particles()
+    assert abs(Xp[0, 0] - (L + xp)) < 1e-9
+    devs = {}
+    for shift in (0.0, 0.25):
+        num = den = 0.0
+        for c in range(6):
+            Xg, Yg, Zg = _sample_grid(c, F.shape[1:])
+            X, Y, Z = Xg - L, Yg - L, Zg - L
+            A = _moving_charge_field(c, X, Y, Z, xp + shift, x0, yc, zc, P9_BETA)
+            rr = np.sqrt((X - xp) ** 2 + (Y - yc) ** 2 + (Z - zc) ** 2)
+            m = (rr >= 4.0) & (rr < 8.0)
+            num += np.sum((F[c] - A)[m] ** 2)
+            den += np.sum(A[m] ** 2)
+        devs[shift] = math.sqrt(num / den)
+    print("moving-charge field deviation %.4f (analytic charge a quarter cell ahead: %.4f)" % (devs[0.0], devs[0.25]))
+    assert devs[0.0] < 0.045
+    assert devs[0.25] > 2 * devs[0.0]
