@@ -190,6 +190,19 @@ int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out);
  * num / den.  Both handles must live on the current device.  Synchronises both streams. */
 int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den);
 
+/* pml_pic_field_error for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same sums,
+ * with the per-workgroup partials and the result in a static device array of the library
+ * (513 KiB per GPU, held until the process ends) instead of the handle's workspace.  It
+ * calls no hipMalloc/hipFree and allocates nothing on the device.  At most 32768
+ * workgroups hold partials (each covers several rows and planes on larger grids); a grid
+ * whose single row of 64-sample x-blocks needs more gives PML_PIC_E_INVALID_ARG (no grid
+ * within the limits of pml_pic_params does).  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  The sums may differ from pml_pic_field_error's in the
+ * order of the FP64 additions.  Synchronises both streams. */
+int pml_pic_field_error_noalloc(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den);
+
 /* Number of sample positions per field component: nn[d] = cells + 1 along each
  * in-plane axis, 1 along the invariant axis; n_samples = nn0 * nn1 * nn2. */
 int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples);

@@ -30,7 +30,7 @@ EXPORTED = [
     "pml_pic_batch_set_launch", "pml_pic_batch_step", "pml_pic_batch_last_error",
     "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
     "pml_pic_backward", "pml_pic_set_conductor", "pml_pic_set_source", "pml_pic_slab_moments",
-    "pml_pic_field_error", "pml_pic_sort_particles",
+    "pml_pic_field_error", "pml_pic_field_error_noalloc", "pml_pic_sort_particles",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
@@ -108,6 +108,7 @@ def load_library():
             "pml_pic_set_source": (C.c_int, [vp, i64, dp, dp, dp, i32]),
             "pml_pic_slab_moments": (C.c_int, [vp, i32, i32, dp, dp]),
             "pml_pic_field_error": (C.c_int, [vp, vp, dp, dp]),
+            "pml_pic_field_error_noalloc": (C.c_int, [vp, vp, dp, dp]),
             "pml_pic_sort_particles": (C.c_int, [vp, P(C.c_int32), P(C.c_uint32), i64, P(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
@@ -268,10 +269,13 @@ class PmlPic:
         num, den = self.field_error_sums(ref)
         return num / den if den > 0 else num
 
-    def field_error_sums(self, ref):
-        """(sum (F - F_ref)^2, sum F_ref^2) of Eq. (error)."""
+    def field_error_sums(self, ref, noalloc=False):
+        """(sum (F - F_ref)^2, sum F_ref^2) of Eq. (error); noalloc: through
+        pml_pic_field_error_noalloc (partials in the library's static device scratch)."""
         num, den = C.c_double(), C.c_double()
-        self._check(load_library().pml_pic_field_error(self._h, ref._h, C.byref(num), C.byref(den)))
+        L = load_library()
+        f = L.pml_pic_field_error_noalloc if noalloc else L.pml_pic_field_error
+        self._check(f(self._h, ref._h, C.byref(num), C.byref(den)))
         return num.value, den.value
 
     def slab_moments(self, axis, edges) -> np.ndarray:

@@ -1626,6 +1626,32 @@ static int pml_pic_field_error_impl(pml_pic_handle *h, pml_pic_handle *ref, doub
   return PML_PIC_OK;
 }
 
+// The same reduction with its partial sums in the library's static device scratch (no
+// workspace, no allocation of any kind on the device).
+static int pml_pic_field_error_noalloc_impl(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
+  const int rc = field_error_check(h, ref, num, den);
+  if (rc) return rc;
+  double *sc = nullptr;
+  HIPCHK(h, field_error_scratch(&sc));
+  HIPCHK(h, hipStreamSynchronize(ref->stream));
+  const bool ok = h->p.precision == 64
+                      ? launch_field_error_scratch<double>(h->grid<double>(), h->fields<double>(), ref->grid<double>(),
+                                                           ref->fields<double>(), sc, h->stream)
+                      : launch_field_error_scratch<float>(h->grid<float>(), h->fields<float>(), ref->grid<float>(),
+                                                          ref->fields<float>(), sc, h->stream);
+  if (!ok)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG,
+                "grid too wide for the static scratch of pml_pic_field_error_noalloc (" +
+                    std::to_string(field_error_scratch_pairs()) + " partial sums)");
+  HIPCHK(h, hipGetLastError());
+  double r[2];
+  HIPCHK(h, hipMemcpyAsync(r, sc, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *num = r[0];
+  *den = r[1];
+  return PML_PIC_OK;
+}
+
 static int pml_pic_diagnose_impl(pml_pic_handle *h, pml_pic_diag *out) {
   if (!h || !out) return PML_PIC_E_INVALID_ARG;
   return h->p.precision == 64 ? diagnose_t<double>(h, out) : diagnose_t<float>(h, out);
@@ -2073,6 +2099,10 @@ int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, 
 
 int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
   return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_field_error_impl(h, ref, num, den); });
+}
+
+int pml_pic_field_error_noalloc(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_field_error_noalloc_impl(h, ref, num, den); });
 }
 
 int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out) {

@@ -295,6 +295,15 @@ void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, Sor
 template <typename T>
 void launch_field_error(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr, const Fields<T> &R, double *partial,
                         double *out, hipStream_t s);
+// The same sums with the partials and the result in the file-scope device array of
+// diag.hip (no workspace): field_error_scratch gives its device address on the current
+// device; the launch returns false (launching nothing) when the grid needs more partial
+// pairs per row of x-blocks than the array holds (field_error_scratch_pairs()).
+hipError_t field_error_scratch(double **ptr);
+int field_error_scratch_pairs();
+template <typename T>
+bool launch_field_error_scratch(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr, const Fields<T> &R,
+                                double *sc, hipStream_t s);
 struct DiagWork {
   double *rho;           // nelem
   const double *rho_static;

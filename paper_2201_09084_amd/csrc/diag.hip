@@ -7,6 +7,9 @@
 //     div E = rho hold from t = 0);
 //   * live particle count and a non-finite flag.
 // Deterministic two-pass reductions: per-block partials, then one block.
+#include <algorithm>
+#include <mutex>
+
 #include "common.h"
 
 namespace pmlpic {
@@ -218,32 +221,37 @@ void launch_diag(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCt
 // Eq. (error) of Sec. III against a reference run: partial[2*b] = sum over the samples of
 // g's physical box of (F - F_ref)^2, partial[2*b + 1] = sum of F_ref^2 (E and B, the six
 // totals).  The reference grid has the same cell size and low PML and covers g's physical
-// box, so a sample has the same index in both.  Then one block sums the partials.
+// box, so a sample has the same index in both.  Workgroup (bx, by, bz) covers x-block bx
+// and the (y-block, plane) pairs by + m gridDim.y, bz + n gridDim.z (one pair when the
+// grid spans every block); then one block sums the partials.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(RB) k_field_error(Grid<T> g, Fields<T> F, Grid<T> gr, Fields<T> R,
                                                     double *partial) {
   __shared__ double sh[RB];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  const int kmax = DIM == 3 ? g.M[2] : 0;
   double num = 0.0, den = 0.0;
-  if (i <= g.M[0] && j <= g.M[1]) {
-    const long q = g.at(i, j, k), qr = gr.at(i, j, k);
-    const int id[3] = {i, j, k};
+  for (int k = (DIM == 3) ? (int)blockIdx.z : 0; k <= kmax; k += (int)gridDim.z) {
+    for (int jb = (int)blockIdx.y; jb * (int)blockDim.y <= g.M[1]; jb += (int)gridDim.y) {
+      const int j = jb * (int)blockDim.y + (int)threadIdx.y;
+      if (i > g.M[0] || j > g.M[1]) continue;
+      const long q = g.at(i, j, k), qr = gr.at(i, j, k);
+      const int id[3] = {i, j, k};
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const int a = c % 3;
-      bool phys = true;
+      for (int c = 0; c < 6; ++c) {
+        const int a = c % 3;
+        bool phys = true;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const bool stag = (c < 3) ? (d == a) : (d != a);
-        phys = phys && in_box(g, id[d] + (stag ? 0.5 : 0.0), d);
+        for (int d = 0; d < DIM; ++d) {
+          const bool stag = (c < 3) ? (d == a) : (d != a);
+          phys = phys && in_box(g, id[d] + (stag ? 0.5 : 0.0), d);
+        }
+        if (!phys) continue;
+        const double v = (double)(c < 3 ? F.E[a] : F.B[a])[q];
+        const double r = (double)(c < 3 ? R.E[a] : R.B[a])[qr];
+        num += (v - r) * (v - r);
+        den += r * r;
       }
-      if (!phys) continue;
-      const double v = (double)(c < 3 ? F.E[a] : F.B[a])[q];
-      const double r = (double)(c < 3 ? R.E[a] : R.B[a])[qr];
-      num += (v - r) * (v - r);
-      den += r * r;
     }
   }
   const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -261,6 +269,7 @@ __global__ void __launch_bounds__(RB) k_sum_pairs(const double *partial, int nb,
   if (threadIdx.x == 0) { out[0] = a; out[1] = c; }
 }
 
+// one workgroup per (x-block, y-block, plane), partial pairs in the handle's workspace
 template <typename T>
 void launch_field_error(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr, const Fields<T> &R, double *partial,
                         double *out, hipStream_t s) {
@@ -269,6 +278,65 @@ void launch_field_error(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr,
   else hipLaunchKernelGGL((k_field_error<T, 3>), grd, blk, 0, s, g, F, gr, R, partial);
   hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RB), 0, s, partial, (int)(grd.x * grd.y * grd.z), out);
 }
+
+// ------------------------------------------------ Eq. (error) without allocation
+// For callers that cannot allocate (code under HIP graph capture, tight serving loops):
+// the partial sums and the result live in this file-scope device array instead of the
+// handle's workspace.  Every GPU the library runs on holds one copy (513 KiB) until the
+// process ends; every call on that GPU shares it, so calls that overlap on one GPU
+// race.  Nothing in it needs to start at zero: each call writes every partial it reads.
+constexpr int FE_SCRATCH_PAIRS = 32768;                 // partial (num, den) pairs
+constexpr int FE_SCRATCH_RESULT = 64;                   // doubles before the partials
+static __device__ __align__(256) double scratch[FE_SCRATCH_RESULT + 2 * FE_SCRATCH_PAIRS];
+
+namespace {
+constexpr int FE_MAX_DEVICES = 64;
+double *g_scratch_ptr[FE_MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per device (in
+// host code the array's name is only a stand-in for that address).
+hipError_t field_error_scratch(double **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= FE_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+int field_error_scratch_pairs() { return FE_SCRATCH_PAIRS; }
+
+// The same sums with at most FE_SCRATCH_PAIRS workgroups (each covers several y-blocks
+// and planes when the grid is larger), partials and result in `sc` (the device address
+// of `scratch`); returns false, launching nothing, if one row of x-blocks alone needs
+// more workgroups than that (no grid within the library's size limits does).
+template <typename T>
+bool launch_field_error_scratch(const Grid<T> &g, const Fields<T> &F, const Grid<T> &gr, const Fields<T> &R,
+                                double *sc, hipStream_t s) {
+  const long gx = (g.M[0] + 1 + 63) / 64, gy = (g.M[1] + 1 + 3) / 4, gz = g.dim == 3 ? g.M[2] + 1 : 1;
+  if (gx > FE_SCRATCH_PAIRS) return false;
+  long cy = std::min<long>(gy, FE_SCRATCH_PAIRS / gx);
+  long cz = std::min<long>(gz, FE_SCRATCH_PAIRS / (gx * cy));
+  dim3 blk(64, 4, 1), grd((unsigned)gx, (unsigned)cy, (unsigned)cz);
+  double *partial = sc + FE_SCRATCH_RESULT;
+  if (g.dim == 2) hipLaunchKernelGGL((k_field_error<T, 2>), grd, blk, 0, s, g, F, gr, R, partial);
+  else hipLaunchKernelGGL((k_field_error<T, 3>), grd, blk, 0, s, g, F, gr, R, partial);
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RB), 0, s, partial, (int)(gx * cy * cz), sc);
+  return true;
+}
+template bool launch_field_error_scratch<float>(const Grid<float> &, const Fields<float> &, const Grid<float> &,
+                                                const Fields<float> &, double *, hipStream_t);
+template bool launch_field_error_scratch<double>(const Grid<double> &, const Fields<double> &, const Grid<double> &,
+                                                 const Fields<double> &, double *, hipStream_t);
 template void launch_field_error<float>(const Grid<float> &, const Fields<float> &, const Grid<float> &,
                                         const Fields<float> &, double *, double *, hipStream_t);
 template void launch_field_error<double>(const Grid<double> &, const Fields<double> &, const Grid<double> &,
