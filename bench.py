@@ -1,15 +1,18 @@
 """Benchmark of the damped-current PML PIC step on one MI355X.
 
-Default workload: 2D 1024x1024 cells + 16-cell PML on all sides (cubic profile),
-1,048,576 electrons in a Gaussian beam (rms 20 cells, gamma in [1.5, 10], 0-30 deg
-toward +x), quadratic shape, FP32 fields and particles, c dt = 0.7; every step runs
+Default workload (the headline configuration): 3D 256^3 cells + 12-cell PML on every face
+(cubic profile), linear shape, c dt = 0.5, FP32 fields and particles; 16,777,216 thermal
+background electrons (1 per physical cell, T = 1e-3 m c^2) plus a gamma = 5 beam of 65,536
+electrons in a radius-8 cylinder moving along +z, whose head fills the +z PML from step 0, so
+every timed step deposits alpha-damped current in that layer (Sec. II.A).  Every step runs
 sort_particles (every 8 steps), gather_push + deposit_current, the alpha damping and
 update_yee_pml.  Inputs are seeded synthetic data, resident in HBM before timing.
 
-Prints one JSON line: particle-pushes/s over the timed steps (whole job), the cell
-update rate, the roofline of the dominant kernel (algorithmic bytes / its average
-duration from HIP events on the library's stream) and the FP64 CPU oracle timed on a
-bounded sample on the host.
+Prints one JSON line: particle-pushes/s over the timed steps (whole job), the cell update
+rate, the roofline of the dominant kernel (algorithmic bytes / its average duration from HIP
+events on the library's stream) and of the whole step, the same steps on the plain FP64 GPU
+path, and the FP64 CPU oracle timed on a bounded sample on the host (all cores, and one
+thread).
 """
 import argparse
 import hashlib
@@ -69,6 +72,28 @@ def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
     if phase == "filter_current":   # J r+w
         return cells * 6 * esz
     return None
+
+
+def step_bytes(cfg, pushes_per_step, occupied_cells, esz):
+    """Algorithmic HBM bytes of one whole step (FP32 per-unit figures scaled by esz/4):
+    72 B per interior cell-update, 144 B (3D) / 112 B (2D) per PML cell-update, +24 B per
+    cell holding particles (the gather's field read), 52 B (2D) / 60 B (3D) per push."""
+    k = esz / 4.0
+    cells, pml = cfg.total_cells(), cfg.pml_cells()
+    per_pml = 144 if cfg.dim == 3 else 112
+    per_push = 60 if cfg.dim == 3 else 52
+    return k * ((cells - pml) * 72 + pml * per_pml + occupied_cells * 24 + pushes_per_step * per_push)
+
+
+def occupied_cells(cfg, parts):
+    """Cells holding at least one particle at the start (host count)."""
+    import numpy as np
+    M = [cfg.n[d] + cfg.pml[d][0] + cfg.pml[d][1] for d in range(cfg.dim)]
+    idx = np.zeros(len(parts), dtype=np.int64)
+    for d in reversed(range(cfg.dim)):
+        c = np.floor(parts.x[:, d] / cfg.dx[d]).astype(np.int64) + cfg.pml[d][0]
+        idx = idx * M[d] + c
+    return int(np.unique(idx).size)
 
 
 def run_gpu(args, cfg, parts, setup=None):
@@ -168,10 +193,10 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(cfg, parts, n_steps, cells=None):
+def cpu_baseline(cfg, parts, n_steps, cells=None, parallel=False):
     import oracle
     oracle.build_library(force=False)
-    o = oracle.OracleSim(cfg.replace(precision=64))
+    o = oracle.OracleSim(cfg.replace(precision=64), parallel=parallel)
     if cells is not None:
         o.set_conductor(cells)
     o.add_particles(parts.x, parts.u, parts.w)
@@ -201,7 +226,10 @@ def main():
                     help="timed steps (default: 2000 beam2d, 100 beam3d, 600 batch, 300 sp3d, 200 cavity)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default 10; cavity: 150, so that the beam fills the box)")
-    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch", "sp3d", "cavity"], default="beam2d")
+    ap.add_argument("--workload", choices=["beam2d", "beam3d", "batch", "sp3d", "cavity"], default="beam3d")
+    ap.add_argument("--input", choices=["straddle", "centre"], default="straddle",
+                    help="beams: straddling the PML face they move toward from step 0 (default), or at the box centre")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU comparison run")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -234,16 +262,20 @@ def main():
         args.warmup = 150 if args.workload == "cavity" else 10
     if args.workload == "batch":
         return run_batch(args)
+    straddle = args.input == "straddle"
     if args.workload == "beam2d":
         cfg = W.beam2d_config(precision=args.precision)
-        parts = W.beam2d_particles(cfg)
+        parts = W.beam2d_particles(cfg, straddle=straddle)
         wl = {"workload": "beam2d", "grid": "1024x1024+16pml", "particles": len(parts),
-              "shape_order": 2, "steps_total": args.warmup + args.steps}
+              "shape_order": 2, "steps_total": args.warmup + args.steps,
+              "input": "Gaussian beam centred on the +x PML interface" if straddle else "beam at the box centre"}
     elif args.workload == "beam3d":
         cfg = W.beam3d_config(precision=args.precision)
-        parts = W.beam3d_particles(cfg)
+        parts = W.beam3d_particles(cfg, straddle=straddle)
         wl = {"workload": "beam3d", "grid": "256^3+12pml", "particles": len(parts),
-              "shape_order": 1, "steps_total": args.warmup + args.steps}
+              "shape_order": 1, "steps_total": args.warmup + args.steps,
+              "input": ("thermal background 1/cell + gamma-5 beam whose head fills the +z PML"
+                        if straddle else "thermal background 1/cell + gamma-5 beam at the box centre")}
     elif args.workload == "cavity":   # the beam through the cavity of Sec. IV.A / App. A.2
         cfg = W.cavity_config(precision=args.precision)
         parts = W.cavity_beam(cfg)
@@ -289,8 +321,59 @@ def main():
                           "of the same inputs through the same warm-up and %d timed steps" % n_prof}
         roof["traffic"] = traffic_bytes(args.workload, name, args.precision)
 
+    srf = None
+    if not per_cell and args.workload in ("beam2d", "beam3d"):
+        occ = occupied_cells(cfg, parts)
+        sb = step_bytes(cfg, pushes / args.steps, occ, esz)
+        ach = sb / (ms_per_step * 1e-3) / 1e9
+        srf = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": int(sb),
+               "occupied_cells": occ,
+               "model": "72 B/interior cell, %d B/PML cell, 24 B/occupied cell, %d B/push (x%d for FP64)"
+                        % (144 if cfg.dim == 3 else 112, 60 if cfg.dim == 3 else 52, esz // 4)}
+
+    fp64 = None
+    if not args.no_fp64 and args.precision == 32 and args.workload in ("beam2d", "beam3d"):
+        import torch
+        from paper_2201_09084_amd import binding as B
+        cfg64 = cfg.replace(precision=64)
+        sim = B.PmlPic(cfg64, max_particles=len(parts))
+        sim.add_particles(parts.x, parts.u, parts.w)
+        if args.warmup:
+            sim.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t0
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        fp64 = {"ms_per_step": 1e3 * e64 / args.steps, "speedup_fp32_over_fp64": e64 / elapsed,
+                "accuracy": "FP32 within relative L2 1e-5 per field component of the FP64 oracle on this "
+                            "workload's parity cases (tests/test_gpu_fullsize.py); FP64 within 1e-10"}
+        print("bench: plain FP64 GPU path %.3f ms/step" % fp64["ms_per_step"], file=sys.stderr, flush=True)
+
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "beam3d":
+        import oracle
+        # bounded sample: the same workload on the 128^3 + 12 sub-box (same densities, the
+        # beam's head in the +z layer), one step with all cores; one thread on 64^3 + 12
+        sub = W.beam3d_config(precision=64, n=128)
+        sp = W.beam3d_particles(sub, n_beam=32768, straddle=straddle)
+        v, secs = cpu_baseline(sub, sp, 1, parallel=True)
+        sub1 = W.beam3d_config(precision=64, n=64)
+        sp1 = W.beam3d_particles(sub1, n_beam=8192, straddle=straddle)
+        v1, secs1 = cpu_baseline(sub1, sp1, 1, parallel=False)
+        cpu = {"value": v, "unit": "particle-pushes/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": ("1 step of the same workload on the 128^3 + 12-cell sub-box (same densities: "
+                          "%d particles, beam head in the +z PML), FP64 C oracle built with OpenMP over "
+                          "cell loops and particles (per-thread current buffers), %d threads, %.1f s"
+                          % (len(sp), oracle.num_threads(), secs)),
+               "single_thread": {"value": v1, "cores": 1,
+                                 "sample": "1 step on the 64^3 + 12-cell sub-box (%d particles), plain "
+                                           "single-threaded oracle, %.1f s" % (len(sp1), secs1)}}
+    elif not args.no_cpu_baseline:
         n_cpu = 2 if per_cell else args.cpu_steps
         sample_parts = parts
         if args.workload == "cavity":
@@ -326,6 +409,8 @@ def main():
         "gauss_residual_fp64": d1["gauss_max"],
         "particles_left": d1["n_particles"],
         "roofline": roof,
+        "step_roofline": srf,
+        "fp64_gpu": fp64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

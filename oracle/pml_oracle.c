@@ -8,7 +8,11 @@
  * The oracle is deliberately plain: absolute FP64 grid coordinates for particles,
  * all twelve split field parts stored everywhere (in the interior both parts of a
  * component are undamped, so only their sum matters), direct loops, no blocking or
- * fusion, compiled with -O2 -ffp-contract=off.
+ * fusion, compiled with -O2 -ffp-contract=off.  A second build of the same file with
+ * -fopenmp (liboracle_omp.so) spreads the cell loops and the particle loop over the host's
+ * cores, each thread depositing into its own current buffer, summed in thread order (a
+ * fixed order for a given thread count); without -fopenmp the pragmas are ignored and the
+ * particle loop below is the plain serial one.
  *
  * What it computes, and where each part comes from (Lehe et al., "Absorption of
  * charged particles in Perfectly-Matched-Layers by optimal damping of the deposited
@@ -37,6 +41,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "pml_oracle.h"
 
 #define NPART 12
@@ -270,6 +277,7 @@ void orc_destroy(orc_sim *s)
     for (int a = 0; a < 3; ++a) free(s->J[a]);
     free(s->rho_static); free(s->X); free(s->U); free(s->W); free(s->LAM); free(s->id);
     free(s->cond); free(s->SX); free(s->SU); free(s->SW); free(s->sstep); free(s->sid);
+    free(s->Jt);
     free(s);
 }
 
@@ -577,6 +585,7 @@ void orc_filter_current(orc_sim *s)
         for (int a = 0; a < 3; ++a) {
             int nv[3];
             for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(a, d));
+            #pragma omp parallel for collapse(2) schedule(static)
             for (int k = 0; k < nv[2]; ++k)
             for (int j = 0; j < nv[1]; ++j)
             for (int i = 0; i < nv[0]; ++i) {
@@ -667,6 +676,7 @@ static void advance(orc_sim *s, int is_e, double tau)
             double *Fp = s->F[2 * c_self + side];
             int nv[3];
             for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(c_self, d));
+            #pragma omp parallel for collapse(2) schedule(static)
             for (int k = 0; k < nv[2]; ++k)
             for (int j = 0; j < nv[1]; ++j)
             for (int i = 0; i < nv[0]; ++i) {
@@ -711,6 +721,7 @@ static void damp_current(orc_sim *s)
     for (int a = 0; a < 3; ++a) {
         int nv[3];
         for (int d = 0; d < 3; ++d) nv[d] = nvalid(s, d, stag_of(a, d));
+        #pragma omp parallel for collapse(2) schedule(static)
         for (int k = 0; k < nv[2]; ++k)
         for (int j = 0; j < nv[1]; ++j)
         for (int i = 0; i < nv[0]; ++i) {
@@ -813,41 +824,101 @@ static void inject(orc_sim *s)
  *  2. J <- alpha J (Eq. alpha / mode), after the binomial filter when it is on;
  *  3. B += dt/2 from E^n; E += dt from B^{n+1/2} and alpha J; B += dt/2 from E^{n+1};
  *     after each of the three, samples inside conductor cells are set to zero. */
-void orc_step(orc_sim *s, int nsteps)
+/* Particle t of step 1 below: gather, push, move to X1, deposit into J; updates u in
+ * place and returns the new Lambda in *lam; returns 1 if it ends outside the PEC box. */
+static int move_one(orc_sim *s, long t, double qdt_2m, double X1[3], double *lam, double *const J[3])
 {
     int dim = s->p.dim;
+    double *X = &s->X[3 * t], *u = &s->U[3 * t];
+    if (s->p.push) {
+        double EB[6];
+        orc_gather(s, X, EB);
+        orc_boris(qdt_2m, EB, EB + 3, u);
+    }
+    double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (int d = 0; d < 3; ++d) X1[d] = X[d];
+    for (int d = 0; d < dim; ++d) X1[d] = X[d] + s->p.dt * u[d] / gam / s->p.dx[d];
+    double qw = s->p.charge * s->W[t];
+    *lam = s->LAM[t];
+    if (s->p.alpha_mode == 3) {
+        /* weight damped by Lambda at mid-step (the time of the deposited current) */
+        double Xh[3] = {X[0], X[1], X[2]};
+        for (int d = 0; d < dim; ++d) Xh[d] = 0.5 * (X[d] + X1[d]);
+        qw *= exp(-(*lam + path_sigma(s, X, Xh, 0.5 * s->p.dt)));
+        *lam += path_sigma(s, X, X1, s->p.dt);
+    }
+    orc_deposit(s, X, X1, u[2] / gam, qw, J);
+    int out = 0;
+    for (int d = 0; d < dim; ++d) if (X1[d] < 0.0 || X1[d] >= (double)s->M[d]) out = 1;
+    return out;
+}
+
+#ifdef _OPENMP
+/* Step 1 over all cores: particles split statically over the threads, each depositing
+ * into its own current buffer; the buffers are summed sample by sample in thread order;
+ * then the survivors are compacted in their order. */
+static void move_all_threads(orc_sim *s, double qdt_2m)
+{
+    int nthr = omp_get_max_threads();
+    size_t ns = s->nsamp;
+    if (s->nthr != nthr) {
+        free(s->Jt);
+        s->Jt = (double *)malloc(sizeof(double) * 3 * ns * (size_t)nthr);
+        s->nthr = nthr;
+    }
+    long np = s->np;
+    double *Xn = (double *)malloc(sizeof(double) * 3 * (np + 1));
+    double *Ln = (double *)malloc(sizeof(double) * (np + 1));
+    char *gone = (char *)malloc((size_t)np + 1);
+    #pragma omp parallel num_threads(nthr)
+    {
+        int th = omp_get_thread_num();
+        double *Jt[3];
+        for (int a = 0; a < 3; ++a) {
+            Jt[a] = s->Jt + ((size_t)th * 3 + a) * ns;
+            memset(Jt[a], 0, sizeof(double) * ns);
+        }
+        #pragma omp for schedule(static)
+        for (long t = 0; t < np; ++t) gone[t] = (char)move_one(s, t, qdt_2m, &Xn[3 * t], &Ln[t], Jt);
+        #pragma omp for schedule(static)
+        for (long q = 0; q < (long)ns; ++q)
+            for (int a = 0; a < 3; ++a) {
+                double acc = s->J[a][q];
+                for (int u = 0; u < nthr; ++u) acc += s->Jt[((size_t)u * 3 + a) * ns + q];
+                s->J[a][q] = acc;
+            }
+    }
+    long keep = 0;
+    for (long t = 0; t < np; ++t) {
+        if (gone[t]) continue;
+        for (int d = 0; d < 3; ++d) { s->X[3 * keep + d] = Xn[3 * t + d]; s->U[3 * keep + d] = s->U[3 * t + d]; }
+        s->W[keep] = s->W[t]; s->LAM[keep] = Ln[t]; s->id[keep] = s->id[t];
+        ++keep;
+    }
+    s->np = keep;
+    free(Xn); free(Ln); free(gone);
+}
+#endif
+
+void orc_step(orc_sim *s, int nsteps)
+{
     double qdt_2m = s->p.charge * s->p.dt / (2.0 * s->p.mass);
     for (int it = 0; it < nsteps; ++it) {
         inject(s);
         orc_zero_current(s);
+#ifdef _OPENMP
+        move_all_threads(s, qdt_2m);
+#else
         long keep = 0;
         for (long t = 0; t < s->np; ++t) {
-            double *X = &s->X[3 * t], *u = &s->U[3 * t];
-            if (s->p.push) {
-                double EB[6];
-                orc_gather(s, X, EB);
-                orc_boris(qdt_2m, EB, EB + 3, u);
-            }
-            double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            double X1[3] = {X[0], X[1], X[2]};
-            for (int d = 0; d < dim; ++d) X1[d] = X[d] + s->p.dt * u[d] / gam / s->p.dx[d];
-            double qw = s->p.charge * s->W[t], lam = s->LAM[t];
-            if (s->p.alpha_mode == 3) {
-                /* weight damped by Lambda at mid-step (the time of the deposited current) */
-                double Xh[3] = {X[0], X[1], X[2]};
-                for (int d = 0; d < dim; ++d) Xh[d] = 0.5 * (X[d] + X1[d]);
-                qw *= exp(-(lam + path_sigma(s, X, Xh, 0.5 * s->p.dt)));
-                lam += path_sigma(s, X, X1, s->p.dt);
-            }
-            orc_deposit(s, X, X1, u[2] / gam, qw, s->J);
-            int out = 0;
-            for (int d = 0; d < dim; ++d) if (X1[d] < 0.0 || X1[d] >= (double)s->M[d]) out = 1;
-            if (out) continue;
-            for (int d = 0; d < 3; ++d) { s->X[3 * keep + d] = X1[d]; s->U[3 * keep + d] = u[d]; }
+            double X1[3], lam;
+            if (move_one(s, t, qdt_2m, X1, &lam, s->J)) continue;
+            for (int d = 0; d < 3; ++d) { s->X[3 * keep + d] = X1[d]; s->U[3 * keep + d] = s->U[3 * t + d]; }
             s->W[keep] = s->W[t]; s->LAM[keep] = lam; s->id[keep] = s->id[t];
             ++keep;
         }
         s->np = keep;
+#endif
         if (s->p.filter_passes > 0) orc_filter_current(s);
         damp_current(s);
         advance(s, 0, 0.5 * s->p.dt);

@@ -44,6 +44,8 @@ typedef struct {
     long nsrc, src_next;     /* beam source: entries sorted by injection step */
     double *SX, *SU, *SW;    /* grid coordinates at injection, u, w */
     long *sstep, *sid;
+    double *Jt;              /* all-cores build: per-thread current buffers (3 nsamp each) */
+    int nthr;                /* threads they were allocated for */
 } orc_sim;
 
 double orc_shape(int order, double d);

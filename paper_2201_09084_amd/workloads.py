@@ -200,15 +200,25 @@ def beam2d_config(precision: int = 32, n: int = 1024, pml: int = 16) -> SimConfi
 
 
 def beam2d_particles(cfg: SimConfig, n_particles: int = 1 << 20, sigma: float = 20.0,
-                     seed: int = 1002, w: float = 1e-4) -> Particles:
+                     seed: int = 1002, w: float = 1e-4, straddle: bool = False) -> Particles:
     """Gaussian beam (rms `sigma` cells) at the box centre; gamma uniform in [1.5, 10];
-    direction uniform in [0, 30] degrees from +x toward +y."""
+    direction uniform in [0, 30] degrees from +x toward +y.  straddle: the same beam centred
+    on the +x interface (x = n_x), so that from step 0 about half of it lies in the +x PML;
+    positions drawn beyond one cell before the outer wall are drawn again (the Gaussian
+    truncated there)."""
     rng = np.random.default_rng(seed)
-    cx, cy = cfg.n[0] / 2.0, cfg.n[1] / 2.0
+    cx, cy = (cfg.n[0] if straddle else cfg.n[0] / 2.0), cfg.n[1] / 2.0
     x = np.empty((n_particles, 2))
     x[:, 0] = rng.normal(cx, sigma, n_particles)
     x[:, 1] = rng.normal(cy, sigma, n_particles)
-    x[:, 0] = np.clip(x[:, 0], 1.0, cfg.n[0] - 1.0)
+    if straddle:
+        xmax = cfg.n[0] + cfg.pml[0][1] - 1.0
+        bad = x[:, 0] > xmax
+        while bad.any():
+            x[bad, 0] = rng.normal(cx, sigma, int(bad.sum()))
+            bad = x[:, 0] > xmax
+    else:
+        x[:, 0] = np.clip(x[:, 0], 1.0, cfg.n[0] - 1.0)
     x[:, 1] = np.clip(x[:, 1], 1.0, cfg.n[1] - 1.0)
     gamma = rng.uniform(1.5, 10.0, n_particles)
     theta = np.radians(rng.uniform(0.0, 30.0, n_particles))
@@ -224,11 +234,13 @@ def beam3d_config(precision: int = 32, n: int = 256, pml: int = 12) -> SimConfig
 
 
 def beam3d_particles(cfg: SimConfig, seed: int = 1004, background_ppc: float = 1.0,
-                     n_beam: int = 65536, temperature: float = 1e-3) -> Particles:
+                     n_beam: int = 65536, temperature: float = 1e-3, straddle: bool = False) -> Particles:
     """Thermal background at `background_ppc` particles per cell (uniform positions,
     u ~ N(0, sqrt(T)) per component, w = 0.01) plus a beam of gamma = 5 electrons
     moving along +z in a cylinder of radius 8 cells around the x-y centre,
-    z in [n/4, 3n/4], w = 0.04."""
+    z in [n/4, 3n/4], w = 0.04.  straddle: the beam cylinder (same length n/2 - 2 cells)
+    ends two cells before the outer wall of the +z PML, so that from step 0 its head
+    fills the +z layer and keeps feeding it for about 2 n/2 steps."""
     rng = np.random.default_rng(seed)
     n = cfg.n
     nb = int(round(background_ppc * n[0] * n[1] * n[2]))
@@ -236,8 +248,13 @@ def beam3d_particles(cfg: SimConfig, seed: int = 1004, background_ppc: float = 1
     ub = rng.normal(0.0, math.sqrt(temperature), (nb, 3))
     r = 8.0 * np.sqrt(rng.uniform(0.0, 1.0, n_beam))
     ph = rng.uniform(0.0, 2 * math.pi, n_beam)
+    if straddle:
+        z1 = n[2] + cfg.pml[2][1] - 2.0
+        z0 = z1 - (n[2] / 2 - 2.0)
+    else:
+        z0, z1 = n[2] / 4, 3 * n[2] / 4
     xe = np.stack([n[0] / 2 + r * np.cos(ph), n[1] / 2 + r * np.sin(ph),
-                   rng.uniform(n[2] / 4, 3 * n[2] / 4, n_beam)], axis=1)
+                   rng.uniform(z0, z1, n_beam)], axis=1)
     g = 5.0
     ue = np.zeros((n_beam, 3))
     ue[:, 2] = math.sqrt(g * g - 1.0)

@@ -14,12 +14,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def both(cfg, particles=None, fields=None, max_particles=None, flags=0, X_ids=None):
-    """Creates a GPU simulation and an oracle with the same configuration and inputs."""
+def both(cfg, particles=None, fields=None, max_particles=None, flags=0, X_ids=None, parallel=False):
+    """Creates a GPU simulation and an oracle with the same configuration and inputs
+    (parallel: the oracle's all-cores build, for the largest cases)."""
     n = len(particles) if particles is not None else 0
     cap = max_particles if max_particles is not None else max(n, 1)
     g = B.PmlPic(cfg, max_particles=cap, flags=flags)
-    o = oracle.OracleSim(cfg)
+    o = oracle.OracleSim(cfg, parallel=parallel)
     if fields is not None:
         g.set_split_fields(fields)
         o.set_split_fields(fields)

@@ -114,3 +114,32 @@ def test_batch_rejects_mixed_shapes():
     cfgs = [runs[0][0], runs[1][0].replace(shape_order=2)]
     with pytest.raises(B.PmlPicError):
         B.PmlPicBatch(cfgs)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_batch_large_runs_thick_layers_against_oracle(precision):
+    """Workload 3's own sizes: runs of 256-512 cells with layers of 8-32 cells (the draw of the
+    benchmark's batch), each particle crossing the +x interface after 40 steps, stepped 70
+    steps (30 of them with the particle in the layer or gone through the wall) in one batch
+    replayed as a graph, against the FP64 oracle: FP64 1e-10, FP32 relative L2 1e-5 per
+    component."""
+    runs = W.batch_runs(5, seed=21, steps_to_cross=40, nmin=256, nmax=512)
+    cfgs = [r.cfg.replace(precision=precision) for r in runs]
+    say("runs", [(c.n[0], c.pml[0][0]) for c in cfgs])
+    assert max(c.pml[0][0] for c in cfgs) >= 20
+    b = B.PmlPicBatch(cfgs, particles_per_run=1, use_graph=True)
+    for k, r in enumerate(runs):
+        b.runs[k].add_particles(r.particles.x, r.particles.u, r.particles.w)
+    b.step(70)
+    b.synchronize()
+    for k, r in enumerate(runs):
+        cfg64 = cfgs[k].replace(precision=64)
+        o = oracle.OracleSim(cfg64, parallel=True)
+        o.add_particles(r.particles.x, r.particles.u, r.particles.w)
+        o.step(70)
+        if precision == 64:
+            compare_fields(b.runs[k], o, cfg64, 1e-10, "batch run %d" % k)
+            compare_particles(b.runs[k], o, 1e-10, 1e-10, "batch run %d" % k)
+        else:
+            worst = compare_fields(b.runs[k], o, cfg64, 1e-5, "batch fp32 run %d" % k, l2=True)
+            say("run", k, "fp32 worst rel L2 %.3e" % worst)
