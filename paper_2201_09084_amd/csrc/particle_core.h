@@ -339,12 +339,12 @@ __device__ __forceinline__ void path_lambda(const Grid<T> &g, const int (&i0)[3]
   }
 }
 
-// charge times weight of a particle for the deposit of the move (i0, f0) -> (i1, f1);
+// charge times weight w of particle p for the deposit of the move (i0, f0) -> (i1, f1);
 // with weight damping also updates its Lambda
 template <typename T, int DIM>
-__device__ __forceinline__ T deposit_charge(const Grid<T> &g, const Parts<T> &P, int p, const int (&i0)[3],
-                                            const T (&f0)[3], const int (&i1)[3], const T (&f1)[3]) {
-  T qw = g.charge * P.w[p];
+__device__ __forceinline__ T deposit_charge_w(const Grid<T> &g, const Parts<T> &P, int p, T w, const int (&i0)[3],
+                                              const T (&f0)[3], const int (&i1)[3], const T (&f1)[3]) {
+  T qw = g.charge * w;
   if (g.wdamp) {
     T half, full;
     path_lambda<T, DIM>(g, i0, f0, i1, f1, half, full);
@@ -353,6 +353,11 @@ __device__ __forceinline__ T deposit_charge(const Grid<T> &g, const Parts<T> &P,
     P.lam[p] = lam + full;
   }
   return qw;
+}
+template <typename T, int DIM>
+__device__ __forceinline__ T deposit_charge(const Grid<T> &g, const Parts<T> &P, int p, const int (&i0)[3],
+                                            const T (&f0)[3], const int (&i1)[3], const T (&f1)[3]) {
+  return deposit_charge_w<T, DIM>(g, P, p, P.w[p], i0, f0, i1, f1);
 }
 
 // Nodes along one axis that a deposit moving from cell i0 to cell i1 can touch

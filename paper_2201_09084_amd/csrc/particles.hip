@@ -700,7 +700,12 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int dim, Parts<T> src, Par
   dst.id[q] = src.id[p];
 }
 
-__global__ void k_copy_count(const int32_t *src, int32_t *dst) { *dst = *src; }
+// the live count after the sort: to the step's counter and after the last key start (the
+// end of the last tile's range, which later injections past the count do not move)
+__global__ void k_copy_count(const int32_t *src, int32_t *dst, uint32_t *key_end) {
+  *dst = *src;
+  *key_end = (uint32_t)*src;
+}
 
 template <typename T>
 void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, SortWork sw,
@@ -717,7 +722,7 @@ void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, Sor
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, sw.blocksums, nb, new_count);
   hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, sw.counts, sw.nkeys, sw.blocksums);
   hipLaunchKernelGGL((k_sort_scatter<T>), grd, blk, 0, s, g.dim, src, dst, sw, ctl.count, n_slots);
-  hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, new_count, ctl.count);
+  hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, new_count, ctl.count, sw.counts + sw.nkeys);
 }
 
 template <typename T>

@@ -1,0 +1,286 @@
+// gather_push + deposit_current for 3D runs with the linear shape, by sort tile, in eight
+// colour passes.
+//
+// The step is the one of particles.hip (gather of the total fields, Eq. MaxwellSum;
+// relativistic Boris; move; Esirkepov's charge-conserving current, used in App. A).  What
+// differs is how the current reaches global memory.  One workgroup takes one sort tile
+// (tile[0] x tile[1] x tile[2] cells) and all of its particles, accumulates their current in
+// an LDS box of the nodes (tile + 3 per axis) that particles in the tile or one cell beyond
+// it can reach, and adds the box to J with plain loads and stores.  Tiles are coloured by
+// the parity of their tile coordinates: two tiles of one colour are two tiles apart along
+// some axis, so their boxes never overlap, and one launch per colour needs no atomics at all
+// (the tile flush was the part of the step that ran at the global-atomic ceiling).  A
+// particle whose move leaves that one-cell margin (it drifted since the last sort) is written
+// to an outlier list and deposited after the eight passes with global atomics.
+#include "particle_core.h"
+
+namespace pmlpic {
+
+constexpr int P3_TPB = 256;
+constexpr int P3_NODES = 1344;   // LDS nodes per current component (FP64): 11^3 for 8^3 tiles
+constexpr int P3_QCAP = 128;     // moves that cross a cell face, queued per workgroup
+
+// Esirkepov's current of a linear-shape move that stays in its cell along every axis: J_a
+// is non-zero only on the half node of that cell along a, times the four nodes of the cell
+// across; with d = f1_a - f0_a and the two shapes S0 = (1 - f0, f0), S1 = (1 - f1, f1) on
+// the cell's two nodes along the transverse axes b, c,
+//   J_a = qw jcoef_a d [S0_b (2 S0_c + S1_c) + S1_b (S0_c + 2 S1_c)] / 6,
+// which is Esirkepov's W_a = dS_a (S0_b S0_c / 3 + S1_b S0_c / 6 + S0_b S1_c / 6 + S1_b S1_c / 3)
+// on the two-node window (twelve values instead of the 3 x 9 x 2 of the general window).
+template <typename T>
+__device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double *box, int q0, const int (&st)[3],
+                                                       int total, const T (&f0)[3], const T (&f1)[3], T qw) {
+#pragma unroll
+  for (int A = 0; A < 3; ++A) {
+    const int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
+    const T d = f1[A] - f0[A];
+    if (d == T(0)) continue;
+    const T coef = qw * g.jcoef[A] * d * T(1.0 / 6.0);
+    const T b0[2] = {T(1) - f0[Bx], f0[Bx]}, b1[2] = {T(1) - f1[Bx], f1[Bx]};
+    const T c0[2] = {T(1) - f0[Cx], f0[Cx]}, c1[2] = {T(1) - f1[Cx], f1[Cx]};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const T u = T(2) * c0[c] + c1[c], v = c0[c] + T(2) * c1[c];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const T val = coef * (b0[b] * u + b1[b] * v);
+        atomicAdd(&box[A * total + q0 + b * st[Bx] + c * st[Cx]], (double)val);
+      }
+    }
+  }
+}
+
+// One colour pass: workgroup b takes tile number b of colour `color` (tile coordinates of
+// parity (color & 1, color >> 1 & 1, color >> 2) along x, y, z), nc[] tiles of that colour
+// per axis.
+template <typename T>
+__global__ void __launch_bounds__(P3_TPB) k_push3d_color(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
+                                                         Outliers<T> O, int push, int color, int ncx, int ncy,
+                                                         long jstride) {
+  __shared__ double box[3 * P3_NODES];
+  __shared__ unsigned int n_pushed;
+  // Moves that cross a cell face take the general Esirkepov window; a few percent of the
+  // thermal particles do, so almost every wavefront would run both forms side by side.
+  // They are queued here and deposited together after the loop (beyond the capacity, in
+  // place).
+  __shared__ int q_n;
+  __shared__ uint32_t q_c0[P3_QCAP], q_c1[P3_QCAP];
+  __shared__ T q_f0[3][P3_QCAP], q_f1[3][P3_QCAP], q_qw[P3_QCAP];
+  const int tid = threadIdx.x;
+  const int b = (int)blockIdx.x;
+  const int tc[3] = {2 * (b % ncx) + (color & 1), 2 * ((b / ncx) % ncy) + ((color >> 1) & 1),
+                     2 * (b / (ncx * ncy)) + ((color >> 2) & 1)};
+  const int t = (tc[2] * tw.ntile[1] + tc[1]) * tw.ntile[0] + tc[0];
+  // the tile's range at the last sort (key_start[n_keys] is the sorted count; particles
+  // injected since then form an unsorted tail pushed by another kernel)
+  const uint32_t s = tw.key_start[(size_t)t * tw.tilecells];
+  const uint32_t e = tw.key_start[(size_t)(t + 1) * tw.tilecells];
+  if (s >= e) return;   // uniform: an empty tile
+  // cells [T0, T0 + tile) of the tile; particles in [T0 - 1, T0 + tile] at both ends of their
+  // move deposit into the box of nodes [T0 - 1, T0 + tile + 1]
+  int T0[3], ext[3], st[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T0[d] = tc[d] * tw.tile[d];
+    ext[d] = tw.tile[d] + 3;
+  }
+  st[0] = 1;
+  st[1] = ext[0];
+  st[2] = ext[0] * ext[1];
+  const int total = st[2] * ext[2];
+  // the first particle's state is requested before the box is cleared, the next one's
+  // before the current one is processed: its memory round trip overlaps the gather's
+  struct PState {
+    uint32_t c;
+    T f[3], u[3], w;
+  };
+  auto load = [&](uint32_t p, PState &q) {
+    q.c = P.cell[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { q.f[d] = P.f[d][p]; q.u[d] = P.u[d][p]; }
+    q.w = P.w[p];
+  };
+  PState cur;
+  uint32_t p = s + (uint32_t)tid;
+  if (p < e) load(p, cur);
+  for (int q = tid; q < 3 * total; q += P3_TPB) box[q] = 0.0;
+  if (tid == 0) { n_pushed = 0u; q_n = 0; }
+  __syncthreads();
+  LdsSink<T> lsink;
+  lsink.lds = box;
+  lsink.e0 = ext[0];
+  lsink.e01 = st[2];
+  lsink.total = total;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lsink.lo[d] = T0[d] - 1;
+  unsigned int my_pushes = 0u;
+  for (; p < e; p += P3_TPB) {
+    PState nxt;
+    if (p + P3_TPB < e) load(p + P3_TPB, nxt);
+    const uint32_t c = cur.c;
+    if (c == DEAD) { cur = nxt; continue; }
+    ++my_pushes;
+    int id[3];
+    unpack_cell(3, c, id[0], id[1], id[2]);
+    T f[3] = {cur.f[0], cur.f[1], cur.f[2]};
+    T u[3] = {cur.u[0], cur.u[1], cur.u[2]};
+    if (push) {
+      T EB[6];
+      gather<T, 3, 1>(g, F, id, f, EB);
+      boris(g.qdt_2m, EB, u);
+    }
+    const int id0[3] = {id[0], id[1], id[2]};
+    const T f0[3] = {f[0], f[1], f[2]};
+    T ig;
+    const bool inside = move<T, 3>(g, id, f, u, ig);
+    P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
+    P.f[0][p] = f[0]; P.f[1][p] = f[1]; P.f[2][p] = f[2];
+    const T qw = deposit_charge_w<T, 3>(g, P, p, cur.w, id0, f0, id, f);
+    cur = nxt;
+    bool inbox = true, incell = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int lo = T0[d] - 1, hi = T0[d] + tw.tile[d];
+      inbox = inbox && id0[d] >= lo && id0[d] <= hi && id[d] >= lo && id[d] <= hi;
+      incell = incell && id[d] == id0[d];
+    }
+    if (inbox && incell) {
+      const int q0 = (id0[0] - lsink.lo[0]) + (id0[1] - lsink.lo[1]) * st[1] + (id0[2] - lsink.lo[2]) * st[2];
+      deposit_incell_linear3<T>(g, box, q0, st, total, f0, f, qw);
+    }
+    const bool cross = inbox && !incell;
+    const unsigned long long mq = __ballot(cross);
+    if (cross) {
+      const int lane = tid & 63;
+      const int leader = __ffsll((long long)mq) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&q_n, __popcll(mq));
+      base = __shfl(base, leader);
+      const int k = base + __popcll(mq & ((1ull << lane) - 1ull));
+      if (k < P3_QCAP) {
+        q_c0[k] = c;
+        q_c1[k] = pack_cell(3, id[0], id[1], id[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { q_f0[d][k] = f0[d]; q_f1[d][k] = f[d]; }
+        q_qw[k] = qw;
+      } else {
+        deposit<T, 3, 1>(g, lsink, id0, f0, id, f, T(0), qw);
+      }
+    }
+    // outliers: one slot block per wavefront that has any
+    const unsigned long long m = __ballot(!inbox);
+    if (!inbox) {
+      const int lane = tid & 63;
+      const int leader = __ffsll((long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(O.count, __popcll(m));
+      base = __shfl(base, leader);
+      const int k = base + __popcll(m & ((1ull << lane) - 1ull));
+      O.cell0[k] = c;
+      O.cell1[k] = pack_cell(3, id[0], id[1], id[2]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) { O.f0[d][k] = f0[d]; O.f1[d][k] = f[d]; }
+      O.qw[k] = qw;
+    }
+    P.cell[p] = inside ? pack_cell(3, id[0], id[1], id[2]) : DEAD;
+  }
+  __syncthreads();
+  {   // the queued moves across cell faces
+    const int nq = min(q_n, P3_QCAP);
+    for (int k = tid; k < nq; k += P3_TPB) {
+      int i0[3], i1[3];
+      unpack_cell(3, q_c0[k], i0[0], i0[1], i0[2]);
+      unpack_cell(3, q_c1[k], i1[0], i1[1], i1[2]);
+      const T f0[3] = {q_f0[0][k], q_f0[1][k], q_f0[2][k]};
+      const T f1[3] = {q_f1[0][k], q_f1[1][k], q_f1[2][k]};
+      deposit<T, 3, 1>(g, lsink, i0, f0, i1, f1, T(0), q_qw[k]);
+    }
+  }
+  // push tally: wavefront sums, then one atomic per workgroup
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) my_pushes += __shfl_xor(my_pushes, off);
+  if ((tid & 63) == 0 && my_pushes) atomicAdd(&n_pushed, my_pushes);
+  __syncthreads();
+  if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
+  // flush: this colour's boxes are disjoint, so plain read-modify-write.  All of a thread's
+  // loads are issued before its first store (one memory round trip, not one per entry);
+  // entry q = ((comp ext2 + k) ext1 + j) ext0 + i, divided by multiply-shift (q < 2^12).
+  __syncthreads();
+  const uint32_t m0 = (1u << 20) / (uint32_t)ext[0] + 1u, m1 = (1u << 20) / (uint32_t)ext[1] + 1u,
+                 m2 = (1u << 20) / (uint32_t)ext[2] + 1u;
+  constexpr int FB = 8;   // entries per thread per batch (3 * P3_NODES fits in two batches)
+  for (int q0 = 0; q0 < 3 * total; q0 += FB * P3_TPB) {
+    long addr[FB];
+    double val[FB];
+    T cur[FB];
+#pragma unroll
+    for (int n = 0; n < FB; ++n) {
+      const uint32_t q = (uint32_t)(q0 + tid + n * P3_TPB);
+      val[n] = q < (uint32_t)(3 * total) ? box[q] : 0.0;
+      const uint32_t r1 = (q * m0) >> 20, i = q - r1 * (uint32_t)ext[0];
+      const uint32_t r2 = (r1 * m1) >> 20, j = r1 - r2 * (uint32_t)ext[1];
+      const uint32_t comp = (r2 * m2) >> 20, k = r2 - comp * (uint32_t)ext[2];
+      // J_comp = J_0 + comp jstride (the three arrays of one workspace)
+      addr[n] = (long)comp * jstride + g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k);
+    }
+    auto *J = gptr(F.J[0]);
+#pragma unroll
+    for (int n = 0; n < FB; ++n)
+      if (val[n] != 0.0) cur[n] = J[addr[n]];
+#pragma unroll
+    for (int n = 0; n < FB; ++n)
+      if (val[n] != 0.0) J[addr[n]] = cur[n] + (T)val[n];
+  }
+}
+
+// the outliers' moves, with global atomics, after the colour passes
+template <typename T>
+__global__ void __launch_bounds__(256) k_outlier_deposit(Grid<T> g, Fields<T> F, Outliers<T> O) {
+  const int n = *O.count;
+  GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+  for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < n; k += (int)(gridDim.x * blockDim.x)) {
+    int i0[3], i1[3];
+    unpack_cell(3, O.cell0[k], i0[0], i0[1], i0[2]);
+    unpack_cell(3, O.cell1[k], i1[0], i1[1], i1[2]);
+    const T f0[3] = {O.f0[0][k], O.f0[1][k], O.f0[2][k]};
+    const T f1[3] = {O.f1[0][k], O.f1[1][k], O.f1[2][k]};
+    deposit<T, 3, 1>(g, gsink, i0, f0, i1, f1, T(0), O.qw[k]);
+  }
+}
+
+__global__ void k_zero_count(int32_t *c) { *c = 0; }
+
+bool push3d_applies(int dim, int order, const int tile[3]) {
+  if (dim != 3 || order != 1) return false;
+  long vol = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (tile[d] < 3) return false;
+    vol *= tile[d] + 3;
+  }
+  return vol <= P3_NODES;
+}
+
+template <typename T>
+void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
+                   const Outliers<T> &O, int push, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, O.count);
+  // the flush addresses J_c as J_0 + c jstride: the three current arrays of a run (or of the
+  // filter's scratch copy) are laid out evenly spaced in the workspace
+  const long jstride = (long)(F.J[1] - F.J[0]);
+  for (int color = 0; color < 8; ++color) {
+    int nc[3];
+    for (int d = 0; d < 3; ++d) nc[d] = (tw.ntile[d] - ((color >> d) & 1) + 1) / 2;
+    const long nb = (long)nc[0] * nc[1] * nc[2];
+    if (nb <= 0) continue;
+    hipLaunchKernelGGL((k_push3d_color<T>), dim3((unsigned)nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, O, push, color,
+                       nc[0], nc[1], jstride);
+  }
+  hipLaunchKernelGGL((k_outlier_deposit<T>), dim3(256), dim3(256), 0, s, g, F, O);
+}
+
+template void launch_push3d<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &, StepCtl,
+                                   const TileWork &, const Outliers<float> &, int, hipStream_t);
+template void launch_push3d<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &, StepCtl,
+                                    const TileWork &, const Outliers<double> &, int, hipStream_t);
+
+}  // namespace pmlpic
