@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmlpic.so")
-SOURCES = ["api.hip", "fields.hip", "particles.hip", "push3d.hip", "diag.hip", "batch.hip", "adjoint.hip",
+SOURCES = ["api.hip", "fields.hip", "particles.hip", "push3d.hip", "fused3d.hip", "diag.hip", "batch.hip", "adjoint.hip",
            "beam.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -237,8 +237,11 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   for (int a = 0; a < 15; ++a) L.off_field[a] = take(L.esz * (size_t)L.nelem);
-  // the one-pass 2D field update reads one set of arrays and writes the other
-  L.has_alt = p.dim == 2 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS);
+  // the one-pass field update reads one set of arrays and writes the other; in 3D it
+  // covers the Yee solver without current filter, conductors or adjoint storage
+  const bool one3 = p.dim == 3 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS) && p.solver == PML_PIC_SOLVER_YEE &&
+                    p.filter_passes == 0 && !p.conductor && p.adjoint_segment == 0;
+  L.has_alt = (p.dim == 2 && !(p.flags & PML_PIC_FLAG_SEPARATE_FIELDS)) || one3;
   if (p.filter_passes > 0) L.off_jtmp = take(3 * L.esz * (size_t)L.nelem);
   if (L.has_alt) {
     for (int a = 0; a < 12; ++a) L.off_alt[a] = take(L.esz * (size_t)L.nelem);
@@ -820,7 +823,13 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     const int ph = h->jphase % 3;
     int *slot_cur = jslot + 4 * JSLOTS * ph;                 // this step's boxes
     JClear<T> jc{{nullptr, nullptr, nullptr}, nullptr, nullptr};
-    if (one_pass) {
+    JZero<T> jz{{nullptr, nullptr, nullptr}};
+    if (one_pass && h->p.dim == 3) {   // deposit into this step's buffer, the field pass clears the other
+      for (int a = 0; a < 3; ++a) {
+        F.J[a] = h->jbuf<T>(h->fset, a);
+        jz.J[a] = h->jbuf<T>(1 - h->fset, a);
+      }
+    } else if (one_pass) {
       ctl.jslot = slot_cur;
       for (int a = 0; a < 3; ++a) {
         F.J[a] = h->jbuf<T>(h->fset, a);        // deposited this step
@@ -837,7 +846,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       pt.end(s, PML_PIC_PHASE_SORT);
     }
     const bool tiled = fused && use_sort && ns > 0;
-    if (one_pass && !tiled) {   // the tiled deposit clears the other buffer itself
+    if (one_pass && h->p.dim == 2 && !tiled) {   // the tiled deposit clears the other buffer itself
       pt.begin(s);
       launch_jbox_clear<T>(g, jc, s);
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
@@ -879,8 +888,11 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     if (one_pass) {
       pt.begin(s);
-      launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), slot_cur,
-                             !sep_damp && current_alpha(amode), s);
+      if (h->p.dim == 3)
+        launch_fused_fields_3d<T>(g, F, h->fields_set<T>(1 - h->fset), jz, !sep_damp && current_alpha(amode), s);
+      else
+        launch_fused_fields<T>(g, F, h->fields_set<T>(1 - h->fset), slot_cur,
+                               !sep_damp && current_alpha(amode), s);
       pt.end(s, PML_PIC_PHASE_UPDATE_FIELDS);
       h->fset = 1 - h->fset;
       h->jphase++;

@@ -355,6 +355,17 @@ template <typename T>
 void launch_fused_fields(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const int *jslot, bool fuse_alpha,
                          hipStream_t s);
 
+// update_yee_pml in one pass over 3D fields (fused3d.hip): reads F (and its J, not
+// cleared), writes the new E, B (and split parts) to D, and clears the other current
+// buffer jz (read by the previous step) over the samples it owns
+template <typename T>
+struct JZero {
+  T *J[3];
+};
+template <typename T>
+void launch_fused_fields_3d(const Grid<T> &g, const Fields<T> &F, const Fields<T> &D, const JZero<T> &jz,
+                            bool fuse_alpha, hipStream_t s);
+
 template <typename T>
 struct AdjFields {
   T *LT[6];
