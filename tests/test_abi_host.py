@@ -121,9 +121,12 @@ def test_ck_solver_and_filter_validation(lib):
     assert _size(cfg2, solver=1)[0] == -1                 # 2D
     assert _size(cfg2, filter_passes=1)[0] == -1          # 2D
     assert _size(cfg3, dt=0.5, filter_passes=5)[0] == -1
-    rc0, n0 = _size(cfg3, dt=0.5)
-    rc1, n1 = _size(cfg3, dt=0.5, filter_passes=1)
+    sep = B.FLAG_SEPARATE_FIELDS
+    rc0, n0 = _size(cfg3, dt=0.5, flags=sep)
+    rc1, n1 = _size(cfg3, dt=0.5, filter_passes=1, flags=sep)
     assert rc0 == 0 and rc1 == 0 and n1 > n0              # the filter's scratch copy of J
+    rc2, n2 = _size(cfg3, dt=0.5)                         # the one-pass update's second field set
+    assert rc2 == 0 and n2 > n0
 
 
 def test_beam_transport_validation(lib):
