@@ -36,8 +36,7 @@ struct Layout {
   size_t off_tab = 0;
   size_t off_cell[2] = {}, off_f[2][3] = {}, off_u[2][3] = {}, off_w[2] = {}, off_lam[2] = {}, off_id[2] = {};
   size_t off_oldcell = 0, off_oldf[3] = {};
-  bool colour_push = false;                 // 3D linear shape: colour-pass push (push3d.hip)
-  size_t off_ocell0 = 0, off_ocell1 = 0, off_of0[3] = {}, off_of1[3] = {}, off_oqw = 0, off_ocount = 0;
+  bool tile_push3 = false;                  // 3D linear shape: push by sort tile (push3d.hip)
   size_t off_count = 0, off_pushes = 0;
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
   int ntiles = 1;
@@ -259,16 +258,7 @@ void make_layout(const pml_pic_params &p, Layout &L) {
   }
   L.off_oldcell = take(4 * cap);
   for (int d = 0; d < 3; ++d) L.off_oldf[d] = d < p.dim ? take(L.esz * cap) : 0;
-  // outlier list of the colour-pass push: at most every live particle in one step
-  L.colour_push = !(p.flags & (PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_NO_SORT)) && push3d_applies(p.dim, p.shape_order, L.tile);
-  if (L.colour_push) {
-    L.off_ocell0 = take(4 * cap);
-    L.off_ocell1 = take(4 * cap);
-    for (int d = 0; d < 3; ++d) L.off_of0[d] = take(L.esz * cap);
-    for (int d = 0; d < 3; ++d) L.off_of1[d] = take(L.esz * cap);
-    L.off_oqw = take(L.esz * cap);
-    L.off_ocount = take(8);
-  }
+  L.tile_push3 = !(p.flags & (PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_NO_SORT)) && push3d_applies(p.dim, p.shape_order, L.tile);
   L.off_count = take(8);
   L.off_pushes = take(8 * N_PUSH_COUNTERS);
   L.off_counts = take(4 * ((size_t)L.nkeys + 1));
@@ -435,15 +425,6 @@ struct pml_pic_handle {
     P.cell = at<uint32_t>(L.off_oldcell);
     for (int d = 0; d < 3; ++d) P.f[d] = d < p.dim ? at<T>(L.off_oldf[d]) : nullptr;
     return P;
-  }
-  template <typename T> Outliers<T> outliers() const {
-    Outliers<T> O;
-    O.cell0 = at<uint32_t>(L.off_ocell0);
-    O.cell1 = at<uint32_t>(L.off_ocell1);
-    for (int d = 0; d < 3; ++d) { O.f0[d] = at<T>(L.off_of0[d]); O.f1[d] = at<T>(L.off_of1[d]); }
-    O.qw = at<T>(L.off_oqw);
-    O.count = at<int32_t>(L.off_ocount);
-    return O;
   }
   StepCtl ctl() const {
     StepCtl c;
@@ -774,7 +755,7 @@ void sort_now(pml_pic_handle *h, const StepCtl &ctl, int ns) {
   hipStream_t s = h->stream;
   const bool fused = !(h->p.flags & PML_PIC_FLAG_UNFUSED);
   launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
-  if (fused && h->p.dim == 3 && !h->L.colour_push) launch_tile_chunks(h->tilework(), ctl.count, s);
+  if (fused && h->p.dim == 3 && !h->L.tile_push3) launch_tile_chunks(h->tilework(), ctl.count, s);
   if (fused && h->p.dim == 2)
     launch_range_items(h->tilework(), h->parts<T>(1 - h->cur).cell, ctl.count, h->p.shape_order,
                        (int)h->L.max_ranges, std::min(h->sort_interval - 1, 2), s);
@@ -857,8 +838,8 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     const Parts<T> P = h->parts<T>(h->cur);
     pt.begin(s);
-    if (fused && use_sort && h->L.colour_push) {
-      launch_push3d<T>(g, F, P, ctl, h->tilework(), h->outliers<T>(), h->p.push, s);
+    if (fused && use_sort && h->L.tile_push3) {
+      launch_push3d<T>(g, F, P, ctl, h->tilework(), h->p.push, s);
       if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
     } else if (fused && use_sort) {
       launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);

@@ -278,22 +278,13 @@ template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                     StepCtl ctl, int n_slots, hipStream_t s);
 
-// 3D linear-shape runs (push3d.hip): gather_push + deposit_current by sort tile in eight
-// colour passes whose tile boxes are disjoint (no atomics), then the moves that left their
-// tile's one-cell margin (the outliers, listed here during the passes) with global atomics.
-template <typename T>
-struct Outliers {
-  uint32_t *cell0, *cell1;   // packed cells before and after the move
-  T *f0[3], *f1[3];          // offsets before and after
-  T *qw;                     // charge times (damped) weight of the move
-  int32_t *count;
-};
-// whether the colour passes apply: 3D, linear shape, a tile box (tile + 3 nodes per axis)
-// that fits in LDS, tiles of at least three cells (same-colour boxes are then disjoint)
+// 3D linear-shape runs (push3d.hip): gather_push + deposit_current, one workgroup per sort
+// tile, its current summed in an LDS box of the tile's nodes (tile + 3 per axis) and added to
+// J with global atomics.  Applies to tiles of at least three cells whose box fits in LDS.
 bool push3d_applies(int dim, int order, const int tile[3]);
 template <typename T>
-void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
-                   const Outliers<T> &O, int push, hipStream_t s);
+void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw, int push,
+                   hipStream_t s);
 
 struct SortWork {
   uint32_t *counts;      // nkeys + 1

@@ -1,17 +1,16 @@
-// gather_push + deposit_current for 3D runs with the linear shape, by sort tile, in eight
-// colour passes.
+// gather_push + deposit_current for 3D runs with the linear shape, one workgroup per sort
+// tile.
 //
 // The step is the one of particles.hip (gather of the total fields, Eq. MaxwellSum;
-// relativistic Boris; move; Esirkepov's charge-conserving current, used in App. A).  What
-// differs is how the current reaches global memory.  One workgroup takes one sort tile
-// (tile[0] x tile[1] x tile[2] cells) and all of its particles, accumulates their current in
-// an LDS box of the nodes (tile + 3 per axis) that particles in the tile or one cell beyond
-// it can reach, and adds the box to J with plain loads and stores.  Tiles are coloured by
-// the parity of their tile coordinates: two tiles of one colour are two tiles apart along
-// some axis, so their boxes never overlap, and one launch per colour needs no atomics at all
-// (the tile flush was the part of the step that ran at the global-atomic ceiling).  A
-// particle whose move leaves that one-cell margin (it drifted since the last sort) is written
-// to an outlier list and deposited after the eight passes with global atomics.
+// relativistic Boris; move; Esirkepov's charge-conserving current, used in App. A).  One
+// workgroup takes one sort tile (tile[0] x tile[1] x tile[2] cells) and all of its
+// particles, accumulates their current in an LDS box of the nodes (tile + 3 per axis) that
+// particles in the tile or one cell beyond it can reach, and adds the box's non-zero entries
+// to J with global atomics.  A move that stays in its cell along every axis (the thermal
+// background: about 96%) takes a 12-value form of Esirkepov's current; moves across a cell
+// face are queued in LDS and deposited after the loop with the general window, so that
+// wavefronts do not run both forms side by side; a move that leaves the tile's one-cell
+// margin (a particle that drifted since the last sort) deposits straight to J.
 #include "particle_core.h"
 
 namespace pmlpic {
@@ -50,27 +49,24 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
   }
 }
 
-// One colour pass: workgroup b takes tile number b of colour `color` (tile coordinates of
-// parity (color & 1, color >> 1 & 1, color >> 2) along x, y, z), nc[] tiles of that colour
-// per axis.
+// Workgroup b takes sort tile b (tiles numbered x fastest: neighbouring workgroups share
+// the cache lines of their fields and currents).
 template <typename T>
-__global__ void __launch_bounds__(P3_TPB) k_push3d_color(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
-                                                         Outliers<T> O, int push, int color, int ncx, int ncy,
-                                                         long jstride) {
+__global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
+                                                         int push) {
   __shared__ double box[3 * P3_NODES];
   __shared__ unsigned int n_pushed;
-  // Moves that cross a cell face take the general Esirkepov window; a few percent of the
-  // thermal particles do, so almost every wavefront would run both forms side by side.
-  // They are queued here and deposited together after the loop (beyond the capacity, in
-  // place).
+  // Moves that cross a cell face (or leave the box: q_glob) take the general Esirkepov
+  // window; a few percent of the thermal particles do, so almost every wavefront would run
+  // both forms side by side.  They are queued here and deposited together after the loop
+  // (beyond the capacity, in place).
   __shared__ int q_n;
   __shared__ uint32_t q_c0[P3_QCAP], q_c1[P3_QCAP];
   __shared__ T q_f0[3][P3_QCAP], q_f1[3][P3_QCAP], q_qw[P3_QCAP];
+  __shared__ unsigned char q_glob[P3_QCAP];
   const int tid = threadIdx.x;
-  const int b = (int)blockIdx.x;
-  const int tc[3] = {2 * (b % ncx) + (color & 1), 2 * ((b / ncx) % ncy) + ((color >> 1) & 1),
-                     2 * (b / (ncx * ncy)) + ((color >> 2) & 1)};
-  const int t = (tc[2] * tw.ntile[1] + tc[1]) * tw.ntile[0] + tc[0];
+  const int t = (int)blockIdx.x;
+  const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
   // the tile's range at the last sort (key_start[n_keys] is the sorted count; particles
   // injected since then form an unsorted tail pushed by another kernel)
   const uint32_t s = tw.key_start[(size_t)t * tw.tilecells];
@@ -148,9 +144,9 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_color(Grid<T> g, Fields<T> F,
       const int q0 = (id0[0] - lsink.lo[0]) + (id0[1] - lsink.lo[1]) * st[1] + (id0[2] - lsink.lo[2]) * st[2];
       deposit_incell_linear3<T>(g, box, q0, st, total, f0, f, qw);
     }
-    const bool cross = inbox && !incell;
-    const unsigned long long mq = __ballot(cross);
-    if (cross) {
+    const bool queued = !(inbox && incell);
+    const unsigned long long mq = __ballot(queued);
+    if (queued) {
       const int lane = tid & 63;
       const int leader = __ffsll((long long)mq) - 1;
       int base = 0;
@@ -163,29 +159,18 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_color(Grid<T> g, Fields<T> F,
 #pragma unroll
         for (int d = 0; d < 3; ++d) { q_f0[d][k] = f0[d]; q_f1[d][k] = f[d]; }
         q_qw[k] = qw;
-      } else {
+        q_glob[k] = inbox ? 0 : 1;
+      } else if (inbox) {
         deposit<T, 3, 1>(g, lsink, id0, f0, id, f, T(0), qw);
+      } else {
+        GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+        deposit<T, 3, 1>(g, gsink, id0, f0, id, f, T(0), qw);
       }
-    }
-    // outliers: one slot block per wavefront that has any
-    const unsigned long long m = __ballot(!inbox);
-    if (!inbox) {
-      const int lane = tid & 63;
-      const int leader = __ffsll((long long)m) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(O.count, __popcll(m));
-      base = __shfl(base, leader);
-      const int k = base + __popcll(m & ((1ull << lane) - 1ull));
-      O.cell0[k] = c;
-      O.cell1[k] = pack_cell(3, id[0], id[1], id[2]);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) { O.f0[d][k] = f0[d]; O.f1[d][k] = f[d]; }
-      O.qw[k] = qw;
     }
     P.cell[p] = inside ? pack_cell(3, id[0], id[1], id[2]) : DEAD;
   }
   __syncthreads();
-  {   // the queued moves across cell faces
+  {   // the queued moves
     const int nq = min(q_n, P3_QCAP);
     for (int k = tid; k < nq; k += P3_TPB) {
       int i0[3], i1[3];
@@ -193,7 +178,12 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_color(Grid<T> g, Fields<T> F,
       unpack_cell(3, q_c1[k], i1[0], i1[1], i1[2]);
       const T f0[3] = {q_f0[0][k], q_f0[1][k], q_f0[2][k]};
       const T f1[3] = {q_f1[0][k], q_f1[1][k], q_f1[2][k]};
-      deposit<T, 3, 1>(g, lsink, i0, f0, i1, f1, T(0), q_qw[k]);
+      if (q_glob[k]) {
+        GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+        deposit<T, 3, 1>(g, gsink, i0, f0, i1, f1, T(0), q_qw[k]);
+      } else {
+        deposit<T, 3, 1>(g, lsink, i0, f0, i1, f1, T(0), q_qw[k]);
+      }
     }
   }
   // push tally: wavefront sums, then one atomic per workgroup
@@ -202,53 +192,20 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_color(Grid<T> g, Fields<T> F,
   if ((tid & 63) == 0 && my_pushes) atomicAdd(&n_pushed, my_pushes);
   __syncthreads();
   if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
-  // flush: this colour's boxes are disjoint, so plain read-modify-write.  All of a thread's
-  // loads are issued before its first store (one memory round trip, not one per entry);
-  // entry q = ((comp ext2 + k) ext1 + j) ext0 + i, divided by multiply-shift (q < 2^12).
-  __syncthreads();
+  // flush: every non-zero entry of the box to J with one global atomic add; entry
+  // q = ((comp ext2 + k) ext1 + j) ext0 + i, divided by multiply-shift (exact for q < 2^12)
   const uint32_t m0 = (1u << 20) / (uint32_t)ext[0] + 1u, m1 = (1u << 20) / (uint32_t)ext[1] + 1u,
                  m2 = (1u << 20) / (uint32_t)ext[2] + 1u;
-  constexpr int FB = 8;   // entries per thread per batch (3 * P3_NODES fits in two batches)
-  for (int q0 = 0; q0 < 3 * total; q0 += FB * P3_TPB) {
-    long addr[FB];
-    double val[FB];
-    T cur[FB];
-#pragma unroll
-    for (int n = 0; n < FB; ++n) {
-      const uint32_t q = (uint32_t)(q0 + tid + n * P3_TPB);
-      val[n] = q < (uint32_t)(3 * total) ? box[q] : 0.0;
-      const uint32_t r1 = (q * m0) >> 20, i = q - r1 * (uint32_t)ext[0];
-      const uint32_t r2 = (r1 * m1) >> 20, j = r1 - r2 * (uint32_t)ext[1];
-      const uint32_t comp = (r2 * m2) >> 20, k = r2 - comp * (uint32_t)ext[2];
-      // J_comp = J_0 + comp jstride (the three arrays of one workspace)
-      addr[n] = (long)comp * jstride + g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k);
-    }
-    auto *J = gptr(F.J[0]);
-#pragma unroll
-    for (int n = 0; n < FB; ++n)
-      if (val[n] != 0.0) cur[n] = J[addr[n]];
-#pragma unroll
-    for (int n = 0; n < FB; ++n)
-      if (val[n] != 0.0) J[addr[n]] = cur[n] + (T)val[n];
+  for (int q = tid; q < 3 * total; q += P3_TPB) {
+    const double v = box[q];
+    if (v == 0.0) continue;
+    const uint32_t uq = (uint32_t)q;
+    const uint32_t r1 = (uq * m0) >> 20, i = uq - r1 * (uint32_t)ext[0];
+    const uint32_t r2 = (r1 * m1) >> 20, j = r1 - r2 * (uint32_t)ext[1];
+    const uint32_t comp = (r2 * m2) >> 20, k = r2 - comp * (uint32_t)ext[2];
+    atomic_add(&F.J[comp][g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k)], (T)v);
   }
 }
-
-// the outliers' moves, with global atomics, after the colour passes
-template <typename T>
-__global__ void __launch_bounds__(256) k_outlier_deposit(Grid<T> g, Fields<T> F, Outliers<T> O) {
-  const int n = *O.count;
-  GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
-  for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < n; k += (int)(gridDim.x * blockDim.x)) {
-    int i0[3], i1[3];
-    unpack_cell(3, O.cell0[k], i0[0], i0[1], i0[2]);
-    unpack_cell(3, O.cell1[k], i1[0], i1[1], i1[2]);
-    const T f0[3] = {O.f0[0][k], O.f0[1][k], O.f0[2][k]};
-    const T f1[3] = {O.f1[0][k], O.f1[1][k], O.f1[2][k]};
-    deposit<T, 3, 1>(g, gsink, i0, f0, i1, f1, T(0), O.qw[k]);
-  }
-}
-
-__global__ void k_zero_count(int32_t *c) { *c = 0; }
 
 bool push3d_applies(int dim, int order, const int tile[3]) {
   if (dim != 3 || order != 1) return false;
@@ -261,26 +218,15 @@ bool push3d_applies(int dim, int order, const int tile[3]) {
 }
 
 template <typename T>
-void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
-                   const Outliers<T> &O, int push, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, O.count);
-  // the flush addresses J_c as J_0 + c jstride: the three current arrays of a run (or of the
-  // filter's scratch copy) are laid out evenly spaced in the workspace
-  const long jstride = (long)(F.J[1] - F.J[0]);
-  for (int color = 0; color < 8; ++color) {
-    int nc[3];
-    for (int d = 0; d < 3; ++d) nc[d] = (tw.ntile[d] - ((color >> d) & 1) + 1) / 2;
-    const long nb = (long)nc[0] * nc[1] * nc[2];
-    if (nb <= 0) continue;
-    hipLaunchKernelGGL((k_push3d_color<T>), dim3((unsigned)nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, O, push, color,
-                       nc[0], nc[1], jstride);
-  }
-  hipLaunchKernelGGL((k_outlier_deposit<T>), dim3(256), dim3(256), 0, s, g, F, O);
+void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw, int push,
+                   hipStream_t s) {
+  if (tw.ntiles <= 0) return;
+  hipLaunchKernelGGL((k_push3d_tiles<T>), dim3((unsigned)tw.ntiles), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
 }
 
 template void launch_push3d<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &, StepCtl,
-                                   const TileWork &, const Outliers<float> &, int, hipStream_t);
+                                   const TileWork &, int, hipStream_t);
 template void launch_push3d<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &, StepCtl,
-                                    const TileWork &, const Outliers<double> &, int, hipStream_t);
+                                    const TileWork &, int, hipStream_t);
 
 }  // namespace pmlpic
