@@ -50,8 +50,9 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
 }
 
 // Workgroup b takes sort tile b (tiles numbered x fastest: neighbouring workgroups share
-// the cache lines of their fields and currents).
-template <typename T>
+// the cache lines of their fields and currents).  TS > 0: cubic tiles of TS cells known at
+// compile time (the box strides become immediates); 0: the tile shape of tw.
+template <typename T, int TS>
 __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
                                                          int push) {
   __shared__ double box[3 * P3_NODES];
@@ -74,11 +75,12 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
   if (s >= e) return;   // uniform: an empty tile
   // cells [T0, T0 + tile) of the tile; particles in [T0 - 1, T0 + tile] at both ends of their
   // move deposit into the box of nodes [T0 - 1, T0 + tile + 1]
-  int T0[3], ext[3], st[3];
+  int T0[3], ext[3], st[3], tl[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    T0[d] = tc[d] * tw.tile[d];
-    ext[d] = tw.tile[d] + 3;
+    tl[d] = TS > 0 ? TS : tw.tile[d];
+    T0[d] = tc[d] * tl[d];
+    ext[d] = tl[d] + 3;
   }
   st[0] = 1;
   st[1] = ext[0];
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
     bool inbox = true, incell = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int lo = T0[d] - 1, hi = T0[d] + tw.tile[d];
+      const int lo = T0[d] - 1, hi = T0[d] + tl[d];
       inbox = inbox && id0[d] >= lo && id0[d] <= hi && id[d] >= lo && id[d] <= hi;
       incell = incell && id[d] == id0[d];
     }
@@ -221,7 +223,10 @@ template <typename T>
 void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw, int push,
                    hipStream_t s) {
   if (tw.ntiles <= 0) return;
-  hipLaunchKernelGGL((k_push3d_tiles<T>), dim3((unsigned)tw.ntiles), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+  if (tw.tile[0] == 8 && tw.tile[1] == 8 && tw.tile[2] == 8)
+    hipLaunchKernelGGL((k_push3d_tiles<T, 8>), dim3((unsigned)tw.ntiles), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+  else
+    hipLaunchKernelGGL((k_push3d_tiles<T, 0>), dim3((unsigned)tw.ntiles), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
 }
 
 template void launch_push3d<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &, StepCtl,
