@@ -31,8 +31,8 @@ def kernel_source_hash():
     """Hash of the kernel and launcher sources (the host control in api.hip launches them but
     does not change what one launch moves)."""
     h = hashlib.sha256()
-    for f in ("particles.hip", "fields.hip", "batch.hip", "beam.hip", "common.h", "field_core.h",
-              "fused2d.h", "particle_core.h"):
+    for f in ("particles.hip", "push3d.hip", "fields.hip", "fused3d.hip", "batch.hip", "beam.hip", "common.h",
+              "field_core.h", "fused2d.h", "particle_core.h"):
         with open(os.path.join(ROOT, "paper_2201_09084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -52,15 +52,17 @@ def traffic_bytes(workload, phase, precision):
     return t.get("bytes_per_launch", {}).get(key)
 
 
-def algorithmic_bytes(cfg, phase, pushes_per_launch, esz):
-    """Algorithmic HBM bytes of one launch of a phase (each array read/written once)."""
+def algorithmic_bytes(cfg, phase, pushes_per_launch, esz, occupied=0):
+    """Algorithmic HBM bytes of one launch of a phase (each array read/written once).  The
+    push launch also deposits: beside its particles it reads the six field components and
+    writes the three current components once per occupied cell."""
     dim = cfg.dim
     cells = cfg.total_cells()
     pml = cfg.pml_cells()
     nsplit_e = 1 if dim == 2 else 3
     if phase == "gather_push":
         per = (4 + dim * esz + 3 * esz + esz) + (4 + dim * esz + 3 * esz)   # read + write
-        return per * pushes_per_launch
+        return per * pushes_per_launch + occupied * (6 + 3) * esz
     if phase == "update_yee_pml_E":
         return cells * (3 + 3 + 3 + 3) * esz + pml * 2 * nsplit_e * esz     # E r+w, B r, J r
     if phase == "update_yee_pml_B":
@@ -311,7 +313,8 @@ def main():
     name, (ms_total, launches) = dom
     avg_s = ms_total / 1e3 / launches
     roof = None
-    per_launch = algorithmic_bytes(cfg, name, prof_pushes / max(1, phases.get("gather_push", (0, 1))[1]), esz)
+    occ = occupied_cells(cfg, parts) if not per_cell and args.workload in ("beam2d", "beam3d") else 0
+    per_launch = algorithmic_bytes(cfg, name, prof_pushes / max(1, phases.get("gather_push", (0, 1))[1]), esz, occ)
     if per_launch is not None:
         ach = per_launch / avg_s / 1e9
         roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -319,11 +322,13 @@ def main():
                 "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(per_launch),
                 "timing": "HIP events around each kernel phase on the library stream, in a second run "
                           "of the same inputs through the same warm-up and %d timed steps" % n_prof}
+        if name == "gather_push":
+            roof["model"] = "%d B/push + %d B/occupied cell (fields read, current written), %d occupied cells" % (
+                (60 if cfg.dim == 3 else 52) * esz // 4, 9 * esz, occ)
         roof["traffic"] = traffic_bytes(args.workload, name, args.precision)
 
     srf = None
     if not per_cell and args.workload in ("beam2d", "beam3d"):
-        occ = occupied_cells(cfg, parts)
         sb = step_bytes(cfg, pushes / args.steps, occ, esz)
         ach = sb / (ms_per_step * 1e-3) / 1e9
         srf = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
