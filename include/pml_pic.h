@@ -295,10 +295,16 @@ int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, cons
  * physical box) after n steps with respect to the PML profile parameters
  * theta = (sigma_coef[d][k] for d < dim, k < 16; then damping_scale; entries with
  * k >= n_sigma_coef are not part of the profile and get 0), by a hand-written
- * reverse-mode pass through update_yee_pml and the alpha damping.  Ballistic runs only
- * (push = 0): the particles' paths, and so the undamped current, do not depend on the
- * fields; alpha_mode must be PML_ALPHA_ONE or PML_ALPHA_DAMPED.  Needs
- * params.adjoint_segment > 0 and adjoint_checkpoints * adjoint_segment >= n_steps. */
+ * reverse-mode pass through the whole step: update_yee_pml and the alpha damping (Sec.
+ * II.A-II.C) and, with push = 1, gather_push and the Esirkepov deposit_current (the
+ * particles' response to the fields, and the fields' to the particles' paths).  With
+ * push = 0 the paths, and so the undamped current, do not depend on the fields.
+ * alpha_mode must be PML_ALPHA_ONE or PML_ALPHA_DAMPED; no current filter, conductors or
+ * beam source; pushed runs need every particle id below max_particles.  Needs
+ * params.adjoint_segment > 0 and adjoint_checkpoints * adjoint_segment >= n_steps.  The
+ * objective is a function of the final fields only; a particle leaving through the outer
+ * wall ends its path there, so U is piecewise smooth in theta and the gradient is that
+ * of the piece holding theta. */
 
 /* Runs n_steps from the current state, keeping the state every adjoint_segment steps
  * and the final state; writes U (FP64 reduction) to *U.  Synchronises. */
@@ -313,6 +319,14 @@ int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U);
  * The final state of the forward run is restored afterwards.  Synchronises. */
 int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out,
                      double *grad_theta, int32_t n_theta);
+
+/* After pml_pic_backward of a pushed run: the adjoint of the initial particle state, by
+ * particle id 0..n-1 (the order of pml_pic_add_particles): dU/dx (n x dim, per unit of
+ * the physical coordinates given to pml_pic_add_particles) and dU/du (n x 3, u = gamma v)
+ * of the seed's objective.  Ids of particles that were never live hold 0.  Host buffers,
+ * caller-owned.  PML_PIC_E_INVALID_ARG if the last reverse pass was not of a pushed run
+ * or n exceeds the particles added.  Synchronises. */
+int pml_pic_particle_adjoint(pml_pic_handle *h, int64_t n, double *dU_dx, double *dU_du);
 
 /* ------------------------------------------------------------------ batches
  * Many independent runs advanced together: each run has its own grid, PML, profile,

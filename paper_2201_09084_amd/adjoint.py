@@ -5,8 +5,9 @@ theta packs the parameters of the conductivity profile sigma/eps0 = sum_k a_{d,k
 alpha = exp(-s Phi) (Sec. II.C), in that order.  The objective is the field energy
 1/2 sum (E^2 + B^2) dV over the physical box after n steps (the energy norm of the
 error in Sec. III).  The forward pass keeps checkpoints on the GPU; the backward pass
-recomputes each segment and runs the transposed update (ballistic particles: their
-current does not depend on the fields or on theta).
+recomputes each segment and runs the transposed step: the field update and alpha damping,
+and with push = 1 also the gather, Boris push and Esirkepov deposit of every particle
+(with push = 0 the current does not depend on the fields or on theta).
 """
 import numpy as np
 import torch

@@ -31,6 +31,7 @@ EXPORTED = [
     "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
     "pml_pic_backward", "pml_pic_set_conductor", "pml_pic_set_source", "pml_pic_slab_moments",
     "pml_pic_field_error", "pml_pic_field_error_noalloc", "pml_pic_sort_particles",
+    "pml_pic_particle_adjoint",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
@@ -104,6 +105,7 @@ def load_library():
             "pml_pic_batch_destroy": (None, [vp]),
             "pml_pic_forward_ckpt": (C.c_int, [vp, i32, dp]),
             "pml_pic_backward": (C.c_int, [vp, dp, i64, dp, dp, i32]),
+            "pml_pic_particle_adjoint": (C.c_int, [vp, i64, dp, dp]),
             "pml_pic_set_conductor": (C.c_int, [vp, P(C.c_uint8)]),
             "pml_pic_set_source": (C.c_int, [vp, i64, dp, dp, dp, i32]),
             "pml_pic_slab_moments": (C.c_int, [vp, i32, i32, dp, dp]),
@@ -349,6 +351,15 @@ class PmlPic:
         self._check(L.pml_pic_backward(self._h, sp, sc, _dp(lam) if lam is not None else None, _dp(grad),
                                        n_theta))
         return grad, (lam.reshape((12,) + self._shape()) if lam is not None else None)
+
+    def particle_adjoint(self, n: int):
+        """After backward() of a pushed run: (dU/dx of shape (n, dim) in the physical
+        coordinates of add_particles, dU/du of shape (n, 3)) for particle ids 0..n-1."""
+        dim = int(self.params.dim)
+        gx = np.zeros(n * dim)
+        gu = np.zeros(n * 3)
+        self._check(load_library().pml_pic_particle_adjoint(self._h, int(n), _dp(gx), _dp(gu)))
+        return gx.reshape(n, dim), gu.reshape(n, 3)
 
     def diagnose(self, allow_nonfinite=False) -> dict:
         d = Diag()

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmlpic.so")
 SOURCES = ["api.hip", "fields.hip", "particles.hip", "push3d.hip", "fused3d.hip", "diag.hip", "batch.hip", "adjoint.hip",
-           "beam.hip"]
+           "adjoint_particles.hip", "beam.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = [

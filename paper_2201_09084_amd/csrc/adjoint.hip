@@ -1,7 +1,8 @@
-// Reverse mode of update_yee_pml and of the alpha damping (ballistic runs: the current
-// before damping does not depend on the fields).  The forward step is linear in the
-// state:  B' = eh B + ghk D(E) (half step), E' = e E + gk D(B') - g w alpha J, then
-// B'' from B' and E'.  Its transpose runs backwards with
+// Reverse mode of update_yee_pml and of the alpha damping.  For given current the field
+// update is linear in the state:  B' = eh B + ghk D(E) (half step),
+// E' = e E + gk D(B') - g w alpha J, then B'' from B' and E'.  (Pushed runs also reverse
+// the particles, adjoint_particles.hip, from the current's adjoint written here.)  Its
+// transpose runs backwards with
 //   * curl-transpose kernels: the adjoint of every neighbour difference, written as a
 //     gather over the samples that read a given sample (no atomics);
 //   * self kernels: lambda <- e lambda per split part, and the FP64 derivatives of the
@@ -259,10 +260,13 @@ __global__ void __launch_bounds__(256) k_adj_E_curl(Grid<T> g, AdjFields<T> L) {
 }
 
 // lambda_E <- (d E' / d E)^T lambda_E; gradients of e, g, g/dx, alpha and sigma (through
-// the split weights of the current); J is the undamped current of the step
+// the split weights of the current); J is the undamped current of the step.  With LJ0
+// set (pushed runs) also writes the adjoint of that current, dU/dJ = -(g alpha)^T lambda_E,
+// to LJ0..LJ2 (0 where E is not updated)
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_adj_E_self(Grid<T> g, AdjFields<T> L, Fields<T> Fe, const T *J0,
-                                                   const T *J1, const T *J2, int alpha_mode, double *Gacc) {
+                                                   const T *J1, const T *J2, int alpha_mode, double *Gacc,
+                                                   T *LJ0, T *LJ1, T *LJ2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = (DIM == 3) ? (int)blockIdx.z : 0;
@@ -275,9 +279,13 @@ __global__ void __launch_bounds__(256) k_adj_E_self(Grid<T> g, AdjFields<T> L, F
   if (i <= g.M[0] && j <= g.M[1]) {
     const long q = g.at(i, j, k);
     const T *Js[3] = {J0, J1, J2};
+    T *LJ[3] = {LJ0, LJ1, LJ2};
 #pragma unroll
     for (int A = 0; A < 3; ++A) {
-      if (!e_updated<T, DIM>(g, A, id)) continue;
+      if (!e_updated<T, DIM>(g, A, id)) {
+        if (LJ0) LJ[A][q] = T(0);
+        continue;
+      }
       const int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
       T Db = T(0), Dc = T(0);
       if (Bx < DIM) Db = Fe.B[Cx][q] - Fe.B[Cx][q - stride_ax<T, DIM>(g, Bx)];
@@ -289,14 +297,14 @@ __global__ void __launch_bounds__(256) k_adj_E_self(Grid<T> g, AdjFields<T> L, F
         for (int d = 0; d < DIM; ++d) { axis_al[d] = g.tb(d, d == A ? T_A_C : T_A_N, id[d]); al *= axis_al[d]; }
       }
       const T lt = L.LT[A][q];
-      double dU_dalpha = 0.0;
+      double dU_daj = 0.0;   // dU/d(alpha J) at this sample
       if (DIM == 2 && (Bx == 2 || Cx == 2)) {
         const int P = (Bx == 2) ? Cx : Bx;
         const T e = g.tb(P, T_E_N, id[P]), gg = g.tb(P, T_G_N, id[P]);
         acc[P][G_E_N] += (double)lt * (double)Fe.E[A][q];
         acc[P][G_GK_N] += (double)lt * (double)(P == Bx ? Db : -Dc);
         acc[P][G_G_N] += (double)lt * (double)(-al * jr);
-        dU_dalpha = -(double)lt * (double)gg * (double)jr;
+        dU_daj = -(double)lt * (double)gg;
         L.LT[A][q] = e * lt;
       } else if (is_split<T, DIM>(g, true, A, id)) {
         const T lb = lt + L.LA[A][q], lc = lt;
@@ -313,13 +321,15 @@ __global__ void __launch_bounds__(256) k_adj_E_self(Grid<T> g, AdjFields<T> L, F
         acc[Cx][G_G_N] += (double)lc * (-wc * aj);
         acc[Bx][G_SIG_N] += -aj * (sc / (S * S)) * ((double)lb * gb - (double)lc * gc);
         acc[Cx][G_SIG_N] += -aj * (sb / (S * S)) * ((double)lc * gc - (double)lb * gb);
-        dU_dalpha = -(double)jr * ((double)lb * gb * wb + (double)lc * gc * wc);
+        dU_daj = -((double)lb * gb * wb + (double)lc * gc * wc);
         const T nb = g.tb(Bx, T_E_N, id[Bx]) * lb, nc = g.tb(Cx, T_E_N, id[Cx]) * lc;
         L.LT[A][q] = nc;
         L.LA[A][q] = nb - nc;
       } else {
-        dU_dalpha = -(double)lt * (double)g.dt * (double)jr;
+        dU_daj = -(double)lt * (double)g.dt;
       }
+      if (LJ0) LJ[A][q] = (T)(dU_daj * (double)al);
+      const double dU_dalpha = dU_daj * (double)jr;
       if (alpha_mode != 1 && dU_dalpha != 0.0) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -362,16 +372,18 @@ void launch_adj_B_half(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> 
 }
 
 // transpose of the E step whose input was Fe (E before, B^{n+1/2} used by the curl), J raw
+// (LJ: null, or the three arrays that receive the adjoint of the step's current)
 template <typename T>
 void launch_adj_E(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> &Fe, T *const J[3], int alpha_mode,
-                  double *Gacc, hipStream_t s) {
+                  double *Gacc, T *const *LJ, hipStream_t s) {
   dim3 blk, grd = adj_grid(g, blk);
+  T *l0 = LJ ? LJ[0] : nullptr, *l1 = LJ ? LJ[1] : nullptr, *l2 = LJ ? LJ[2] : nullptr;
   if (g.dim == 2) {
     hipLaunchKernelGGL((k_adj_E_curl<T, 2>), grd, blk, 0, s, g, L);
-    hipLaunchKernelGGL((k_adj_E_self<T, 2>), grd, blk, 0, s, g, L, Fe, J[0], J[1], J[2], alpha_mode, Gacc);
+    hipLaunchKernelGGL((k_adj_E_self<T, 2>), grd, blk, 0, s, g, L, Fe, J[0], J[1], J[2], alpha_mode, Gacc, l0, l1, l2);
   } else {
     hipLaunchKernelGGL((k_adj_E_curl<T, 3>), grd, blk, 0, s, g, L);
-    hipLaunchKernelGGL((k_adj_E_self<T, 3>), grd, blk, 0, s, g, L, Fe, J[0], J[1], J[2], alpha_mode, Gacc);
+    hipLaunchKernelGGL((k_adj_E_self<T, 3>), grd, blk, 0, s, g, L, Fe, J[0], J[1], J[2], alpha_mode, Gacc, l0, l1, l2);
   }
 }
 
@@ -380,8 +392,8 @@ template void launch_adj_seed_energy<double>(const Grid<double> &, const Fields<
 template void launch_adj_B_half<float>(const Grid<float> &, const AdjFields<float> &, const Fields<float> &, double *, hipStream_t);
 template void launch_adj_B_half<double>(const Grid<double> &, const AdjFields<double> &, const Fields<double> &, double *, hipStream_t);
 template void launch_adj_E<float>(const Grid<float> &, const AdjFields<float> &, const Fields<float> &, float *const[3], int,
-                                  double *, hipStream_t);
+                                  double *, float *const *, hipStream_t);
 template void launch_adj_E<double>(const Grid<double> &, const AdjFields<double> &, const Fields<double> &, double *const[3],
-                                   int, double *, hipStream_t);
+                                   int, double *, double *const *, hipStream_t);
 
 }  // namespace pmlpic

@@ -55,6 +55,9 @@ struct Layout {
   size_t off_ckpt = 0, ckpt_stride = 0;
   size_t off_seg_state = 0, off_seg_J = 0, J_bytes = 0;
   size_t off_adj = 0, off_bh = 0, off_grad = 0;
+  // pushed runs: the particle buffer and live count at each step of a segment, the
+  // adjoint of one step's current, and the particle adjoints (offsets, momenta) by id
+  size_t off_seg_parts = 0, off_seg_count = 0, off_lj = 0, off_padj = 0;
   size_t total = 0;
 };
 
@@ -309,6 +312,12 @@ void make_layout(const pml_pic_params &p, Layout &L) {
     L.off_adj = take(12 * fb);
     L.off_bh = take(6 * fb);
     L.off_grad = take(8 * 3 * 8 * (size_t)L.ntab);
+    if (p.push) {
+      L.off_seg_parts = take(L.parts_bytes * (size_t)L.seg);
+      L.off_seg_count = take(4 * (size_t)L.seg);
+      L.off_lj = take(3 * fb);
+      L.off_padj = take(6 * L.esz * cap);
+    }
   }
   L.total = off;
 }
@@ -339,6 +348,11 @@ struct pml_pic_handle {
   // while set, step k of step_t copies the 12 field arrays before the step to
   // snap_state[k] and the undamped current after the deposit to snap_J[k]
   std::vector<char *> snap_state, snap_J;
+  // pushed runs: the particle buffer and count as step k's push reads them go to
+  // snap_parts[k] and snap_count[k], the host's slot bound to snap_ns[k]
+  std::vector<char *> snap_parts, snap_count;
+  std::vector<int64_t> snap_ns;
+  bool padj_valid = false;   // particle adjoints hold the last pml_pic_backward's result
   // the last step's filtered current lives in the filter's scratch arrays (odd passes)
   bool j_in_tmp = false;
   bool has_cond = false;                 // conductor mask set
@@ -837,6 +851,11 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       pt.end(s, PML_PIC_PHASE_CLEAR_J);
     }
     const Parts<T> P = h->parts<T>(h->cur);
+    if (it < (int)h->snap_parts.size()) {
+      HIPCHK(h, hipMemcpyAsync(h->snap_parts[it], P.cell, h->L.parts_bytes, hipMemcpyDeviceToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(h->snap_count[it], ctl.count, 4, hipMemcpyDeviceToDevice, s));
+      h->snap_ns[it] = ns;
+    }
     pt.begin(s);
     if (fused && use_sort && h->L.tile_push3) {
       launch_push3d<T>(g, F, P, ctl, h->tilework(), h->p.push, s);
@@ -1838,7 +1857,8 @@ int restore_ckpt(pml_pic_handle *h, int c) {
 
 int check_adjoint(pml_pic_handle *h) {
   if (h->L.seg <= 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "created without adjoint_segment");
-  if (h->p.push != 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "the adjoint covers ballistic runs (push = 0)");
+  if (h->p.push != 0 && h->n_added > h->L.cap)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "the pushed adjoint needs particle ids below max_particles");
   if (h->p.alpha_mode == PML_ALPHA_ZERO)
     return fail(&h->err, PML_PIC_E_INVALID_ARG, "alpha_mode 0 is not differentiable in the profile");
   if (h->p.alpha_mode == PML_ALPHA_WEIGHT)
@@ -1864,6 +1884,7 @@ int forward_ckpt_t(pml_pic_handle *h, int n, double *U) {
   }
   if ((rc = save_ckpt(h, h->L.nckpt - 1))) return rc;
   h->fwd_steps = n;
+  h->padj_valid = false;
   pml_pic_diag d;
   rc = diagnose_t<T>(h, &d);
   if (rc && rc != PML_PIC_E_NONFINITE) return rc;
@@ -1941,6 +1962,20 @@ int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double
     A.LA[c] = (T *)(h->ws + L.off_adj + (6 + c) * fb);
   }
   HIPCHK(h, hipMemsetAsync(h->ws + L.off_adj, 0, 12 * fb, s));
+  const bool pushed = h->p.push != 0;
+  T *LJ[3] = {nullptr, nullptr, nullptr};
+  PartAdj<T> PA{};
+  if (pushed) {   // the current's adjoint is 0 outside the samples E updates; particles start at 0
+    const size_t cap = (size_t)std::max<int64_t>(L.cap, 1);
+    for (int a = 0; a < 3; ++a) LJ[a] = (T *)(h->ws + L.off_lj + a * fb);
+    for (int d = 0; d < 3; ++d) {
+      PA.lf[d] = (T *)(h->ws + L.off_padj + d * sizeof(T) * cap);
+      PA.lu[d] = (T *)(h->ws + L.off_padj + (3 + d) * sizeof(T) * cap);
+    }
+    HIPCHK(h, hipMemsetAsync(h->ws + L.off_lj, 0, 3 * fb, s));
+    HIPCHK(h, hipMemsetAsync(h->ws + L.off_padj, 0, 6 * sizeof(T) * cap, s));
+  }
+  h->padj_valid = false;
   if ((rc = restore_ckpt(h, L.nckpt - 1))) return rc;
   const size_t ns = (size_t)L.nn[0] * L.nn[1] * L.nn[2];
   if (!seed) {
@@ -1979,10 +2014,19 @@ int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double
     for (int k = 0; k < len; ++k) {
       h->snap_state.push_back(seg_state + (size_t)k * L.fields_bytes);
       h->snap_J.push_back(seg_J + (size_t)k * L.J_bytes);
+      if (pushed) {
+        h->snap_parts.push_back(h->ws + L.off_seg_parts + (size_t)k * L.parts_bytes);
+        h->snap_count.push_back(h->ws + L.off_seg_count + 4 * (size_t)k);
+        h->snap_ns.push_back(0);
+      }
     }
     rc = step_t<T>(h, len, pt);
+    const std::vector<int64_t> seg_ns = h->snap_ns;
     h->snap_state.clear();
     h->snap_J.clear();
+    h->snap_parts.clear();
+    h->snap_count.clear();
+    h->snap_ns.clear();
     if (rc) return rc;
     HIPCHK(h, hipMemcpyAsync(seg_state + (size_t)len * L.fields_bytes, h->ws + h->foff(0), L.fields_bytes,
                              hipMemcpyDeviceToDevice, s));
@@ -2000,12 +2044,27 @@ int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double
       Fields<T> F3 = FH;        // second B half step: B^{n+1/2} -> B^{n+1} with E^{n+1}
       for (int a = 0; a < 3; ++a) F3.E[a] = Fn1.E[a];
       launch_adj_B_half<T>(g, A, F3, Gacc, s);
-      launch_adj_E<T>(g, A, FH, J, h->p.alpha_mode, Gacc, s);   // E^n -> E^{n+1} with B^{n+1/2}
+      launch_adj_E<T>(g, A, FH, J, h->p.alpha_mode, Gacc, pushed ? LJ : nullptr, s);   // E^n -> E^{n+1}
       launch_adj_B_half<T>(g, A, Fn, Gacc, s);                 // first half step: B^n, E^n
+      if (pushed) {   // gather_push and deposit_current of step k, from its particles and E^n, B^n
+        const size_t rel = (size_t)k * L.parts_bytes - L.off_cell[0] + L.off_seg_parts;
+        Parts<T> Pk = h->parts<T>(0);
+        Pk.cell = (uint32_t *)(h->ws + rel + L.off_cell[0]);
+        for (int d = 0; d < 3; ++d) {
+          Pk.f[d] = d < h->p.dim ? (T *)(h->ws + rel + L.off_f[0][d]) : nullptr;
+          Pk.u[d] = (T *)(h->ws + rel + L.off_u[0][d]);
+        }
+        Pk.w = (T *)(h->ws + rel + L.off_w[0]);
+        Pk.lam = nullptr;
+        Pk.id = (int32_t *)(h->ws + rel + L.off_id[0]);
+        launch_adj_particles<T>(g, Fn, Pk, (const int32_t *)(h->ws + L.off_seg_count + 4 * (size_t)k),
+                                (int)seg_ns[k], A, LJ, PA, s);
+      }
     }
     HIPCHK(h, hipGetLastError());
   }
   if ((rc = restore_ckpt(h, L.nckpt - 1))) return rc;
+  h->padj_valid = pushed;
   std::vector<double> Gv((size_t)3 * 8 * L.ntab);
   HIPCHK(h, hipMemcpyAsync(Gv.data(), Gacc, 8 * Gv.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -2049,6 +2108,27 @@ static int pml_pic_backward_impl(pml_pic_handle *h, const double *seed, int64_t 
   if (seed && seed_count < 12 * ns) return fail(&h->err, PML_PIC_E_INVALID_ARG, "seed buffer too small");
   return h->p.precision == 64 ? backward_t<double>(h, seed, lambda_out, grad_theta)
                               : backward_t<float>(h, seed, lambda_out, grad_theta);
+}
+
+static int pml_pic_particle_adjoint_impl(pml_pic_handle *h, int64_t n, double *dU_dx, double *dU_du) {
+  if (!h || !dU_dx || !dU_du || n < 0) return PML_PIC_E_INVALID_ARG;
+  if (!h->padj_valid)
+    return fail(&h->err, PML_PIC_E_INVALID_ARG, "no pml_pic_backward of a pushed run to read particle adjoints from");
+  if (n > h->n_added || n > h->L.cap) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n exceeds the particles added");
+  const Layout &L = h->L;
+  const size_t cap = (size_t)std::max<int64_t>(L.cap, 1), esz = L.esz;
+  std::vector<char> buf(6 * esz * cap);
+  HIPCHK(h, hipMemcpy(buf.data(), h->ws + L.off_padj, buf.size(), hipMemcpyDeviceToHost));
+  auto val = [&](int arr, int64_t i) {
+    const char *q = buf.data() + ((size_t)arr * cap + (size_t)i) * esz;
+    return esz == 8 ? *(const double *)q : (double)*(const float *)q;
+  };
+  const int dim = h->p.dim;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int d = 0; d < dim; ++d) dU_dx[dim * i + d] = val(d, i) / h->p.dx[d];   // offsets are in cells
+    for (int d = 0; d < 3; ++d) dU_du[3 * i + d] = val(3 + d, i);
+  }
+  return PML_PIC_OK;
 }
 
 }  // extern "C"
@@ -2167,6 +2247,10 @@ int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U) {
 
 int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out, double *grad_theta, int32_t n_theta) {
   return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_backward_impl(h, seed, seed_count, lambda_out, grad_theta, n_theta); });
+}
+
+int pml_pic_particle_adjoint(pml_pic_handle *h, int64_t n, double *dU_dx, double *dU_du) {
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_particle_adjoint_impl(h, n, dU_dx, dU_du); });
 }
 
 }  // extern "C"

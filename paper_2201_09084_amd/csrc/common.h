@@ -368,7 +368,18 @@ template <typename T>
 void launch_adj_B_half(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> &Fb, double *Gacc, hipStream_t s);
 template <typename T>
 void launch_adj_E(const Grid<T> &g, const AdjFields<T> &L, const Fields<T> &Fe, T *const J[3], int alpha_mode,
-                  double *Gacc, hipStream_t s);
+                  double *Gacc, T *const *LJ, hipStream_t s);
+// adjoint of each particle's offset (cell units, per axis) and momentum, indexed by id
+template <typename T>
+struct PartAdj {
+  T *lf[3];
+  T *lu[3];
+};
+// reverse of one step's gather_push and deposit_current (adjoint_particles.hip): Fn holds
+// the fields at the start of the step, P the particles as that step's push read them
+template <typename T>
+void launch_adj_particles(const Grid<T> &g, const Fields<T> &Fn, const Parts<T> &P, const int32_t *count, int ns,
+                          const AdjFields<T> &L, T *const LJ[3], const PartAdj<T> &A, hipStream_t s);
 
 // one run of a batch: everything its kernels need, in device memory
 template <typename T>

@@ -266,9 +266,9 @@ def beam3d_particles(cfg: SimConfig, seed: int = 1004, background_ppc: float = 1
 
 # ---------------------------------------------------------------- workload 5
 def adjoint_config(precision: int = 32, n: int = 512, pml: int = 16) -> SimConfig:
-    """2D 512x512 grid, 16-cell PML, quadratic shape, c dt = 0.7, ballistic particles
-    (the current does not depend on the fields, so the adjoint is that of the field
-    update and of the damping)."""
+    """2D 512x512 grid, 16-cell PML, quadratic shape, c dt = 0.7, sigma/eps0 = 3.2 r^3,
+    s = 1; ballistic particles (push = 0: the current does not depend on the fields, so
+    the adjoint is that of the field update and of the damping) unless push=1 is set."""
     return SimConfig(dim=2, n=(n, n, 1), pml=((pml, pml), (pml, pml), (0, 0)), dt=0.7,
                      shape_order=2, alpha_mode=ALPHA_DAMPED, damping_scale=1.0,
                      sigma_coef=cubic_profile(3.2), push=0, precision=precision)
@@ -282,7 +282,7 @@ def positive_profile(scale: float = 1.0) -> tuple:
 
 
 def adjoint_small_config(precision: int = 64, n: int = 40, pml: int = 8, dim: int = 2) -> SimConfig:
-    """Small ballistic case for gradient checks against the oracle."""
+    """Small case for gradient checks against the oracle (ballistic unless push=1 is set)."""
     nz = n if dim == 3 else 1
     pz = (pml, pml) if dim == 3 else (0, 0)
     return SimConfig(dim=dim, n=(n, n, nz), pml=((pml, pml), (pml, pml), pz), dt=0.5 if dim == 3 else 0.7,

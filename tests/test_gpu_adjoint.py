@@ -1,7 +1,27 @@
-"""Adjoint of the step (ballistic particles): the transposed update checked by the
-dot-product identity, the gradient of the interior field energy checked against the
-oracle's central differences, FP32 against FP64, checkpoint segment invariance, the
-torch.autograd.Function wrapper, and the full-size workload."""
+"""Adjoint of the step.
+
+Ballistic particles (push = 0): the transposed update checked by the dot-product identity,
+the gradient of the interior field energy against the oracle's central differences, FP32
+against FP64, checkpoint segment invariance, the torch.autograd.Function wrapper.
+
+Pushed particles (push = 1, the whole step: gather, Boris push and Esirkepov deposit
+reversed too): from random initial fields (so the particles' response to the fields is
+large), the profile gradient, the particles' dU/dx0 and dU/du0 and the adjoint of the
+initial fields in a random direction, each against the FP64 oracle's Richardson-extrapolated
+central differences, in 2D and 3D for shape orders 1-3; FP32 against FP64; segment
+invariance.
+
+The full-size workload (2D 512^2, 16-cell PML, 4096-particle bunch, 500 steps,
+checkpoints every 50, sigma/eps0 = 3.2 r^3, s = 1): ballistic and pushed, FP32 against
+FP64, and the pushed FP64 gradient against the oracle's differences stored in
+tests/golden/adjoint_c5_pushed_fd.json.
+
+A finite-difference reference carries its own error: the tolerance on each comparison is
+a small relative slack plus four times the difference between the estimates at h and h/2
+(which bounds the error of the extrapolated value)."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -123,9 +143,20 @@ def test_invalid_uses_are_rejected():
     plain = B.PmlPic(cfg, max_particles=2)
     with pytest.raises(B.PmlPicError):
         plain.forward_ckpt(5)              # no adjoint storage
-    pushed = A.make_sim(cfg.replace(push=1), A.theta_of(cfg), p, 20, 10)
     with pytest.raises(B.PmlPicError):
-        pushed.forward_ckpt(5)             # the adjoint covers ballistic runs
+        A.make_sim(cfg.replace(alpha_mode=W.ALPHA_WEIGHT), A.theta_of(cfg), p, 20, 10).forward_ckpt(5)
+    sim.forward_ckpt(10)
+    sim.backward()
+    with pytest.raises(B.PmlPicError):
+        sim.particle_adjoint(2)            # a ballistic reverse pass has no particle adjoint
+    pushed = A.make_sim(cfg.replace(push=1), A.theta_of(cfg), p, 20, 10)
+    pushed.forward_ckpt(10)
+    with pytest.raises(B.PmlPicError):
+        pushed.particle_adjoint(2)         # not reversed yet
+    pushed.backward()
+    with pytest.raises(B.PmlPicError):
+        pushed.particle_adjoint(3)         # more ids than particles added
+    assert pushed.particle_adjoint(2)[1].shape == (2, 3)
 
 
 def test_autograd_function():
@@ -139,10 +170,11 @@ def test_autograd_function():
 
 
 def test_full_size_workload_fp32_against_fp64_and_differences():
-    """2D 512 x 512, 16-cell layer, 4096-particle bunch, 500 steps, checkpoints every
-    50: FP32 gradient against the FP64 gradient, and the FP64 gradient against central
-    differences of the FP64 forward run on the GPU for a few parameters."""
-    cfg64 = W.adjoint_config(precision=64).replace(sigma_coef=W.positive_profile())
+    """Ballistic: 2D 512 x 512, 16-cell layer, 4096-particle bunch, 500 steps, checkpoints
+    every 50, sigma/eps0 = 3.2 r^3: FP32 gradient against the FP64 gradient, and the FP64
+    gradient against central differences of the FP64 forward run on the GPU for the
+    parameters that are non-zero at this profile."""
+    cfg64 = W.adjoint_config(precision=64)
     p = W.adjoint_particles(cfg64)
     steps, seg = 500, 50
     U64, g64, _, _ = _grad(cfg64, p, steps, seg)
@@ -152,8 +184,8 @@ def test_full_size_workload_fp32_against_fp64_and_differences():
     assert abs(U32 - U64) <= 1e-4 * abs(U64)
     assert err <= 1e-3
     th0 = A.theta_of(cfg64)
-    for i in (0, 3, 19, 32):
-        h = 1e-3 * max(abs(th0[i]), 0.1)
+    for i in (3, 19, 32):
+        h = 1e-3 * abs(th0[i])
         D = []
         for hh in (h, 0.5 * h):
             Us = []
@@ -168,3 +200,125 @@ def test_full_size_workload_fp32_against_fp64_and_differences():
         fd = (4 * D[1] - D[0]) / 3
         say("  theta", i, "adjoint", g64[i], "differences", fd)
         assert abs(g64[i] - fd) <= 1e-6 * np.max(np.abs(g64))
+
+
+# ---------------------------------------------------------------- pushed particles
+def _pushed_case(dim, order):
+    if dim == 2:
+        cfg = W.adjoint_small_config().replace(push=1, shape_order=order)
+        steps = 60
+    else:
+        cfg = W.adjoint_small_config(n=12, pml=4, dim=3).replace(push=1, shape_order=order)
+        steps = 30
+    p = W.adjoint_small_particles(cfg, 4)
+    S0 = W.random_split_fields(cfg, 41, amp=0.05)
+    return cfg, p, steps, S0
+
+
+def _oracle_U(cfg, p, steps, S0, theta=None, x=None, u=None):
+    c = cfg if theta is None else oracle.with_theta(cfg, theta)
+    return oracle.interior_energy(c, p.x if x is None else x, p.u if u is None else u, p.w, steps, fields=S0)
+
+
+def _richardson(f, h):
+    """Central differences at h and h/2, extrapolated; and |D(h) - D(h/2)|."""
+    D = [(f(hh) - f(-hh)) / (2.0 * hh) for hh in (h, 0.5 * h)]
+    return (4.0 * D[1] - D[0]) / 3.0, abs(D[1] - D[0])
+
+
+def _check(name, got, ref, err, scale, rel=1e-7):
+    tol = rel * scale + 1e-6 * abs(ref) + 4.0 * err
+    say("  %-10s adjoint % .10e differences % .10e |diff| %.2e tol %.2e" % (name, got, ref, abs(got - ref), tol))
+    assert abs(got - ref) <= tol, name
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_pushed_adjoint_matches_oracle_differences(dim, order):
+    """Profile gradient, particle adjoints and the initial-field adjoint of a pushed run."""
+    cfg, p, steps, S0 = _pushed_case(dim, order)
+    sim = A.make_sim(cfg, A.theta_of(cfg), p, steps, 7)
+    sim.set_split_fields(S0)
+    U = sim.forward_ckpt(steps)
+    g, lam = sim.backward(want_lambda=True)
+    gx, gu = sim.particle_adjoint(len(p.w))
+    Uo = _oracle_U(cfg, p, steps, S0)
+    say("dim", dim, "order", order, "U gpu", U, "oracle", Uo)
+    assert abs(U - Uo) <= 1e-12 * abs(Uo)
+    th0 = oracle.theta_vector(cfg)
+    idx = [0, 3, 5, 16, 19, 32] if dim == 2 else [0, 3, 19, 35, 48]
+    refs = {}
+    for i in idx:
+        def f(e, i=i):
+            th = th0.copy()
+            th[i] += e
+            return _oracle_U(cfg, p, steps, S0, theta=th)
+        refs[i] = _richardson(f, 1e-3 * max(abs(th0[i]), 0.1))
+    scale = max(abs(r[0]) for r in refs.values())
+    for i in idx:
+        _check("theta %d" % i, g[i], refs[i][0], refs[i][1], scale)
+    prefs = []
+    for j in range(2):
+        for c in range(dim + 3):
+            def f(e, j=j, c=c):
+                x, u = p.x.copy(), p.u.copy()
+                if c < dim:
+                    x[j, c] += e
+                else:
+                    u[j, c - dim] += e
+                return _oracle_U(cfg, p, steps, S0, x=x, u=u)
+            got = gx[j, c] if c < dim else gu[j, c - dim]
+            prefs.append(("%s[%d,%d]" % ("x" if c < dim else "u", j, c if c < dim else c - dim), got)
+                         + _richardson(f, 1e-5))
+    scale = max(abs(r[2]) for r in prefs)
+    for name, got, ref, err in prefs:
+        _check(name, got, ref, err, scale)
+    d = W.random_split_fields(cfg, 43)
+    ref, err = _richardson(lambda e: _oracle_U(cfg, p, steps, S0 + e * d), 1e-4)
+    _check("fields.d", float(np.sum(lam * d)), ref, err, abs(ref))
+
+
+def test_pushed_segment_length_does_not_change_the_gradient():
+    cfg, p, steps, S0 = _pushed_case(2, 2)
+    out = []
+    for seg in (7, 60):
+        sim = A.make_sim(cfg, A.theta_of(cfg), p, steps, seg)
+        sim.set_split_fields(S0)
+        U = sim.forward_ckpt(steps)
+        g, _ = sim.backward()
+        out.append((U, g, sim.particle_adjoint(len(p.w))[1]))
+    assert abs(out[0][0] - out[1][0]) <= 1e-13 * abs(out[0][0])
+    assert np.max(np.abs(out[0][1] - out[1][1])) <= 1e-11 * np.max(np.abs(out[0][1]))
+    assert np.max(np.abs(out[0][2] - out[1][2])) <= 1e-11 * np.max(np.abs(out[0][2]))
+
+
+def test_pushed_fp32_gradient_close_to_fp64():
+    cfg = W.adjoint_small_config(n=64, pml=12).replace(push=1)
+    p = W.adjoint_small_particles(cfg, 64)
+    _, g64, _, _ = _grad(cfg, p, 120, 20)
+    _, g32, _, _ = _grad(cfg.replace(precision=32), p, 120, 20)
+    err = np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))
+    say("pushed FP32 vs FP64 gradient, max-norm relative", err)
+    assert err <= 1e-3
+
+
+def test_full_size_pushed_workload_against_oracle_differences():
+    """Pushed: the full-size workload at sigma/eps0 = 3.2 r^3, s = 1 (the bunch crosses the
+    +x layer and leaves through the outer wall by step ~150; U after 500 steps).  FP64 U
+    and gradient against the oracle's stored values, FP32 against FP64."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "adjoint_c5_pushed_fd.json")) as fh:
+        ref = json.load(fh)
+    cfg64 = W.adjoint_config(precision=64).replace(push=1)
+    p = W.adjoint_particles(cfg64)
+    steps, seg = 500, 50
+    U64, g64, _, sim = _grad(cfg64, p, steps, seg)
+    gx, gu = sim.particle_adjoint(len(p.w))
+    U32, g32, _, _ = _grad(cfg64.replace(precision=32), p, steps, seg)
+    err = np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))
+    say("C5 pushed: U fp64", U64, "oracle", ref["U"], "fp32", U32, "gradient fp32 vs fp64", err)
+    say("  |dU/du0| max", np.max(np.abs(gu)), "|dU/dx0| max", np.max(np.abs(gx)))
+    assert abs(U64 - ref["U"]) <= 1e-10 * abs(ref["U"])
+    assert abs(U32 - U64) <= 1e-4 * abs(U64)
+    assert err <= 1e-3
+    scale = np.max(np.abs(g64))
+    for i, r in ref["derivatives"].items():
+        _check("theta " + i, g64[int(i)], r["value"], r["error_estimate"], scale, rel=1e-10)
