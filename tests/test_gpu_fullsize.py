@@ -5,7 +5,7 @@ deposit alpha-damped current there).
 * The 2D beam centred on the +x interface (1024^2 + 16-cell PML, 1,048,576 particles, a third of
   them in the layer at step 0, the fastest leaving through the outer wall within the window):
   FP64 and FP32 against the FP64 oracle (all-cores build) over 8 steps, every sample and
-  particle.
+  particle, and over the 128-step window, every sample every 32 steps.
 * The 3D beam whose head fills the +z layer (the benchmark's input): the oracle needs about a
   minute per step at 256^3 + 12 with 16.8M particles, so the parity case is the same workload
   on the largest sub-box it steps in seconds, 128^3 + 12 (2,129,920 particles, the same
@@ -115,6 +115,26 @@ def test_beam2d_straddling_pml_full_size_against_oracle():
     say("particles left", n_left)
     assert n_left < len(parts)                  # some went through the outer wall
     assert g.num_particles == n_left == g32.num_particles
+
+
+def test_beam2d_straddling_pml_128_step_window_against_oracle():
+    """The 128-step parity window with the beam in the +x layer from its first step: FP64
+    and FP32 against the FP64 oracle (all-cores build) every 32 steps, fields and the live
+    particles at the end (the fast head leaves through the outer wall meanwhile)."""
+    cfg = W.beam2d_config(precision=64)
+    parts = W.beam2d_particles(cfg, straddle=True)
+    g, o = both(cfg, parts, parallel=True)
+    g32 = _gpu(cfg.replace(precision=32), parts)
+    for k in range(4):
+        for s in (g, o, g32):
+            s.step(32)
+        compare_fields(g, o, cfg, 1e-10, "fp64 window @%d" % (32 * k + 32))
+        worst = compare_fields(g32, o, cfg, FP32_TOL, "fp32 window @%d" % (32 * k + 32), l2=True)
+        say("step", 32 * k + 32, "fp32 vs oracle worst rel L2 %.3e" % worst, "particles", o.num_particles)
+    # positions (grid units, up to ~1056 cells) to the same relative 1e-10 as the fields: the
+    # per-step roundings of two summation orders grow along 128 steps of self-consistent orbits
+    compare_particles(g, o, 1e-10 * (cfg.n[0] + 2 * cfg.pml[0][1]), 1e-10, "fp64 window")
+    assert g.num_particles == o.num_particles < len(parts)
 
 
 def test_beam3d_straddling_pml_subbox_against_oracle():
