@@ -70,9 +70,14 @@ enum {
     PML_PIC_FLAG_SEPARATE_DAMP = 4,/* damp_pml_current as its own pass over the PML */
     PML_PIC_FLAG_KEEP_CURRENT = 8, /* keep J after the step (for pml_pic_get_current); by
                                       default the E update consumes J and zeroes it */
-    PML_PIC_FLAG_SEPARATE_FIELDS = 16 /* update_yee_pml as three sweeps (B half, E, B half);
+    PML_PIC_FLAG_SEPARATE_FIELDS = 16,/* update_yee_pml as three sweeps (B half, E, B half);
                                       by default 2D runs make one pass over the fields,
                                       which keeps J after the step */
+    PML_PIC_FLAG_DETERMINISTIC = 32 /* debug mode: implies UNFUSED and NO_SORT, and one thread
+                                      adds the particles' currents in slot order with plain
+                                      loads and stores, so that a run repeats bit for bit and
+                                      equals the atomic deposit to rounding (slow: meant for
+                                      runs of a few thousand particles; single runs only) */
 };
 
 typedef struct {

@@ -19,6 +19,7 @@ PML_PIC_OK = 0
 STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_CFL", -3: "E_WORKSPACE", -4: "E_HIP",
           -5: "E_NONFINITE", -6: "E_CAPACITY", -7: "E_HOST"}
 FLAG_UNFUSED, FLAG_NO_SORT, FLAG_SEPARATE_DAMP, FLAG_KEEP_CURRENT, FLAG_SEPARATE_FIELDS = 1, 2, 4, 8, 16
+FLAG_DETERMINISTIC = 32
 
 EXPORTED = [
     "pml_pic_workspace_size", "pml_pic_create", "pml_pic_add_particles", "pml_pic_step",

@@ -127,6 +127,11 @@ int kernel_alpha_mode(const pml_pic_params &p) {
   return p.alpha_mode;
 }
 
+// the flags a run works with: the deterministic debug mode implies the unfused, unsorted form
+int effective_flags(int flags) {
+  return (flags & PML_PIC_FLAG_DETERMINISTIC) ? (flags | PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_NO_SORT) : flags;
+}
+
 int validate(const pml_pic_params *p, std::string *err) {
   if (!p) return fail(err, PML_PIC_E_INVALID_ARG, "params is NULL");
   if (p->dim != 2 && p->dim != 3) return fail(err, PML_PIC_E_INVALID_ARG, "dim must be 2 or 3");
@@ -209,7 +214,9 @@ int validate(const pml_pic_params *p, std::string *err) {
   return PML_PIC_OK;
 }
 
-void make_layout(const pml_pic_params &p, Layout &L) {
+void make_layout(const pml_pic_params &p_in, Layout &L) {
+  pml_pic_params p = p_in;
+  p.flags = effective_flags(p.flags);
   L.dim = p.dim;
   L.esz = p.precision == 64 ? 8 : 4;
   for (int d = 0; d < 3; ++d) {
@@ -869,7 +876,7 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     pt.end(s, PML_PIC_PHASE_PUSH);
     if (!fused) {
       pt.begin(s);
-      launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, s);
+      launch_deposit<T>(g, F, P, h->old_parts<T>(), ctl, ns, (fl & PML_PIC_FLAG_DETERMINISTIC) != 0, s);
       pt.end(s, PML_PIC_PHASE_DEPOSIT);
     }
     if (h->p.filter_passes > 0) {
@@ -1001,6 +1008,7 @@ static int create_handle(const pml_pic_params *params, void *device_workspace, s
     return fail(err, PML_PIC_E_WORKSPACE, "workspace must be 256-byte aligned");
   pml_pic_handle *h = new pml_pic_handle();
   h->p = *params;
+  h->p.flags = effective_flags(params->flags);
   h->L = L;
   h->ws = (char *)device_workspace;
   h->stream = (hipStream_t)stream;
@@ -1089,6 +1097,8 @@ int batch_layout(const pml_pic_params *runs, int32_t n, std::vector<Layout> &Ls,
     }
     if (runs[r].conductor || runs[r].max_source > 0)
       return fail(err, PML_PIC_E_INVALID_ARG, "batched runs have neither conductors nor sources");
+    if (runs[r].flags & PML_PIC_FLAG_DETERMINISTIC)
+      return fail(err, PML_PIC_E_INVALID_ARG, "the deterministic debug mode is for single runs");
     if (runs[r].solver != PML_PIC_SOLVER_YEE || runs[r].filter_passes > 0)
       return fail(err, PML_PIC_E_INVALID_ARG, "batched runs use the Yee solver without current filter");
     if (runs[r].dim != runs[0].dim || runs[r].shape_order != runs[0].shape_order ||

@@ -276,7 +276,7 @@ void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts
                                const TileWork &tw, int n_slots, int push, hipStream_t s);
 template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
-                    StepCtl ctl, int n_slots, hipStream_t s);
+                    StepCtl ctl, int n_slots, bool serial, hipStream_t s);
 
 // 3D linear-shape runs (push3d.hip): gather_push + deposit_current, one workgroup per sort
 // tile, its current summed in an LDS box of the tile's nodes (tile + 3 per axis) and added to

@@ -428,6 +428,52 @@ __global__ void __launch_bounds__(256) k_deposit(Grid<T> g, Fields<T> F, Parts<T
   }
 }
 
+// Deterministic debug form of the unfused deposit: one thread adds every particle's current
+// in slot order with plain loads and stores (the values of k_deposit, summed in a fixed
+// order, so that a run repeats bit for bit; with sorting off the slot order never changes).
+template <typename T>
+struct PlainSink {
+  T *J[3];
+  long q0, sy, sz;
+  __device__ __forceinline__ void origin(const Grid<T> &g, const int (&ws)[3]) {
+    q0 = g.at(ws[0], ws[1], ws[2]);
+    sy = g.sy;
+    sz = g.sz;
+  }
+  __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) { J[comp][q0 + a + b * sy + c * sz] += v; }
+};
+
+template <typename T, int DIM, int ORDER>
+__global__ void __launch_bounds__(64) k_deposit_serial(Grid<T> g, Fields<T> F, Parts<T> P, Parts<T> old,
+                                                        StepCtl ctl, int n_slots) {
+  if (threadIdx.x != 0) return;
+  const int n = min(n_slots, *ctl.count);
+  int box[4] = {0x7FFFFFFF, -0x7FFFFFFF, 0x7FFFFFFF, -0x7FFFFFFF};
+  PlainSink<T> sink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+  for (int p = 0; p < n; ++p) {
+    const uint32_t c = P.cell[p];
+    if (c == DEAD) continue;
+    int i1[3], i0[3];
+    unpack_cell(DIM, c, i1[0], i1[1], i1[2]);
+    unpack_cell(DIM, old.cell[p], i0[0], i0[1], i0[2]);
+    const T f1[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
+    const T f0[3] = {old.f[0][p], old.f[1][p], DIM == 3 ? old.f[2][p] : T(0)};
+    const T ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
+    const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
+    deposit<T, DIM, ORDER>(g, sink, i0, f0, i1, f1, uz * ig, deposit_charge<T, DIM>(g, P, p, i0, f0, i1, f1));
+    int rng[4];
+    dep_range<ORDER>(i0[0], i1[0], rng[0], rng[1]);
+    dep_range<ORDER>(i0[1], i1[1], rng[2], rng[3]);
+    box[0] = min(box[0], rng[0]); box[1] = max(box[1], rng[1]);
+    box[2] = min(box[2], rng[2]); box[3] = max(box[3], rng[3]);
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) inside = inside && i1[d] >= 0 && i1[d] < g.M[d];
+    if (!inside) P.cell[p] = DEAD;
+  }
+  if (DIM == 2 && ctl.jslot) jslot_merge(ctl.jslot, box[0], box[1], box[2], box[3]);
+}
+
 #define PMLPIC_DISPATCH_ORDER(DIMV, KERNEL, ...)                                         \
   switch (g.order) {                                                                    \
     case 1: hipLaunchKernelGGL((KERNEL<T, DIMV, 1>), grd, blk, 0, s, __VA_ARGS__); break; \
@@ -487,8 +533,14 @@ void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts
 
 template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
-                    StepCtl ctl, int n_slots, hipStream_t s) {
+                    StepCtl ctl, int n_slots, bool serial, hipStream_t s) {
   if (n_slots <= 0) return;
+  if (serial) {
+    dim3 blk(64), grd(1);
+    if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_deposit_serial, g, F, P, old, ctl, n_slots) }
+    else { PMLPIC_DISPATCH_ORDER(3, k_deposit_serial, g, F, P, old, ctl, n_slots) }
+    return;
+  }
   dim3 blk(256), grd((n_slots + 255) / 256);
   if (g.dim == 2) { PMLPIC_DISPATCH_ORDER(2, k_deposit, g, F, P, old, ctl, n_slots) }
   else { PMLPIC_DISPATCH_ORDER(3, k_deposit, g, F, P, old, ctl, n_slots) }
@@ -763,9 +815,9 @@ template void launch_gather_push<float>(const Grid<float> &, const Fields<float>
 template void launch_gather_push<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
                                          Parts<double>, StepCtl, int, int, bool, hipStream_t);
 template void launch_deposit<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
-                                    Parts<float>, StepCtl, int, hipStream_t);
+                                    Parts<float>, StepCtl, int, bool, hipStream_t);
 template void launch_deposit<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
-                                     Parts<double>, StepCtl, int, hipStream_t);
+                                     Parts<double>, StepCtl, int, bool, hipStream_t);
 template void launch_sort<float>(const Grid<float> &, const Parts<float> &, const Parts<float> &, SortWork,
                                  StepCtl, int, hipStream_t);
 template void launch_sort<double>(const Grid<double> &, const Parts<double> &, const Parts<double> &, SortWork,

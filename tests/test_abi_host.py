@@ -190,3 +190,15 @@ def test_host_allocation_failure_is_a_status_code(lib):
                        timeout=120)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr[-2000:])
     assert "rc -7 out of host memory" in r.stdout, r.stdout
+
+
+def test_deterministic_mode_layout_and_batch_rejection(lib):
+    """The deterministic debug mode takes the unfused, unsorted layout (no tile work
+    lists), and batches refuse it."""
+    cfg = W.SimConfig(dim=3, n=(13, 11, 9), pml=((4, 5), (3, 4), (5, 3)), dt=0.45, shape_order=1, precision=32)
+    det = B.workspace_size(B.make_params(cfg, 1000, B.FLAG_DETERMINISTIC))
+    plain = B.workspace_size(B.make_params(cfg, 1000, B.FLAG_UNFUSED | B.FLAG_NO_SORT))
+    assert det == plain
+    with pytest.raises(B.PmlPicError) as e:
+        B.batch_workspace_size([B.make_params(cfg, 1, B.FLAG_DETERMINISTIC)] * 2)
+    assert "single runs" in str(e.value)
