@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpmlpic.so")
+# PMLPIC_LIB may name another build of the library (the bounds-checked libpmlpic_check.so)
+LIB_PATH = os.environ.get("PMLPIC_LIB") or os.path.join(HERE, "libpmlpic.so")
 
 PML_PIC_OK = 0
 STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_CFL", -3: "E_WORKSPACE", -4: "E_HIP",
@@ -74,7 +75,7 @@ def load_library():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("libpmlpic.so is not built; run __graft_entry__.build()")
+            raise ImportError("%s is not built; run __graft_entry__.build()" % os.path.basename(LIB_PATH))
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, P(C.c_double)

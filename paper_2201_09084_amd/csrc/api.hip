@@ -58,6 +58,7 @@ struct Layout {
   // pushed runs: the particle buffer and live count at each step of a segment, the
   // adjoint of one step's current, and the particle adjoints (offsets, momenta) by id
   size_t off_seg_parts = 0, off_seg_count = 0, off_lj = 0, off_padj = 0;
+  size_t off_check = 0;                     // bounds-checked builds: the CHECK_* word
   size_t total = 0;
 };
 
@@ -270,6 +271,7 @@ void make_layout(const pml_pic_params &p_in, Layout &L) {
   for (int d = 0; d < 3; ++d) L.off_oldf[d] = d < p.dim ? take(L.esz * cap) : 0;
   L.tile_push3 = !(p.flags & (PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_NO_SORT)) && push3d_applies(p.dim, p.shape_order, L.tile);
   L.off_count = take(8);
+  L.off_check = take(4);
   L.off_pushes = take(8 * N_PUSH_COUNTERS);
   L.off_counts = take(4 * ((size_t)L.nkeys + 1));
   L.off_rank = take(4 * cap);
@@ -395,6 +397,11 @@ struct pml_pic_handle {
     g.wdamp = p.alpha_mode == PML_ALPHA_WEIGHT ? 1 : 0;
     g.prof = at<T>(L.off_tab) + 3 * T_NKIND * (size_t)L.ntab;
     g.cmask = has_cond ? at<uint8_t>(L.off_cmask) : nullptr;
+#ifdef PMLPIC_CHECK
+    g.check = at<uint32_t>(L.off_check);
+#else
+    g.check = nullptr;
+#endif
     return g;
   }
   // offset of field array idx (0..11: E, B, Ea, Ba) of set `set`
@@ -461,6 +468,11 @@ struct pml_pic_handle {
     s.blocksums = at<uint32_t>(L.off_blocksums);
     s.nkeys = L.nkeys;
     for (int d = 0; d < 3; ++d) { s.tile[d] = L.tile[d]; s.ntile[d] = L.ntile[d]; }
+#ifdef PMLPIC_CHECK
+    s.check = at<uint32_t>(L.off_check);
+#else
+    s.check = nullptr;
+#endif
     return s;
   }
   TileWork tilework() const {
@@ -1610,6 +1622,26 @@ static int pml_pic_set_particles_impl(pml_pic_handle *h, int64_t n, const int64_
   return PML_PIC_OK;
 }
 
+// Bounds-checked builds: after a call that ran kernels, any CHECK_* bit the kernels set
+// becomes PML_PIC_E_HIP with a message (and the word is cleared); other builds return rc.
+static int report_checks(pml_pic_handle *h, int rc) {
+#ifdef PMLPIC_CHECK
+  if (!h) return rc;
+  uint32_t bits = 0;
+  if (hipStreamSynchronize(h->stream) != hipSuccess ||
+      hipMemcpy(&bits, h->ws + h->L.off_check, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(&h->err, PML_PIC_E_HIP, "bounds-check word unreadable");
+  if (bits) {
+    (void)hipMemset(h->ws + h->L.off_check, 0, 4);
+    char msg[160];
+    snprintf(msg, sizeof msg, "bounds check failed (bits 0x%x: 1 sample index, 2 global current, 4 LDS box, 8 sort key)",
+             bits);
+    return fail(&h->err, PML_PIC_E_HIP, msg);
+  }
+#endif
+  return rc;
+}
+
 static int pml_pic_step_impl(pml_pic_handle *h, int32_t n_steps) {
   if (!h) return PML_PIC_E_INVALID_ARG;
   if (n_steps < 0) return fail(&h->err, PML_PIC_E_INVALID_ARG, "n_steps < 0");
@@ -2196,11 +2228,11 @@ int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, cons
 }
 
 int pml_pic_step(pml_pic_handle *h, int32_t n_steps) {
-  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_step_impl(h, n_steps); });
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return report_checks(h, pml_pic_step_impl(h, n_steps)); });
 }
 
 int pml_pic_step_profiled(pml_pic_handle *h, int32_t n_steps, double *phase_ms, int64_t *phase_calls) {
-  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_step_profiled_impl(h, n_steps, phase_ms, phase_calls); });
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return report_checks(h, pml_pic_step_profiled_impl(h, n_steps, phase_ms, phase_calls)); });
 }
 
 int pml_pic_field_error(pml_pic_handle *h, pml_pic_handle *ref, double *num, double *den) {
@@ -2212,7 +2244,7 @@ int pml_pic_field_error_noalloc(pml_pic_handle *h, pml_pic_handle *ref, double *
 }
 
 int pml_pic_diagnose(pml_pic_handle *h, pml_pic_diag *out) {
-  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_diagnose_impl(h, out); });
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return report_checks(h, pml_pic_diagnose_impl(h, out)); });
 }
 
 int pml_pic_grid_shape(const pml_pic_handle *h, int32_t nn[3], int64_t *n_samples) {
@@ -2240,7 +2272,7 @@ int pml_pic_set_rho_static(pml_pic_handle *h, const double *host, int64_t count)
 }
 
 int pml_pic_sort_particles(pml_pic_handle *h, int32_t tile[3], uint32_t *key_start, int64_t cap, int64_t *n_keys) {
-  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_sort_particles_impl(h, tile, key_start, cap, n_keys); });
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return report_checks(h, pml_pic_sort_particles_impl(h, tile, key_start, cap, n_keys)); });
 }
 
 int pml_pic_num_particles(pml_pic_handle *h, int64_t *n) {
@@ -2252,11 +2284,11 @@ int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *
 }
 
 int pml_pic_forward_ckpt(pml_pic_handle *h, int32_t n_steps, double *U) {
-  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_forward_ckpt_impl(h, n_steps, U); });
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return report_checks(h, pml_pic_forward_ckpt_impl(h, n_steps, U)); });
 }
 
 int pml_pic_backward(pml_pic_handle *h, const double *seed, int64_t seed_count, double *lambda_out, double *grad_theta, int32_t n_theta) {
-  return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_backward_impl(h, seed, seed_count, lambda_out, grad_theta, n_theta); });
+  return abi_guard(h ? &h->err : &g_create_error, [&] { return report_checks(h, pml_pic_backward_impl(h, seed, seed_count, lambda_out, grad_theta, n_theta)); });
 }
 
 int pml_pic_particle_adjoint(pml_pic_handle *h, int64_t n, double *dU_dx, double *dU_du) {

@@ -50,6 +50,20 @@ enum { PROF_LO = 0, PROF_HI, PROF_LLO, PROF_LHI, PROF_DX, PROF_C, PROF_N = PROF_
 // alpha applied to the current in the field update (modes 0 and 2)
 __host__ __device__ __forceinline__ bool current_alpha(int alpha_mode) { return alpha_mode == 0 || alpha_mode == 2; }
 
+// Bounds-checked debug builds (compiled with -DPMLPIC_CHECK into libpmlpic_check.so): the
+// particle kernels' index computations are checked before each access; a failed check sets a
+// bit in a word of the workspace and the access is skipped (or redirected to sample 0), so
+// the kernel still ends normally, and the host turns the bits into an error.
+enum CheckBits : uint32_t {
+  CHECK_SAMPLE = 1u,      // a field / current sample index outside its array
+  CHECK_GLOBAL_J = 2u,    // a deposit to global J outside the array
+  CHECK_LDS_BOX = 4u,     // a deposit into a workgroup's LDS current box outside the box
+  CHECK_SORT_KEY = 8u     // a particle's sort key outside the key range
+};
+__device__ __forceinline__ void check_failed(uint32_t *check, uint32_t bit) {
+  if (check) atomicOr(check, bit);
+}
+
 template <typename T>
 struct Grid {
   int dim, order;
@@ -72,8 +86,16 @@ struct Grid {
   const T *prof;       // [3][PROF_N]: layer edges, thicknesses and sigma coefficients
   const uint8_t *cmask;  // conductor: per node, bit c set when sample c (E_x..E_z, B_x..B_z)
                          // at that node index lies in a conductor cell; null without conductors
+  uint32_t *check;       // bounds-checked builds (PMLPIC_CHECK): CHECK_* bits of failed
+                         // checks, read by the host after each call; null otherwise
 
-  __host__ __device__ long at(int i, int j, int k) const { return base + i + j * sy + k * sz; }
+  __host__ __device__ long at(int i, int j, int k) const {
+    const long q = base + i + j * sy + k * sz;
+#if defined(PMLPIC_CHECK) && defined(__HIP_DEVICE_COMPILE__)
+    if (q < 0 || q >= nelem) { check_failed(check, CHECK_SAMPLE); return 0; }
+#endif
+    return q;
+  }
   __device__ T tb(int axis, int kind, int i) const {
     return gptr(tab)[(axis * T_NKIND + kind) * ntab + i + G];
   }
@@ -293,6 +315,7 @@ struct SortWork {
   int nkeys;
   int tile[3];
   int ntile[3];
+  uint32_t *check;       // bounds-checked builds: as Grid::check
 };
 template <typename T>
 void launch_sort(const Grid<T> &g, const Parts<T> &src, const Parts<T> &dst, SortWork sw,

@@ -166,13 +166,21 @@ template <typename T>
 struct GlobalSink {
   T *J[3];
   long q0, sy, sz;
+  long nelem = 0;
+  uint32_t *check = nullptr;
   __device__ __forceinline__ void origin(const Grid<T> &g, const int (&ws)[3]) {
     q0 = g.at(ws[0], ws[1], ws[2]);
     sy = g.sy;
     sz = g.sz;
+    nelem = g.nelem;
+    check = g.check;
   }
   __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) {
-    atomic_add(&J[comp][q0 + a + b * sy + c * sz], v);
+    const long q = q0 + a + b * sy + c * sz;
+#ifdef PMLPIC_CHECK
+    if (q < 0 || q >= nelem) { check_failed(check, CHECK_GLOBAL_J); return; }
+#endif
+    atomic_add(&J[comp][q], v);
   }
 };
 
@@ -187,11 +195,17 @@ struct LdsSink {
   int lo[3];
   int e0, e01, total;
   int q0;
-  __device__ __forceinline__ void origin(const Grid<T> &, const int (&ws)[3]) {
+  uint32_t *check = nullptr;
+  __device__ __forceinline__ void origin(const Grid<T> &g, const int (&ws)[3]) {
     q0 = (ws[0] - lo[0]) + (ws[1] - lo[1]) * e0 + (ws[2] - lo[2]) * e01;
+    check = g.check;
   }
   __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) {
-    atomicAdd(&lds[comp * total + q0 + a + b * e0 + c * e01], (double)v);
+    const int q = q0 + a + b * e0 + c * e01;
+#ifdef PMLPIC_CHECK
+    if (q < 0 || q >= total) { check_failed(check, CHECK_LDS_BOX); return; }
+#endif
+    atomicAdd(&lds[comp * total + q], (double)v);
   }
 };
 

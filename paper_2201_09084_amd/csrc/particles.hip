@@ -435,12 +435,22 @@ template <typename T>
 struct PlainSink {
   T *J[3];
   long q0, sy, sz;
+  long nelem = 0;
+  uint32_t *check = nullptr;
   __device__ __forceinline__ void origin(const Grid<T> &g, const int (&ws)[3]) {
     q0 = g.at(ws[0], ws[1], ws[2]);
     sy = g.sy;
     sz = g.sz;
+    nelem = g.nelem;
+    check = g.check;
   }
-  __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) { J[comp][q0 + a + b * sy + c * sz] += v; }
+  __device__ __forceinline__ void add(int comp, int a, int b, int c, T v) {
+    const long q = q0 + a + b * sy + c * sz;
+#ifdef PMLPIC_CHECK
+    if (q < 0 || q >= nelem) { check_failed(check, CHECK_GLOBAL_J); return; }
+#endif
+    J[comp][q] += v;
+  }
 };
 
 template <typename T, int DIM, int ORDER>
@@ -612,6 +622,9 @@ __global__ void __launch_bounds__(HIST_TPB) k_sort_hist(int dim, Parts<T> P, Sor
         int i, j, kk;
         unpack_cell(dim, c, i, j, kk);
         key[k] = cell_key(dim, sw, i, j, kk);
+#ifdef PMLPIC_CHECK
+        if (key[k] >= (uint32_t)sw.nkeys) { check_failed(sw.check, CHECK_SORT_KEY); key[k] = 0xFFFFFFFFu; }
+#endif
       }
     }
     // the table slot of my tile: the first lane of each run of equal tiles looks it up
@@ -741,6 +754,9 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int dim, Parts<T> src, Par
   int i, j, k;
   unpack_cell(dim, c, i, j, k);
   const uint32_t key = cell_key(dim, sw, i, j, k);
+#ifdef PMLPIC_CHECK
+  if (key >= (uint32_t)sw.nkeys) return;   // flagged by the histogram
+#endif
   const uint32_t q = sw.counts[key] + sw.rank[p];
   dst.cell[q] = c;
   for (int d = 0; d < dim; ++d) dst.f[d][q] = src.f[d][p];

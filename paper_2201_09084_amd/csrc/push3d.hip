@@ -43,7 +43,11 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const T val = coef * (b0[b] * u + b1[b] * v);
-        atomicAdd(&box[A * total + q0 + b * st[Bx] + c * st[Cx]], (double)val);
+        const int q = q0 + b * st[Bx] + c * st[Cx];
+#ifdef PMLPIC_CHECK
+        if (q < 0 || q >= total) { check_failed(g.check, CHECK_LDS_BOX); continue; }
+#endif
+        atomicAdd(&box[A * total + q], (double)val);
       }
     }
   }

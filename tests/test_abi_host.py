@@ -202,3 +202,14 @@ def test_deterministic_mode_layout_and_batch_rejection(lib):
     with pytest.raises(B.PmlPicError) as e:
         B.batch_workspace_size([B.make_params(cfg, 1, B.FLAG_DETERMINISTIC)] * 2)
     assert "single runs" in str(e.value)
+
+
+def test_checked_build_exports_every_declared_function():
+    """The bounds-checked debug build (libpmlpic_check.so) loads and exports the same calls."""
+    path = os.path.join(os.path.dirname(B.__file__), "libpmlpic_check.so")
+    assert os.path.exists(path), "build it with __graft_entry__.build()"
+    L = C.CDLL(path)
+    names = _declared_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
