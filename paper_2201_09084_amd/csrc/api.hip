@@ -39,6 +39,7 @@ struct Layout {
   bool tile_push3 = false;                  // 3D linear shape: push by sort tile (push3d.hip)
   size_t off_count = 0, off_pushes = 0;
   size_t off_counts = 0, off_rank = 0, off_blocksums = 0, off_tprefix = 0, off_tpartial = 0, off_tblocks = 0;
+  size_t off_tdense = 0;
   int ntiles = 1;
   size_t off_items = 0, max_items = 0, off_jbox = 0, off_jslot = 0;
   size_t off_rflags = 0, off_nitems = 0, max_ranges = 0;
@@ -279,6 +280,7 @@ void make_layout(const pml_pic_params &p_in, Layout &L) {
   L.ntiles = L.ntile[0] * L.ntile[1] * L.ntile[2];
   L.off_tprefix = take(4 * ((size_t)L.ntiles + 1));
   L.off_tpartial = take(4 * ((size_t)L.ntiles + 1));
+  L.off_tdense = take(4 * ((size_t)L.ntiles + 1));
   L.off_tblocks = take(4 * ((size_t)(L.ntiles + 4095) / 4096 + 2));
   // chunks of the tiled step: 3D, at most one partial chunk per tile beyond cap / chunk;
   // 2D, fixed ranges of the sorted array, each split into at most RANGE_SPLIT_MAX items
@@ -480,8 +482,10 @@ struct pml_pic_handle {
     w.key_start = at<uint32_t>(L.off_counts);
     w.prefix = at<uint32_t>(L.off_tprefix);
     w.pprefix = at<uint32_t>(L.off_tpartial);
+    w.dprefix = at<uint32_t>(L.off_tdense);
     w.blocksums = at<uint32_t>(L.off_tblocks);
     w.items = at<int4>(L.off_items);
+    w.sel = 0;
     w.flags = at<uint32_t>(L.off_rflags);
     w.n_items = at<uint32_t>(L.off_nitems);
     w.ntiles = L.ntiles;
@@ -788,7 +792,8 @@ void sort_now(pml_pic_handle *h, const StepCtl &ctl, int ns) {
   hipStream_t s = h->stream;
   const bool fused = !(h->p.flags & PML_PIC_FLAG_UNFUSED);
   launch_sort<T>(g, h->parts<T>(h->cur), h->parts<T>(1 - h->cur), h->sortwork(), ctl, ns, s);
-  if (fused && h->p.dim == 3 && !h->L.tile_push3) launch_tile_chunks(h->tilework(), ctl.count, s);
+  if (fused && h->p.dim == 3) launch_tile_chunks(h->tilework(), ctl.count, s);
+
   if (fused && h->p.dim == 2)
     launch_range_items(h->tilework(), h->parts<T>(1 - h->cur).cell, ctl.count, h->p.shape_order,
                        (int)h->L.max_ranges, std::min(h->sort_interval - 1, 2), s);
@@ -877,7 +882,13 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     }
     pt.begin(s);
     if (fused && use_sort && h->L.tile_push3) {
-      launch_push3d<T>(g, F, P, ctl, h->tilework(), h->p.push, s);
+      // dense tiles (a cell with many particles: a beam whose LDS adds would meet on a few
+      // nodes) take the kernel with chunk-sized replicated boxes, the others the tile-box one
+      TileWork tw = h->tilework();
+      tw.sel = 1;
+      launch_push_deposit_tiles<T>(g, F, P, ctl, jc, tw, ns, h->p.push, s);
+      tw.sel = 2;
+      launch_push3d<T>(g, F, P, ctl, tw, ns, h->p.push, s);
       if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
     } else if (fused && use_sort) {
       launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);

@@ -274,8 +274,10 @@ void launch_gather_push_tail(const Grid<T> &g, const Fields<T> &F, const Parts<T
 // work items (full chunks first, then each tile's partial chunk).
 struct TileWork {
   const uint32_t *key_start;   // sort counts: first slot of every cell key at the last sort
-  uint32_t *prefix;            // ntiles + 1: exclusive prefix of full chunks per tile, total last
-  uint32_t *pprefix;           // ntiles + 1: the same for the partial last chunk of each tile
+  uint32_t *dprefix;           // ntiles + 1: exclusive prefix of the chunks of dense tiles (a cell
+                               // holding more than DENSE_CELL particles), total last
+  uint32_t *prefix;            // ntiles + 1: the same for the full chunks of the other tiles
+  uint32_t *pprefix;           // ntiles + 1: the same for their last partial chunk
   uint32_t *blocksums;         // scan scratch
   int4 *items;                 // per chunk: first slot, end slot, tile
   uint32_t *flags;             // 2D: per fixed range, 1 if its node box does not fit in LDS
@@ -283,6 +285,8 @@ struct TileWork {
   int ntiles, tilecells, chunk, margin;
   int tile[3], ntile[3];
   int by_tile;                 // 1: tile items; 0: ranges of the sorted array (2D list)
+  int sel;                     // tile items a launch takes: 0 all, 1 the chunks of dense tiles,
+                               // 2 the chunks of the other tiles
 };
 void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s);
 // 2D work list after a sort: cell = the sorted particles' cells, max_ranges = ranges of
@@ -300,13 +304,14 @@ template <typename T>
 void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Parts<T> old,
                     StepCtl ctl, int n_slots, bool serial, hipStream_t s);
 
-// 3D linear-shape runs (push3d.hip): gather_push + deposit_current, one workgroup per sort
-// tile, its current summed in an LDS box of the tile's nodes (tile + 3 per axis) and added to
-// J with global atomics.  Applies to tiles of at least three cells whose box fits in LDS.
+// 3D linear-shape runs (push3d.hip): gather_push + deposit_current, one workgroup per chunk
+// of a sort tile (the work items of launch_tile_chunks), its current summed in an LDS box of
+// the tile's nodes (tile + 3 per axis) and added to J with global atomics.  Applies to tiles
+// of at least three cells whose box fits in LDS.
 bool push3d_applies(int dim, int order, const int tile[3]);
 template <typename T>
-void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw, int push,
-                   hipStream_t s);
+void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
+                   int n_slots, int push, hipStream_t s);
 
 struct SortWork {
   uint32_t *counts;      // nkeys + 1

@@ -14,6 +14,8 @@
 //
 // The fused kernel does both for one particle in registers, so x^n and x^{n+1} are
 // exactly the stored positions of consecutive steps (exact discrete continuity).
+#include <algorithm>
+
 #include "particle_core.h"
 
 namespace pmlpic {
@@ -54,7 +56,9 @@ template <> struct TileCfg<3> { static constexpr int NODES = 1344; static conste
 // tile item whose particles spread since the sort, it may instead be that box
 // clipped to the tile grown by `margin` cells per side (when the whole box does not
 // fit, or when clipping buys more replicas at the cost of at most 1/16 of the chunk),
-// and particles outside it deposit straight to global J.
+// and particles outside it deposit straight to global J.  A workgroup takes items
+// blockIdx.x, blockIdx.x + gridDim.x, ...: one item when the grid covers the list, several
+// when a short grid walks a list of unknown length (the dense tiles' chunks).
 template <typename T, int DIM, int ORDER, int PPT, bool BY_TILE>
 __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl,
                                                             JClear<T> jc, TileWork tw, int push) {
@@ -66,197 +70,202 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
   __shared__ unsigned int n_pushed, n_out;
   const int tid = threadIdx.x;
   if (DIM == 2 && jc.prev) jclear_share(g, jc);   // the other current buffer (a different array)
-  int p0, p1, t = -1;
-  {
-    // by tile: the items of the tiles; else the 2D list (heavy pieces last).  Uniform.
-    // (Giving each XCD a contiguous eighth of the 3D list cut the fetched bytes by 3x
-    // but ran 5% slower: the order below spreads the work of every region over all XCDs.)
-    const unsigned n_items = BY_TILE ? tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles] : *tw.n_items;
-    int4 item = make_int4(0, 0, -1, 0);
-    if (blockIdx.x < n_items) item = tw.items[blockIdx.x];
-    p0 = __builtin_amdgcn_readfirstlane(item.x);
-    p1 = __builtin_amdgcn_readfirstlane(item.y);
-    if (BY_TILE) t = __builtin_amdgcn_readfirstlane(item.z);
-  }
-  if (p0 >= p1) return;
-  int clo[3] = {-0x3FFFFFFF, -0x3FFFFFFF, -0x3FFFFFFF}, chi[3] = {0x3FFFFFFF, 0x3FFFFFFF, 0x3FFFFFFF};
-  if (t >= 0) {   // old cells of the tile grown by the margin
-    const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      clo[d] = tc[d] * tw.tile[d] - tw.margin;
-      chi[d] = tc[d] * tw.tile[d] + tw.tile[d] - 1 + tw.margin;
+  // by tile: the items of the tiles; else the 2D list (heavy pieces last).  Uniform.
+  // (Giving each XCD a contiguous eighth of the 3D list cut the fetched bytes by 3x
+  // but ran 5% slower: the order below spreads the work of every region over all XCDs.)
+  // (tw.sel == 1: the chunks of the dense tiles only, listed first)
+  const unsigned n_items =
+      BY_TILE ? tw.dprefix[tw.ntiles] + (tw.sel == 1 ? 0u : tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles])
+              : *tw.n_items;
+  for (unsigned it = blockIdx.x; it < n_items; it += gridDim.x) {
+    int p0, p1, t = -1;
+    {
+      const int4 item = tw.items[it];
+      p0 = __builtin_amdgcn_readfirstlane(item.x);
+      p1 = __builtin_amdgcn_readfirstlane(item.y);
+      if (BY_TILE) t = __builtin_amdgcn_readfirstlane(item.z);
     }
-  }
-  if (tid == 0) { n_pushed = 0u; n_out = 0u; }
-  if (tid < 3) {
-    sbox[tid] = 0x7FFFFFFF; sbox[3 + tid] = -0x7FFFFFFF;
-    sbox[6 + tid] = 0x7FFFFFFF; sbox[9 + tid] = -0x7FFFFFFF;
-  }
-  __syncthreads();
-  int mn[6] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
-  int mx[6] = {-0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF};
-  unsigned int out = 0u;
+    if (p0 >= p1) continue;
+    int clo[3] = {-0x3FFFFFFF, -0x3FFFFFFF, -0x3FFFFFFF}, chi[3] = {0x3FFFFFFF, 0x3FFFFFFF, 0x3FFFFFFF};
+    if (t >= 0) {   // old cells of the tile grown by the margin
+      const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int p = p0 + k * TPB + tid;
-    if (p < p1) {
-      const uint32_t c = P.cell[p];
-      if (c != DEAD) {
-        int id[3];
-        unpack_cell(DIM, c, id[0], id[1], id[2]);
-        bool in = true;
+      for (int d = 0; d < DIM; ++d) {
+        clo[d] = tc[d] * tw.tile[d] - tw.margin;
+        chi[d] = tc[d] * tw.tile[d] + tw.tile[d] - 1 + tw.margin;
+      }
+    }
+    if (tid == 0) { n_pushed = 0u; n_out = 0u; }
+    if (tid < 3) {
+      sbox[tid] = 0x7FFFFFFF; sbox[3 + tid] = -0x7FFFFFFF;
+      sbox[6 + tid] = 0x7FFFFFFF; sbox[9 + tid] = -0x7FFFFFFF;
+    }
+    __syncthreads();
+    int mn[6] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+    int mx[6] = {-0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF};
+    unsigned int out = 0u;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          mn[d] = min(mn[d], id[d]);
-          mx[d] = max(mx[d], id[d]);
-          if constexpr (BY_TILE) {
-            const int v = min(max(id[d], clo[d]), chi[d]);
-            in = in && v == id[d];
-            mn[3 + d] = min(mn[3 + d], v);
-            mx[3 + d] = max(mx[3 + d], v);
+    for (int k = 0; k < PPT; ++k) {
+      const int p = p0 + k * TPB + tid;
+      if (p < p1) {
+        const uint32_t c = P.cell[p];
+        if (c != DEAD) {
+          int id[3];
+          unpack_cell(DIM, c, id[0], id[1], id[2]);
+          bool in = true;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            mn[d] = min(mn[d], id[d]);
+            mx[d] = max(mx[d], id[d]);
+            if constexpr (BY_TILE) {
+              const int v = min(max(id[d], clo[d]), chi[d]);
+              in = in && v == id[d];
+              mn[3 + d] = min(mn[3 + d], v);
+              mx[3 + d] = max(mx[3 + d], v);
+            }
           }
+          out += in ? 0u : 1u;
         }
-        out += in ? 0u : 1u;
       }
     }
-  }
-  // reduce over the wavefront first: 256 lanes updating the same few LDS words
-  // serialise (measured: 8-17 us per workgroup in the dense 2D beam)
+    // reduce over the wavefront first: 256 lanes updating the same few LDS words
+    // serialise (measured: 8-17 us per workgroup in the dense 2D beam)
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
+    for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      mn[d] = min(mn[d], __shfl_xor(mn[d], off));
-      mx[d] = max(mx[d], __shfl_xor(mx[d], off));
-      if constexpr (BY_TILE) {
-        mn[3 + d] = min(mn[3 + d], __shfl_xor(mn[3 + d], off));
-        mx[3 + d] = max(mx[3 + d], __shfl_xor(mx[3 + d], off));
+      for (int d = 0; d < DIM; ++d) {
+        mn[d] = min(mn[d], __shfl_xor(mn[d], off));
+        mx[d] = max(mx[d], __shfl_xor(mx[d], off));
+        if constexpr (BY_TILE) {
+          mn[3 + d] = min(mn[3 + d], __shfl_xor(mn[3 + d], off));
+          mx[3 + d] = max(mx[3 + d], __shfl_xor(mx[3 + d], off));
+        }
       }
+      if constexpr (BY_TILE) out += __shfl_xor(out, off);
     }
-    if constexpr (BY_TILE) out += __shfl_xor(out, off);
-  }
-  if ((tid & 63) == 0) {
+    if ((tid & 63) == 0) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (mn[d] <= mx[d]) {
-        atomicMin(&sbox[d], mn[d]); atomicMax(&sbox[3 + d], mx[d]);
-        if constexpr (BY_TILE) { atomicMin(&sbox[6 + d], mn[3 + d]); atomicMax(&sbox[9 + d], mx[3 + d]); }
+      for (int d = 0; d < DIM; ++d) {
+        if (mn[d] <= mx[d]) {
+          atomicMin(&sbox[d], mn[d]); atomicMax(&sbox[3 + d], mx[d]);
+          if constexpr (BY_TILE) { atomicMin(&sbox[6 + d], mn[3 + d]); atomicMax(&sbox[9 + d], mx[3 + d]); }
+        }
       }
+      if (BY_TILE && out) atomicAdd(&n_out, out);
     }
-    if (BY_TILE && out) atomicAdd(&n_out, out);
-  }
-  __syncthreads();
-  int sb[12];   // the box words, wave-uniform (scalar registers)
+    __syncthreads();
+    int sb[12];   // the box words, wave-uniform (scalar registers)
 #pragma unroll
-  for (int k = 0; k < 12; ++k) sb[k] = __builtin_amdgcn_readfirstlane(sbox[k]);
-  if (DIM == 2 && ctl.jslot && tid == 0 && sb[0] <= sb[3])   // nodes this chunk can deposit to
-    jslot_merge(ctl.jslot, sb[0] + WLO, sb[3] + WHI, sb[1] + WLO, sb[4] + WHI);
-  LdsSink<T> lsink;
-  const bool any = sb[0] <= sb[3];
-  // replicas that fit for a box of n nodes per component (0: does not fit)
-  auto reps = [&](long n) {
-    const long st = (3 * n) | 1;
-    int r = 0;
-    while (r < 16 && (r ? 2 * r : 1) * st <= 3 * NODES) r = r ? 2 * r : 1;
-    return r;
-  };
-  int o = 0;   // 0: whole bounding box; 6: clipped box, particles outside it go global
-  if (BY_TILE && any) {
-    long full = 1, clip = 1;
+    for (int k = 0; k < 12; ++k) sb[k] = __builtin_amdgcn_readfirstlane(sbox[k]);
+    if (DIM == 2 && ctl.jslot && tid == 0 && sb[0] <= sb[3])   // nodes this chunk can deposit to
+      jslot_merge(ctl.jslot, sb[0] + WLO, sb[3] + WHI, sb[1] + WLO, sb[4] + WHI);
+    LdsSink<T> lsink;
+    const bool any = sb[0] <= sb[3];
+    // replicas that fit for a box of n nodes per component (0: does not fit)
+    auto reps = [&](long n) {
+      const long st = (3 * n) | 1;
+      int r = 0;
+      while (r < 16 && (r ? 2 * r : 1) * st <= 3 * NODES) r = r ? 2 * r : 1;
+      return r;
+    };
+    int o = 0;   // 0: whole bounding box; 6: clipped box, particles outside it go global
+    if (BY_TILE && any) {
+      long full = 1, clip = 1;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      full *= sb[3 + d] - sb[d] + (WHI - WLO) + 1;
-      clip *= sb[9 + d] - sb[6 + d] + (WHI - WLO) + 1;
+      for (int d = 0; d < DIM; ++d) {
+        full *= sb[3 + d] - sb[d] + (WHI - WLO) + 1;
+        clip *= sb[9 + d] - sb[6 + d] + (WHI - WLO) + 1;
+      }
+      const int rf = reps(full), rc = reps(clip);
+      const unsigned nout = __builtin_amdgcn_readfirstlane(n_out);
+      // the clipped box wins if the whole one does not fit, or if it allows more
+      // replicas at the price of at most 1/16 of the chunk going to global memory
+      if (rf == 0 || (rc > rf && 16u * nout <= (unsigned)(p1 - p0))) o = 6;
     }
-    const int rf = reps(full), rc = reps(clip);
-    const unsigned nout = __builtin_amdgcn_readfirstlane(n_out);
-    // the clipped box wins if the whole one does not fit, or if it allows more
-    // replicas at the price of at most 1/16 of the chunk going to global memory
-    if (rf == 0 || (rc > rf && 16u * nout <= (unsigned)(p1 - p0))) o = 6;
-  }
-  int ext[3] = {1, 1, 1}, bmn[3] = {0, 0, 0}, bmx[3] = {0, 0, 0};
-  long total = 1;   // 64-bit: the box of a sparse range can exceed 2^31 nodes
+    int ext[3] = {1, 1, 1}, bmn[3] = {0, 0, 0}, bmx[3] = {0, 0, 0};
+    long total = 1;   // 64-bit: the box of a sparse range can exceed 2^31 nodes
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (d < DIM) {
-      bmn[d] = o ? sb[6 + d] : sb[d];
-      bmx[d] = o ? sb[9 + d] : sb[3 + d];
-      lsink.lo[d] = bmn[d] + WLO;
-      ext[d] = any ? bmx[d] - bmn[d] + (WHI - WLO) + 1 : 1;
-    } else {
-      lsink.lo[d] = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (d < DIM) {
+        bmn[d] = o ? sb[6 + d] : sb[d];
+        bmx[d] = o ? sb[9 + d] : sb[3 + d];
+        lsink.lo[d] = bmn[d] + WLO;
+        ext[d] = any ? bmx[d] - bmn[d] + (WHI - WLO) + 1 : 1;
+      } else {
+        lsink.lo[d] = 0;
+      }
+      total *= ext[d];
     }
-    total *= ext[d];
-  }
-  const long lstride = (3 * total) | 1;
-  const bool use_lds = any && lstride <= 3 * NODES;
-  // past this point the box sizes are used only when the box fits in LDS (int range)
-  const int stride = use_lds ? (int)lstride : 1;
-  int R = 1;
-  while (use_lds && R < 16 && 2 * R * stride <= 3 * NODES) R *= 2;
-  lsink.e0 = ext[0];
-  lsink.e01 = use_lds ? ext[0] * ext[1] : 0;
-  lsink.total = use_lds ? (int)total : 0;
-  if (use_lds) {
-    for (int e = tid; e < R * stride; e += TPB) lds[e] = 0.0;
-  }
-  lsink.lds = lds + (tid % R) * stride;
-  __syncthreads();
-  GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+    const long lstride = (3 * total) | 1;
+    const bool use_lds = any && lstride <= 3 * NODES;
+    // past this point the box sizes are used only when the box fits in LDS (int range)
+    const int stride = use_lds ? (int)lstride : 1;
+    int R = 1;
+    while (use_lds && R < 16 && 2 * R * stride <= 3 * NODES) R *= 2;
+    lsink.e0 = ext[0];
+    lsink.e01 = use_lds ? ext[0] * ext[1] : 0;
+    lsink.total = use_lds ? (int)total : 0;
+    if (use_lds) {
+      for (int e = tid; e < R * stride; e += TPB) lds[e] = 0.0;
+    }
+    lsink.lds = lds + (tid % R) * stride;
+    __syncthreads();
+    GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
 #pragma unroll 1
-  for (int k = 0; k < PPT; ++k) {
-    const int p = p0 + k * TPB + tid;
-    bool active = false;
-    if (p < p1) {
-      const uint32_t c = P.cell[p];
-      if (c != DEAD) {
-        active = true;
-        int id[3];
-        unpack_cell(DIM, c, id[0], id[1], id[2]);
-        bool inbox = use_lds;
+    for (int k = 0; k < PPT; ++k) {
+      const int p = p0 + k * TPB + tid;
+      bool active = false;
+      if (p < p1) {
+        const uint32_t c = P.cell[p];
+        if (c != DEAD) {
+          active = true;
+          int id[3];
+          unpack_cell(DIM, c, id[0], id[1], id[2]);
+          bool inbox = use_lds;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) inbox = inbox && id[d] >= bmn[d] && id[d] <= bmx[d];
-        T f[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
-        T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
-        if (push) {
-          T EB[6];
-          gather<T, DIM, ORDER>(g, F, id, f, EB);
-          boris(g.qdt_2m, EB, u);
+          for (int d = 0; d < DIM; ++d) inbox = inbox && id[d] >= bmn[d] && id[d] <= bmx[d];
+          T f[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
+          T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+          if (push) {
+            T EB[6];
+            gather<T, DIM, ORDER>(g, F, id, f, EB);
+            boris(g.qdt_2m, EB, u);
+          }
+          const int id0[3] = {id[0], id[1], id[2]};
+          const T f0[3] = {f[0], f[1], f[2]};
+          T ig;
+          const bool inside = move<T, DIM>(g, id, f, u, ig);
+          P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
+          const T qw = deposit_charge<T, DIM>(g, P, p, id0, f0, id, f);
+          if (inbox) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
+          else deposit<T, DIM, ORDER>(g, gsink, id0, f0, id, f, u[2] * ig, qw);
+          P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
         }
-        const int id0[3] = {id[0], id[1], id[2]};
-        const T f0[3] = {f[0], f[1], f[2]};
-        T ig;
-        const bool inside = move<T, DIM>(g, id, f, u, ig);
-        P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
-        const T qw = deposit_charge<T, DIM>(g, P, p, id0, f0, id, f);
-        if (inbox) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
-        else deposit<T, DIM, ORDER>(g, gsink, id0, f0, id, f, u[2] * ig, qw);
-        P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
+      }
+      const unsigned long long m = __ballot(active);
+      if ((tid & 63) == 0 && m) atomicAdd(&n_pushed, (unsigned int)__popcll(m));
+    }
+    __syncthreads();
+    if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
+    if (use_lds) {
+      const int ntot = lsink.total;
+      for (int e = tid; e < 3 * ntot; e += TPB) {
+        double acc = lds[e];
+        for (int r = 1; r < R; ++r) acc += lds[r * stride + e];
+        const T v = (T)acc;
+        if (v == T(0)) continue;
+        const int comp = e / ntot;
+        int r = e - comp * ntot;
+        const int i = r % ext[0];
+        r /= ext[0];
+        const int j = r % ext[1];
+        const int kk = r / ext[1];
+        atomic_add(&F.J[comp][g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk)], v);
       }
     }
-    const unsigned long long m = __ballot(active);
-    if ((tid & 63) == 0 && m) atomicAdd(&n_pushed, (unsigned int)__popcll(m));
-  }
-  __syncthreads();
-  if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
-  if (use_lds) {
-    const int ntot = lsink.total;
-    for (int e = tid; e < 3 * ntot; e += TPB) {
-      double acc = lds[e];
-      for (int r = 1; r < R; ++r) acc += lds[r * stride + e];
-      const T v = (T)acc;
-      if (v == T(0)) continue;
-      const int comp = e / ntot;
-      int r = e - comp * ntot;
-      const int i = r % ext[0];
-      r /= ext[0];
-      const int j = r % ext[1];
-      const int kk = r / ext[1];
-      atomic_add(&F.J[comp][g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk)], v);
-    }
+    __syncthreads();   // the next item reuses the box and the counters
   }
 }
 
@@ -372,30 +381,55 @@ __device__ __forceinline__ void tile_range(const TileWork &tw, int t, const int3
   s = tw.key_start[(size_t)t * tw.tilecells];
   e = t + 1 < tw.ntiles ? tw.key_start[(size_t)(t + 1) * tw.tilecells] : (uint32_t)*count;
 }
-__global__ void k_tile_chunks(TileWork tw, const int32_t *count) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= tw.ntiles) return;
+// A tile is dense when one of its cells holds more than DENSE_CELL particles (a beam whose
+// particles crowd a few cells: lanes of a wavefront would add into the same few nodes of a
+// box spanning the whole tile).  Chunks are `chunk` particles of one tile's sorted range,
+// the last one partial.  The list holds the chunks of the dense tiles first (dprefix counts
+// them per tile), then the full chunks of the other tiles (prefix), then the other tiles'
+// last partial chunks (pprefix): long items first, the short ones finish the launch.
+constexpr uint32_t DENSE_CELL = 16;
+// one wavefront per tile: its cells' counts from the key starts, reduced to the largest
+__global__ void __launch_bounds__(256) k_tile_chunks(TileWork tw, const int32_t *count) {
+  const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= tw.ntiles) return;   // uniform over the wavefront
   uint32_t s, e;
   tile_range(tw, t, count, s, e);
   const uint32_t n = e > s ? e - s : 0u;
-  tw.prefix[t] = n / tw.chunk;
-  tw.pprefix[t] = n % tw.chunk ? 1u : 0u;
+  uint32_t big = 0;
+  if (n > DENSE_CELL) {   // key_start[n_keys] is the sorted count
+    const size_t k0 = (size_t)t * tw.tilecells;
+    for (int c = lane; c < tw.tilecells; c += 64) big = max(big, tw.key_start[k0 + c + 1] - tw.key_start[k0 + c]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) big = max(big, (uint32_t)__shfl_xor((int)big, off));
+  }
+  if (lane == 0) {
+    const bool dense = big > DENSE_CELL;
+    const uint32_t nfull = n / tw.chunk, part = n % tw.chunk ? 1u : 0u;
+    tw.dprefix[t] = dense ? nfull + part : 0u;
+    tw.prefix[t] = dense ? 0u : nfull;
+    tw.pprefix[t] = dense ? 0u : part;
+  }
 }
-// one work item per chunk, after the scans: every full chunk first, then the partial
-// last chunks of the tiles (the short items finish the launch instead of a long one)
+// one work item per chunk, after the scans
 __global__ void k_tile_items(TileWork tw, const int32_t *count) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= tw.ntiles) return;
   uint32_t s, e;
   tile_range(tw, t, count, s, e);
+  const uint32_t nd = tw.dprefix[tw.ntiles], nf = tw.prefix[tw.ntiles];
+  if (tw.dprefix[t + 1] > tw.dprefix[t]) {   // dense: every chunk in the first section
+    for (uint32_t c = 0, p = s; p < e; ++c, p += tw.chunk)
+      tw.items[tw.dprefix[t] + c] = make_int4((int)p, (int)min(e, p + (uint32_t)tw.chunk), t, 0);
+    return;
+  }
   const uint32_t nfull = e > s ? (e - s) / tw.chunk : 0u;
-  const uint32_t first = tw.prefix[t];
   for (uint32_t c = 0; c < nfull; ++c) {
     const uint32_t p = s + c * tw.chunk;
-    tw.items[first + c] = make_int4((int)p, (int)(p + tw.chunk), t, 0);
+    tw.items[nd + tw.prefix[t] + c] = make_int4((int)p, (int)(p + tw.chunk), t, 0);
   }
   const uint32_t p = s + nfull * tw.chunk;
-  if (p < e) tw.items[tw.prefix[tw.ntiles] + tw.pprefix[t]] = make_int4((int)p, (int)e, t, 0);
+  if (p < e) tw.items[nd + nf + tw.pprefix[t]] = make_int4((int)p, (int)e, t, 0);
 }
 
 // second half of the unfused particle step: deposit from the saved x^n to x^{n+1}
@@ -522,7 +556,11 @@ void launch_push_deposit_tiles(const Grid<T> &g, const Fields<T> &F, const Parts
   if (n_slots <= 0) return;
   // an upper bound of the item count: by tile, every tile's last chunk may be partial;
   // else every range may be split
-  const long nb = deposit_blocks<T>(g, tw, n_slots, true);
+  // tw.sel == 1: the dense tiles' chunks, whose number only the device knows (none in most
+  // runs): a grid of a few workgroups per compute unit walks them
+  const long nb = tw.sel == 1 ? std::min<long>(1024, deposit_blocks<T>(g, tw, n_slots, true))
+                              : deposit_blocks<T>(g, tw, n_slots, true);
+  if (nb <= 0) return;
   dim3 blk(TPB), grd((unsigned)nb);
 #define PMLPIC_TILES(DIMV, ORD)                                                                                \
   do {                                                                                                         \
@@ -808,16 +846,13 @@ int tiled_chunk(int dim) { return TPB * (dim == 2 ? TileCfg<2>::PPT : TileCfg<3>
 int tiled_nodes(int dim) { return dim == 2 ? TileCfg<2>::NODES : TileCfg<3>::NODES; }
 
 void launch_tile_chunks(const TileWork &tw, const int32_t *count, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_chunks, dim3((tw.ntiles + 255) / 256), dim3(256), 0, s, tw, count);
+  hipLaunchKernelGGL(k_tile_chunks, dim3((tw.ntiles + 3) / 4), dim3(256), 0, s, tw, count);
   const int nb = (tw.ntiles + SCAN_TILE - 1) / SCAN_TILE;
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.prefix, tw.ntiles, tw.blocksums);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, tw.blocksums, nb,
-                     (int32_t *)(tw.prefix + tw.ntiles));
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.prefix, tw.ntiles, tw.blocksums);
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.pprefix, tw.ntiles, tw.blocksums);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, tw.blocksums, nb,
-                     (int32_t *)(tw.pprefix + tw.ntiles));
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, tw.pprefix, tw.ntiles, tw.blocksums);
+  for (uint32_t *a : {tw.dprefix, tw.prefix, tw.pprefix}) {   // exclusive scans, totals last
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_BLOCK), 0, s, a, tw.ntiles, tw.blocksums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, s, tw.blocksums, nb, (int32_t *)(a + tw.ntiles));
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, a, tw.ntiles, tw.blocksums);
+  }
   hipLaunchKernelGGL(k_tile_items, dim3((tw.ntiles + 255) / 256), dim3(256), 0, s, tw, count);
 }
 

@@ -1,12 +1,13 @@
-// gather_push + deposit_current for 3D runs with the linear shape, one workgroup per sort
-// tile.
+// gather_push + deposit_current for 3D runs with the linear shape, one workgroup per chunk of
+// a sort tile.
 //
 // The step is the one of particles.hip (gather of the total fields, Eq. MaxwellSum;
 // relativistic Boris; move; Esirkepov's charge-conserving current, used in App. A).  One
-// workgroup takes one sort tile (tile[0] x tile[1] x tile[2] cells) and all of its
-// particles, accumulates their current in an LDS box of the nodes (tile + 3 per axis) that
-// particles in the tile or one cell beyond it can reach, and adds the box's non-zero entries
-// to J with global atomics.  A move that stays in its cell along every axis (the thermal
+// workgroup takes one work item: a chunk of up to tw.chunk particles of one sort tile
+// (tile[0] x tile[1] x tile[2] cells; a tile at one particle per cell is one item; tiles of a
+// dense beam go to the replicated-box kernel of particles.hip), accumulates their current in an LDS box of the nodes (tile + 3 per
+// axis) that particles in the tile or one cell beyond it can reach, and adds the box's
+// non-zero entries to J with global atomics.  A move that stays in its cell along every axis (the thermal
 // background: about 96%) takes a 12-value form of Esirkepov's current; moves across a cell
 // face are queued in LDS and deposited after the loop with the general window, so that
 // wavefronts do not run both forms side by side; a move that leaves the tile's one-cell
@@ -53,9 +54,12 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
   }
 }
 
-// Workgroup b takes sort tile b (tiles numbered x fastest: neighbouring workgroups share
-// the cache lines of their fields and currents).  TS > 0: cubic tiles of TS cells known at
-// compile time (the box strides become immediates); 0: the tile shape of tw.
+// Workgroup b takes work item b of the list built after the sort (with tw.sel == 2, of the
+// part listing the tiles that are not dense: their full chunks, then their partial ones in
+// tile order, x fastest; at one particle per cell every tile is one partial chunk and
+// neighbouring workgroups take neighbouring tiles, sharing the cache lines of their fields
+// and currents).  TS > 0: cubic tiles of TS cells known at compile time (the box
+// strides become immediates); 0: the tile shape of tw.
 template <typename T, int TS>
 __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
                                                          int push) {
@@ -70,13 +74,17 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
   __shared__ T q_f0[3][P3_QCAP], q_f1[3][P3_QCAP], q_qw[P3_QCAP];
   __shared__ unsigned char q_glob[P3_QCAP];
   const int tid = threadIdx.x;
-  const int t = (int)blockIdx.x;
+  // the items of the last sort (particles injected since then form an unsorted tail pushed
+  // by another kernel); the grid is an upper bound of their number.  With tw.sel == 2 only
+  // the chunks of tiles that are not dense (dense tiles go to the kernel of particles.hip,
+  // whose replicated LDS box fits the chunk instead of the tile: a dense beam's lanes would
+  // otherwise meet on a few nodes of the tile box)
+  const unsigned first = tw.sel == 2 ? tw.dprefix[tw.ntiles] : 0u;
+  if (first + blockIdx.x >= tw.dprefix[tw.ntiles] + tw.prefix[tw.ntiles] + tw.pprefix[tw.ntiles]) return;
+  const int4 item = tw.items[first + blockIdx.x];
+  const int t = item.z;
   const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
-  // the tile's range at the last sort (key_start[n_keys] is the sorted count; particles
-  // injected since then form an unsorted tail pushed by another kernel)
-  const uint32_t s = tw.key_start[(size_t)t * tw.tilecells];
-  const uint32_t e = tw.key_start[(size_t)(t + 1) * tw.tilecells];
-  if (s >= e) return;   // uniform: an empty tile
+  const uint32_t s = (uint32_t)item.x, e = (uint32_t)item.y;
   // cells [T0, T0 + tile) of the tile; particles in [T0 - 1, T0 + tile] at both ends of their
   // move deposit into the box of nodes [T0 - 1, T0 + tile + 1]
   int T0[3], ext[3], st[3], tl[3];
@@ -224,18 +232,20 @@ bool push3d_applies(int dim, int order, const int tile[3]) {
 }
 
 template <typename T>
-void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw, int push,
-                   hipStream_t s) {
-  if (tw.ntiles <= 0) return;
+void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
+                   int n_slots, int push, hipStream_t s) {
+  if (tw.ntiles <= 0 || n_slots <= 0) return;
+  // items: at most one partial chunk per tile, plus the full chunks of the slots
+  const unsigned nb = (unsigned)(tw.ntiles + (n_slots + tw.chunk - 1) / tw.chunk);
   if (tw.tile[0] == 8 && tw.tile[1] == 8 && tw.tile[2] == 8)
-    hipLaunchKernelGGL((k_push3d_tiles<T, 8>), dim3((unsigned)tw.ntiles), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+    hipLaunchKernelGGL((k_push3d_tiles<T, 8>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
   else
-    hipLaunchKernelGGL((k_push3d_tiles<T, 0>), dim3((unsigned)tw.ntiles), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+    hipLaunchKernelGGL((k_push3d_tiles<T, 0>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
 }
 
 template void launch_push3d<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &, StepCtl,
-                                   const TileWork &, int, hipStream_t);
+                                   const TileWork &, int, int, hipStream_t);
 template void launch_push3d<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &, StepCtl,
-                                    const TileWork &, int, hipStream_t);
+                                    const TileWork &, int, int, hipStream_t);
 
 }  // namespace pmlpic
