@@ -26,6 +26,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# the HIP kernels behind a timed phase (phase, dim, shape order), for the roofline record
+PHASE_KERNELS = {
+    ("gather_push", 3, 1): "k_push3d_tiles (tiles that are not dense) + k_push_deposit_tiles (dense tiles)",
+    ("gather_push", 2, 2): "k_push_deposit_tiles",
+    ("update_yee_pml", 3, 1): "k_fused_3d",
+    ("update_yee_pml", 2, 2): "k_fused_2d",
+}
+
 
 def kernel_source_hash():
     """Hash of the kernel and launcher sources (the host control in api.hip launches them but
@@ -323,8 +331,12 @@ def main():
                 "timing": "HIP events around each kernel phase on the library stream, in a second run "
                           "of the same inputs through the same warm-up and %d timed steps" % n_prof}
         if name == "gather_push":
-            roof["model"] = "%d B/push + %d B/occupied cell (fields read, current written), %d occupied cells" % (
-                (60 if cfg.dim == 3 else 52) * esz // 4, 9 * esz, occ)
+            roof["model"] = "%d B/push" % ((60 if cfg.dim == 3 else 52) * esz // 4) + (
+                " + %d B/occupied cell (fields read, current written), %d occupied cells" % (9 * esz, occ)
+                if occ else "")
+        kern = PHASE_KERNELS.get((name, cfg.dim, cfg.shape_order))
+        if kern:
+            roof["kernels"] = kern
         roof["traffic"] = traffic_bytes(args.workload, name, args.precision)
 
     srf = None
