@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 
-from gpu_helpers import both, compare_current, compare_fields, compare_particles, say
+from gpu_helpers import both, compare_current, compare_fields, compare_particles, rel_err, rel_l2, say
 from paper_2201_09084_amd import binding as B
 from paper_2201_09084_amd import workloads as W
 
@@ -442,3 +442,43 @@ def test_dense_and_sparse_ranges_2d():
         compare_fields(g, o, cfg, 1e-10, "step %d" % (5 * k + 5))
         compare_current(g, o, 1e-10, "step %d" % (5 * k + 5))
         compare_particles(g, o, 1e-10, 1e-10, "step %d" % (5 * k + 5))
+
+
+@pytest.mark.parametrize("dim,order,precision", [(2, 2, 64), (3, 1, 64), (3, 1, 32)])
+def test_restart_from_exported_state(dim, order, precision):
+    """Checkpoint and resume through the state calls: 9 steps in one run equal 4 steps, an
+    export of the fields (every split part), the particles (ids, positions, momenta, weights)
+    and the partner density, an import into a new run and 5 more steps.  The runs differ only
+    in the order of their atomic adds (the new run sorts at its first step), so FP64 agrees to
+    relative 1e-12 and FP32 to its rounding (relative L2 1e-6 per component)."""
+    cfg, parts, fields = _random_case(dim, order, seed=900 + dim, n_particles=400, precision=precision)
+    def fresh():
+        g = B.PmlPic(cfg, max_particles=len(parts.w))
+        g.set_split_fields(fields)
+        g.add_particles(parts.x, parts.u, parts.w)
+        return g
+    a, b = fresh(), fresh()
+    a.step(9)
+    b.step(4)
+    F, (ids, X, u, w), rho = b.split_fields(), b.particles(), b.rho_static()
+    c = B.PmlPic(cfg, max_particles=len(parts.w))
+    c.set_split_fields(F)
+    c.set_particles(ids, X, u, w)
+    c.set_rho_static(rho)
+    c.step(5)
+    Fa, Fc = a.fields(), c.fields()
+    if precision == 64:
+        worst = max(rel_err(Fc[k], Fa[k]) for k in range(6) if np.max(np.abs(Fa[k])) > 0)
+        assert worst <= 1e-12, worst
+    else:
+        worst = max(rel_l2(Fc[k], Fa[k]) for k in range(6) if np.max(np.abs(Fa[k])) > 0)
+        assert worst <= 1e-6, worst
+    ia, Xa, ua, _ = a.particles()
+    ic, Xc, uc, _ = c.particles()
+    assert np.array_equal(ia, ic)
+    tol = 1e-10 if precision == 64 else 1e-4
+    assert np.max(np.abs(Xa - Xc)) <= tol and np.max(np.abs(ua - uc)) <= tol
+    da, dc = a.diagnose(), c.diagnose()
+    assert da["n_particles"] == dc["n_particles"]
+    assert abs(da["u_interior"] - dc["u_interior"]) <= (1e-12 if precision == 64 else 1e-5) * abs(da["u_interior"])
+    say("restart", dim, precision, "worst field difference", worst)
