@@ -537,7 +537,10 @@ static int levi(int a, int b, int c)
  * into the part damped by sigma_z and the longitudinal one into the (undamped)
  * E_z.  Reading for every face, edge and corner: weight sigma_b/(sigma_b+sigma_c);
  * where both vanish the whole current goes to the part with b = a+1 (mod 3); there
- * both parts are undamped, so only their sum matters. */
+ * both parts are undamped, so only their sum matters.  Pins: the exit-error ordering at
+ * 60 degrees (a transverse current in the undamped part breaks it) and the x-y mirror
+ * symmetry of an edge and corner run; parity unpinned beyond them (another rule that is
+ * symmetric in b and c and equals the face assignment would pass both). */
 static double source_weight(int a, int b, double sb, double sc)
 {
     if (sb + sc > 0.0) return sb / (sb + sc);

@@ -282,3 +282,84 @@ def test_interior_field_is_the_moving_charge_field(p9_reference):
     print("moving-charge field deviation %.4f (analytic charge a quarter cell ahead: %.4f)" % (devs[0.0], devs[0.25]))
     assert devs[0.0] < 0.045
     assert devs[0.25] > 2 * devs[0.0]
+
+
+# ------------------------------------------------------------------ edges and corners
+def _mirror_xy(F):
+    """The split state of the run mirrored in the plane x = y (x and y exchanged): E is a
+    vector, B a pseudovector (its mirror image changes sign).  Parts in the order Exy Exz Eyz
+    Eyx Ezx Ezy Bxy Bxz Byz Byx Bzx Bzy; each sample array (nz, ny, nx) is transposed in its
+    last two axes, which maps the staggered sample of one component onto its partner's."""
+    T = lambda a: a.transpose(0, 2, 1)
+    swap = [3, 2, 1, 0, 5, 4, 9, 8, 7, 6, 11, 10]
+    sign = [1] * 6 + [-1] * 6
+    return np.stack([sign[p] * T(F[swap[p]]) for p in range(12)])
+
+
+def _split_active(sim, shape):
+    """Per part, the samples where its component is split (sigma_b + sigma_c > 0 at the
+    sample); elsewhere both parts are undamped and only their sum is defined."""
+    nz, ny, nx = shape
+    masks = []
+    for p in range(12):
+        comp = p // 2
+        a = comp % 3
+        is_e = comp < 3
+        tot = np.zeros(shape)
+        for d in range(3):
+            if d == a:
+                continue
+            half = 0.0 if is_e else 0.5   # E_a sits on nodes across a, B_a between them
+            n = (nx, ny, nz)[d]
+            sig = np.array([sim.sigma(d, i + half) for i in range(n)])
+            shp = [1, 1, 1]
+            shp[2 - d] = n
+            tot = tot + sig.reshape(shp)
+        masks.append(tot > 0)
+    return masks
+
+
+def _edge_run(coef_y):
+    cfg = W.SimConfig(dim=3, n=(14, 14, 10), pml=((6, 6), (6, 6), (5, 5)), dt=0.45, shape_order=2,
+                      alpha_mode=W.ALPHA_DAMPED, damping_scale=1.0 / 0.6,
+                      sigma_coef=((0.0, 0.0, 0.0, 3.2), coef_y, (0.0, 0.0, 2.0)), push=0)
+    d = np.array([1.0, 1.0, 0.7])
+    d /= np.linalg.norm(d)
+    g = 1.0 / math.sqrt(1.0 - 0.6 ** 2)
+    sim = oracle.OracleSim(cfg)
+    sim.add_particles(np.array([[9.0, 9.0, 5.0]]), (g * 0.6 * d)[None, :], np.array([1.0]))
+    sim.step(55)
+    return sim
+
+
+def _asymmetry(sim):
+    F = sim.split_fields()
+    M = _mirror_xy(F)
+    tot = F[0::2] + F[1::2]
+    mtot = M[0::2] + M[1::2]
+    scale = np.max(np.abs(tot))
+    a_tot = np.max(np.abs(tot - mtot)) / scale
+    masks = _split_active(sim, F.shape[1:])
+    a_part = max(np.max(np.abs((F[p] - M[p])[masks[p]]), initial=0.0) for p in range(12)) / scale
+    return a_tot, a_part
+
+
+def test_edge_and_corner_fields_are_mirror_symmetric():
+    """A charge moving along (1, 1, 0.7) through the +x +y edge into the +x +y +z corner of a 3D
+    PML whose x and y profiles are equal: the setup is symmetric under the exchange of x and y,
+    so the fields must be too (E_x <-> E_y, E_z even, B_x <-> -B_y, B_z odd), and so must the
+    split parts wherever a component is split (E_xy <-> E_yx, E_xz <-> E_yz, ...; where
+    sigma_b + sigma_c = 0 both parts are undamped and only their sum is defined).  This pins the
+    edge and corner updates against any mistake that treats x and y differently: a transposed
+    index or operand, a dropped or sign-flipped term in one component's split update, alpha or
+    the current's share taken along the wrong axis.  The same run with the y profile 3% steeper
+    breaks the symmetry by many orders of magnitude more than rounding does."""
+    sim = _edge_run((0.0, 0.0, 0.0, 3.2))
+    X = sim.particles()[1][0]
+    assert X[0] > 14 + 6 + 2 and X[1] > 14 + 6 + 2 and X[2] > 10 + 5 + 1   # in the corner region
+    a_tot, a_part = _asymmetry(sim)
+    b_tot, b_part = _asymmetry(_edge_run((0.0, 0.0, 0.0, 3.3)))
+    print("mirror asymmetry: totals %.2e, split parts %.2e (equal profiles); %.2e, %.2e (y 3%% steeper)"
+          % (a_tot, a_part, b_tot, b_part))
+    assert a_tot <= 1e-13 and a_part <= 1e-13
+    assert b_tot > 1e6 * max(a_tot, 1e-16) and b_part > 1e6 * max(a_part, 1e-16)
