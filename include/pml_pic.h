@@ -291,7 +291,8 @@ int pml_pic_get_particles(pml_pic_handle *h, int64_t cap, int64_t *ids, double *
 
 /* Replaces all particles by the given ones (grid coordinates as above); the static
  * partner density is left as it is; with PML_ALPHA_WEIGHT their damping integrals
- * restart at zero. */
+ * restart at zero.  Ids must lie in [0, 2^31) (PML_PIC_E_INVALID_ARG otherwise); the
+ * pushed adjoint needs them below max_particles. */
 int pml_pic_set_particles(pml_pic_handle *h, int64_t n, const int64_t *ids, const double *X,
                           const double *u, const double *w);
 

@@ -293,13 +293,14 @@ __device__ __forceinline__ void cross(const T (&a)[3], const T (&b)[3], T (&o)[3
 
 template <typename T, int DIM, int ORDER>
 __global__ void __launch_bounds__(256) k_adj_particles(Grid<T> g, Fields<T> Fn, Parts<T> P, const int32_t *count,
-                                                      int ns, AdjFields<T> L, const T *LJx, const T *LJy,
+                                                      int ns, int cap, AdjFields<T> L, const T *LJx, const T *LJy,
                                                       const T *LJz, PartAdj<T> A) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ns || p >= *count) return;
   const uint32_t cell = P.cell[p];
   if (cell == DEAD) return;
   const int pid = P.id[p];
+  if (pid < 0 || pid >= cap) return;   // ids are below the capacity (checked by the host)
   int i0[3];
   unpack_cell(DIM, cell, i0[0], i0[1], i0[2]);
   const T f0[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
@@ -407,11 +408,11 @@ __global__ void __launch_bounds__(256) k_adj_particles(Grid<T> g, Fields<T> Fn, 
 
 template <typename T>
 void launch_adj_particles(const Grid<T> &g, const Fields<T> &Fn, const Parts<T> &P, const int32_t *count, int ns,
-                          const AdjFields<T> &L, T *const LJ[3], const PartAdj<T> &A, hipStream_t s) {
+                          int cap, const AdjFields<T> &L, T *const LJ[3], const PartAdj<T> &A, hipStream_t s) {
   if (ns <= 0) return;
   const dim3 blk(256), grd((ns + 255) / 256);
 #define PMLPIC_ADJP(D, O) \
-  hipLaunchKernelGGL((k_adj_particles<T, D, O>), grd, blk, 0, s, g, Fn, P, count, ns, L, LJ[0], LJ[1], LJ[2], A)
+  hipLaunchKernelGGL((k_adj_particles<T, D, O>), grd, blk, 0, s, g, Fn, P, count, ns, cap, L, LJ[0], LJ[1], LJ[2], A)
   if (g.dim == 2) {
     if (g.order == 1) PMLPIC_ADJP(2, 1);
     else if (g.order == 2) PMLPIC_ADJP(2, 2);
@@ -425,10 +426,10 @@ void launch_adj_particles(const Grid<T> &g, const Fields<T> &Fn, const Parts<T> 
 }
 
 template void launch_adj_particles<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &,
-                                          const int32_t *, int, const AdjFields<float> &, float *const[3],
+                                          const int32_t *, int, int, const AdjFields<float> &, float *const[3],
                                           const PartAdj<float> &, hipStream_t);
 template void launch_adj_particles<double>(const Grid<double> &, const Fields<double> &, const Parts<double> &,
-                                           const int32_t *, int, const AdjFields<double> &, double *const[3],
+                                           const int32_t *, int, int, const AdjFields<double> &, double *const[3],
                                            const PartAdj<double> &, hipStream_t);
 
 }  // namespace pmlpic

@@ -732,6 +732,10 @@ int write_particles(pml_pic_handle *h, int64_t at_slot, int64_t n, const int64_t
     cell[t] = pack_cell(dim, ic[0], ic[1], ic[2]);
     for (int d = 0; d < 3; ++d) { f[d][t] = ff[d]; uu[d][t] = (T)u[3 * t + d]; }
     ww[t] = (T)w[t];
+    if (ids && (ids[t] < 0 || ids[t] > INT32_MAX)) {
+      h->err = "particle " + std::to_string(t) + " has an id outside [0, 2^31)";
+      return PML_PIC_E_INVALID_ARG;
+    }
     id[t] = ids ? (int32_t)ids[t] : (int32_t)(h->n_added + t);
   }
   const int b = h->cur;
@@ -2111,7 +2115,7 @@ int backward_t(pml_pic_handle *h, const double *seed, double *lambda_out, double
         Pk.lam = nullptr;
         Pk.id = (int32_t *)(h->ws + rel + L.off_id[0]);
         launch_adj_particles<T>(g, Fn, Pk, (const int32_t *)(h->ws + L.off_seg_count + 4 * (size_t)k),
-                                (int)seg_ns[k], A, LJ, PA, s);
+                                (int)seg_ns[k], (int)L.cap, A, LJ, PA, s);
       }
     }
     HIPCHK(h, hipGetLastError());

@@ -407,7 +407,7 @@ struct PartAdj {
 // the fields at the start of the step, P the particles as that step's push read them
 template <typename T>
 void launch_adj_particles(const Grid<T> &g, const Fields<T> &Fn, const Parts<T> &P, const int32_t *count, int ns,
-                          const AdjFields<T> &L, T *const LJ[3], const PartAdj<T> &A, hipStream_t s);
+                          int cap, const AdjFields<T> &L, T *const LJ[3], const PartAdj<T> &A, hipStream_t s);
 
 // one run of a batch: everything its kernels need, in device memory
 template <typename T>

@@ -213,3 +213,4 @@ def test_checked_build_exports_every_declared_function():
     assert len(names) >= 17
     for n in names:
         assert hasattr(L, n), n
+

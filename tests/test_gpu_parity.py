@@ -482,3 +482,18 @@ def test_restart_from_exported_state(dim, order, precision):
     assert da["n_particles"] == dc["n_particles"]
     assert abs(da["u_interior"] - dc["u_interior"]) <= (1e-12 if precision == 64 else 1e-5) * abs(da["u_interior"])
     say("restart", dim, precision, "worst field difference", worst)
+
+
+def test_particle_ids_out_of_range_are_rejected():
+    """Ids index per-particle arrays (the pushed adjoint's): set_particles rejects a negative id
+    and one beyond 32 bits, and leaves the run as it was."""
+    cfg, parts, fields = _random_case(2, 1, seed=31, n_particles=4)
+    g = B.PmlPic(cfg, max_particles=8)
+    g.add_particles(parts.x, parts.u, parts.w)
+    ids, X, u, w = g.particles()
+    for bad in (-1, 2 ** 31):
+        with pytest.raises(B.PmlPicError):
+            g.set_particles(np.array([bad, 1, 2, 3]), X, u, w)
+    assert np.array_equal(g.particles()[0], ids)
+    g.set_particles(np.array([7, 1, 2, 3]), X, u, w)
+    assert sorted(g.particles()[0].tolist()) == [1, 2, 3, 7]
