@@ -11,7 +11,8 @@
 // the previous plane kept in registers, y neighbours through LDS (each wavefront publishes
 // its row of B^{n+1/2} and of E^{n+1}).  At plane k it computes B^{n+1/2}(k), E^{n+1}(k)
 // and B^{n+1}(k - 1).  Halo work: lanes 0, 62, 63, the rows y0 - 1 and y0 + 14, and one
-// plane before and after the chunk, computed and thrown away.  Every owned sample in
+// plane before and after the chunk, computed and thrown away (and the loads of a second
+// plane after it, issued and not used).  Every owned sample in
 // [0, M] is written (a sample the update leaves alone is copied); split parts wherever the
 // split is active.  The current of this step is read (and not cleared); the other current
 // buffer, read by the previous step, is cleared over the owned samples for the next deposit.
@@ -22,9 +23,16 @@
 namespace pmlpic {
 
 // output rows per workgroup (with one halo row on each side, ROWS + 2 wavefronts): 14 in
-// FP32; 6 in FP64, whose registers would not fit 16 wavefronts
-template <typename T> struct F3Cfg { static constexpr int ROWS = 14; };
-template <> struct F3Cfg<double> { static constexpr int ROWS = 6; };
+// FP32; 6 in FP64, whose registers would not fit 16 wavefronts.  ITEMS: the number of
+// workgroups the chunks of planes aim at (see fused_3d_shape)
+template <typename T> struct F3Cfg {
+  static constexpr int ROWS = 14;
+  static constexpr long ITEMS = 1536;
+};
+template <> struct F3Cfg<double> {
+  static constexpr int ROWS = 6;
+  static constexpr long ITEMS = 2048;
+};
 
 template <typename T>
 struct Tab9 {   // per-axis tables at one index: the kinds the B and E updates read
@@ -41,6 +49,22 @@ __device__ __forceinline__ void load_tab9(const Grid<T> &g, int axis, int idx, T
   t.gN = g.tb(axis, T_G_N, idx);
   t.aC = g.tb(axis, T_A_C, idx);
   t.aN = g.tb(axis, T_A_N, idx);
+}
+
+// a value that is the same in every lane, moved to a scalar register
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ Tab9<T> wave_uniform(const Tab9<T> &t) {
+  return {wave_uniform(t.sigC), wave_uniform(t.ghkC), wave_uniform(t.ehC), wave_uniform(t.sigN), wave_uniform(t.gkN),
+          wave_uniform(t.eN),   wave_uniform(t.gN),   wave_uniform(t.aC),  wave_uniform(t.aN)};
 }
 
 template <typename T>
@@ -79,10 +103,20 @@ __device__ __forceinline__ void estep1(T &e, T &ea, const Tab9<T> &TB, const Tab
   }
 }
 
+constexpr int F3_KZMAX = 64;   // planes per chunk at most
+
+// Every load of the plane loop is issued whatever the lane's position, into the register
+// that keeps it: an index outside the sample range is clamped to the range (such lanes and
+// rows feed only samples the workgroup does not own), and a split part where the split is
+// off reads the plain component at the same sample (a value the update then ignores).  With
+// the z tables of the chunk's planes in LDS, the next plane's loads are a fixed count that
+// the wave leaves in flight while it works on the current plane (a load skipped on some
+// path, or a condition on a value just loaded, would make it wait for every load in flight).
 template <typename T, int F3_ROWS = F3Cfg<T>::ROWS, int F3_WAVES = F3_ROWS + 2>
 __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T> F, Fields<T> D, JZero<T> jz,
                                                             int nstrips, int nrb, int kz, int nchunk, bool fuse_alpha) {
   __shared__ T sh_bx[F3_WAVES][64], sh_bz[F3_WAVES][64], sh_ex[F3_WAVES][64], sh_ez[F3_WAVES][64];
+  __shared__ Tab9<T> sh_tz[F3_KZMAX + 3];   // z tables of planes k0 - 1 .. k1 + 1
   // workgroup b runs on XCD b mod 8: each XCD takes a contiguous eighth of the items, so
   // that neighbouring strips and rows (which read each other's halo) share its L2
   const int per = (int)(gridDim.x >> 3);
@@ -95,13 +129,13 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
   const int i = strip * FW - 1 + lane;
   const int j = rb * F3_ROWS - 1 + w;
   const int k0 = chunk * kz, k1 = min(k0 + kz, M2 + 1);
-  const bool colok = i >= -G && i <= M0 + G;
-  const bool rowok = j >= -G && j <= M1 + G;
-  const bool rowok1 = j + 1 >= -G && j + 1 <= M1 + G;
+  for (int p = (int)threadIdx.x; p <= k1 - k0 + 2; p += 64 * F3_WAVES)
+    load_tab9(g, 2, min(max(k0 - 1 + p, -G), M2 + G), sh_tz[p]);
   const bool own = lane >= 1 && lane <= FW && i <= M0 && w >= 1 && w <= F3_ROWS && j <= M1;
-  Tab9<T> X, Y;
+  Tab9<T> X, Y;   // x tables per lane, y tables per wavefront (scalar registers)
   load_tab9(g, 0, min(max(i, -G), M0 + G), X);
   load_tab9(g, 1, min(max(j, -G), M1 + G), Y);
+  Y = wave_uniform(Y);
   // update extents: B_a at index <= M along a, <= M - 1 across; E_a at <= M - 1 along a,
   // in [1, M - 1] across (PEC walls); nothing below 0
   const bool bx_x = i >= 0 && i <= M0, bx_c = i >= 0 && i <= M0 - 1, ex_a = i >= 0 && i <= M0 - 1,
@@ -109,9 +143,13 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
   const bool by_y = j >= 0 && j <= M1, by_c = j >= 0 && j <= M1 - 1, ey_a = j >= 0 && j <= M1 - 1,
              ey_c = j >= 1 && j <= M1 - 1;
   const long sz = g.sz;
-  const long q0 = g.at(i, j, 0);
-  auto ld = [&](const T *a, long q, bool ok) -> T { return ok ? gptr(a)[q] : T(0); };
-  const bool ok = colok && rowok;
+  // sample offsets of plane 0 at the column and row clamped to the sample range (equal to
+  // the lane's own where it owns a sample), and at the row above
+  const int ic = min(max(i, -G), M0 + G);
+  const long q0 = g.at(ic, min(max(j, -G), M1 + G), 0);
+  const long q0r = g.at(ic, min(max(j + 1, -G), M1 + G), 0);
+  auto ld = [&](const T *a, long q) -> T { return gptr(a)[q]; };
+  auto ld_split = [&](const T *part, const T *plain, long q, bool on) -> T { return gptr(on ? part : plain)[q]; };
   const int wm = max(w - 1, 0), wp = min(w + 1, F3_WAVES - 1);   // LDS rows of j - 1, j + 1
 
   // inputs of plane k: E^n at k + 1, E^n at row j + 1, B^n, split parts, J
@@ -123,40 +161,39 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
     T jx, jy, jz;
   };
   auto fetch = [&](int k, In &r) {
-    Tab9<T> Z;
-    load_tab9(g, 2, min(max(k, -G), M2 + G), Z);
+    const Tab9<T> Z = wave_uniform(sh_tz[k - k0 + 1]);
     const long q = q0 + (long)k * sz;
-    r.ex1 = ld(F.E[0], q + sz, ok);
-    r.ey1 = ld(F.E[1], q + sz, ok);
-    r.ez1 = ld(F.E[2], q + sz, ok);
-    r.exr = ld(F.E[0], q + g.sy, colok && rowok1);
-    r.ezr = ld(F.E[2], q + g.sy, colok && rowok1);
-    r.exa = ld(F.Ea[0], q, ok && Y.sigN + Z.sigN > T(0));
-    r.eya = ld(F.Ea[1], q, ok && Z.sigN + X.sigN > T(0));
-    r.eza = ld(F.Ea[2], q, ok && X.sigN + Y.sigN > T(0));
-    r.bx = ld(F.B[0], q, ok);
-    r.by = ld(F.B[1], q, ok);
-    r.bz = ld(F.B[2], q, ok);
-    r.bxa = ld(F.Ba[0], q, ok && Y.sigC + Z.sigC > T(0));
-    r.bya = ld(F.Ba[1], q, ok && Z.sigC + X.sigC > T(0));
-    r.bza = ld(F.Ba[2], q, ok && X.sigC + Y.sigC > T(0));
-    r.jx = ld(F.J[0], q, ok);
-    r.jy = ld(F.J[1], q, ok);
-    r.jz = ld(F.J[2], q, ok);
+    r.ex1 = ld(F.E[0], q + sz);
+    r.ey1 = ld(F.E[1], q + sz);
+    r.ez1 = ld(F.E[2], q + sz);
+    r.exr = ld(F.E[0], q0r + (long)k * sz);
+    r.ezr = ld(F.E[2], q0r + (long)k * sz);
+    r.exa = ld_split(F.Ea[0], F.E[0], q, Y.sigN + Z.sigN > T(0));
+    r.eya = ld_split(F.Ea[1], F.E[1], q, Z.sigN + X.sigN > T(0));
+    r.eza = ld_split(F.Ea[2], F.E[2], q, X.sigN + Y.sigN > T(0));
+    r.bx = ld(F.B[0], q);
+    r.by = ld(F.B[1], q);
+    r.bz = ld(F.B[2], q);
+    r.bxa = ld_split(F.Ba[0], F.B[0], q, Y.sigC + Z.sigC > T(0));
+    r.bya = ld_split(F.Ba[1], F.B[1], q, Z.sigC + X.sigC > T(0));
+    r.bza = ld_split(F.Ba[2], F.B[2], q, X.sigC + Y.sigC > T(0));
+    r.jx = ld(F.J[0], q);
+    r.jy = ld(F.J[1], q);
+    r.jz = ld(F.J[2], q);
   };
 
+  __syncthreads();   // the z tables
   int k = k0 - 1;
-  T ecx = ld(F.E[0], q0 + (long)k * sz, ok), ecy = ld(F.E[1], q0 + (long)k * sz, ok),
-    ecz = ld(F.E[2], q0 + (long)k * sz, ok);   // E^n(k)
-  In cur, nxt;
-  fetch(k, cur);
-  Tab9<T> Zp, Zc;   // tables of planes k - 1, k
-  load_tab9(g, 2, min(max(k, -G), M2 + G), Zc);
+  T ecx = ld(F.E[0], q0 + (long)k * sz), ecy = ld(F.E[1], q0 + (long)k * sz),
+    ecz = ld(F.E[2], q0 + (long)k * sz);   // E^n(k)
+  In ia, ib;
+  fetch(k, ia);
+  Tab9<T> Zp, Zc = wave_uniform(sh_tz[0]);   // tables of planes k - 1, k
   Zp = Zc;
   Vec3S<T> bhp = {T(0), T(0), T(0), T(0), T(0), T(0)};   // B^{n+1/2}(k - 1)
   Vec3S<T> enp = {T(0), T(0), T(0), T(0), T(0), T(0)};   // E^{n+1}(k - 1)
-  for (; k <= k1; ++k) {
-    if (k < k1) fetch(k + 1, nxt);   // next plane's loads go out before this plane's arithmetic
+  // the work at plane k from its inputs cur, then the advance to plane k + 1
+  auto plane = [&](const int k, const In &cur) {
     const bool bz_z = k >= 0 && k <= M2, bz_c = k >= 0 && k <= M2 - 1, ez_a = k >= 0 && k <= M2 - 1,
                ez_c = k >= 1 && k <= M2 - 1;
     // B^{n+1/2}(k)
@@ -224,22 +261,29 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
     bhp = bh;
     enp = en;
     Zp = Zc;
-    load_tab9(g, 2, min(max(k + 1, -G), M2 + G), Zc);
+    Zc = wave_uniform(sh_tz[k - k0 + 2]);
     ecx = cur.ex1;
     ecy = cur.ey1;
     ecz = cur.ez1;
-    cur = nxt;
+  };
+  // the next plane's loads go out before this plane's arithmetic (at the last plane, those
+  // of the plane after it, which are not used: a fixed load count on every path)
+  for (; k <= k1; ++k) {
+    fetch(k + 1, ib);
+    plane(k, ia);
+    ia = ib;
   }
 }
 
-// planes per chunk: about 8 workgroups per compute unit over the launch (measured on the
-// 280^3 beam grid: 16 planes 0.71 ms, 28 planes 0.73 ms per pass)
-static void fused_3d_shape(const int M[3], int rows, int &nstrips, int &nrb, int &kz, int &nchunk) {
+// planes per chunk, so that the launch holds about `want` workgroups: longer chunks re-read
+// fewer halo planes, shorter ones balance the compute units better.  FP32 on the 281^3-sample
+// beam grid (16-wavefront workgroups, one per compute unit): 9 planes 0.70 ms, 14 planes
+// 0.685 ms, 19 planes 0.67 ms, 28 planes 0.70 ms, 38 planes 0.73 ms per pass
+static void fused_3d_shape(const int M[3], int rows, long want, int &nstrips, int &nrb, int &kz, int &nchunk) {
   nstrips = (M[0] + 1 + FW - 1) / FW;
   nrb = (M[1] + 1 + rows - 1) / rows;
   const long per_plane = (long)nstrips * nrb;
-  const long want = 2048;
-  kz = (int)std::min<long>(64, std::max<long>(8, (M[2] + 1) * per_plane / want));
+  kz = (int)std::min<long>(F3_KZMAX, std::max<long>(8, (M[2] + 1) * per_plane / want));
   nchunk = (M[2] + 1 + kz - 1) / kz;
 }
 
@@ -248,7 +292,7 @@ void launch_fused_fields_3d(const Grid<T> &g, const Fields<T> &F, const Fields<T
                             bool fuse_alpha, hipStream_t s) {
   constexpr int rows = F3Cfg<T>::ROWS;
   int nstrips, nrb, kz, nchunk;
-  fused_3d_shape(g.M, rows, nstrips, nrb, kz, nchunk);
+  fused_3d_shape(g.M, rows, F3Cfg<T>::ITEMS, nstrips, nrb, kz, nchunk);
   const long items = (long)nstrips * nrb * nchunk;
   const unsigned blocks = (unsigned)((items + 7) / 8 * 8);
   hipLaunchKernelGGL((k_fused_3d<T>), dim3(blocks), dim3(64 * (rows + 2)), 0, s, g, F, D, jz, nstrips, nrb, kz,
