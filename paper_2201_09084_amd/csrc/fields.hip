@@ -249,20 +249,25 @@ __global__ void __launch_bounds__(256) k_filter_J(Grid<T> g, const T *src, T *ds
   if (i >= ext0 || j >= ext1 || k0 >= k1) return;
   const T *J = src + (size_t)A * g.nelem;
   T *out = dst + (size_t)A * g.nelem;
-  const bool xl = i > 0, xr = i + 1 < ext0, yl = j > 0, yr = j + 1 < ext1;
+  // neighbour weights, zero outside the extents: all nine loads of a plane are issued on every
+  // path (the neighbours lie in the guard layers or hold finite samples) and then combined, one
+  // memory round trip per plane instead of one per load
+  const T wl = i > 0 ? T(0.25) : T(0), wr = i + 1 < ext0 ? T(0.25) : T(0);
+  const T wd = j > 0 ? T(0.25) : T(0), wu = j + 1 < ext1 ? T(0.25) : T(0);
   auto row = [&](long q) {
-    T r = T(0.5) * J[q];
-    if (xl) r += T(0.25) * J[q - 1];
-    if (xr) r += T(0.25) * J[q + 1];
-    return r;
+    const T c = gptr(J)[q], l = gptr(J)[q - 1], r = gptr(J)[q + 1];
+    T v = T(0.5) * c;
+    v += wl * l;
+    v += wr * r;
+    return v;
   };
   auto plane = [&](int k) {
-    if (k < 0 || k >= ext2) return T(0);
-    const long q = g.at(i, j, k);
-    T p = T(0.5) * row(q);
-    if (yl) p += T(0.25) * row(q - g.sy);
-    if (yr) p += T(0.25) * row(q + g.sy);
-    return p;
+    const long q = g.at(i, j, k);   // k in [-1, ext2]: inside the guard layers
+    const T rd = row(q - g.sy), r0 = row(q), ru = row(q + g.sy);
+    T p = T(0.5) * r0;
+    p += wd * rd;
+    p += wu * ru;
+    return k >= 0 && k < ext2 ? p : T(0);
   };
   T pm = plane(k0 - 1), p0 = plane(k0);
   for (int k = k0; k < k1; ++k) {
