@@ -99,6 +99,12 @@ struct Grid {
   __device__ T tb(int axis, int kind, int i) const {
     return gptr(tab)[(axis * T_NKIND + kind) * ntab + i + G];
   }
+  // the same entry read through the constant address space: with an index that is the same
+  // in every lane it becomes a scalar load (a scalar register, not counted with the vector
+  // loads); the tables are not written while a kernel runs
+  __device__ T tb_uniform(int axis, int kind, int i) const {
+    return ((const __attribute__((address_space(4))) T *)tab)[(axis * T_NKIND + kind) * ntab + i + G];
+  }
 };
 
 template <typename T>

@@ -50,17 +50,146 @@ void launch_jbox_clear(const Grid<T> &g, const JClear<T> &jc, hipStream_t s) {
 template void launch_jbox_clear<float>(const Grid<float> &, const JClear<float> &, hipStream_t);
 template void launch_jbox_clear<double>(const Grid<double> &, const JClear<double> &, hipStream_t);
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
+// ---------------------------------------------------------------- 3D sweeps
+// The B half step and the E step of update_B_apply / update_E_apply (field_core.h) for the
+// three components of one 3D node, with every load of the node requested up front (the
+// conductor mask first, inside the one uniform branch; the neighbours of the far faces lie in
+// the guard layers; a split part where the split is off reads the plain component, a value
+// the update ignores): a memory round trip or two per node, where the per-component form
+// waited on each load in turn.  Same arithmetic in the same order, so the same bits.
+template <typename T>
+struct NodeTabs {   // per-axis table entries at the node's index along each axis
+  T sig[3], gk[3], eh[3];
+};
+
+// B_A at the node from its differences Db (along b = A + 1 of E_c) and Dc (along c = A + 2
+// of E_b), the loaded B_A and split part, written back where the node holds a B_A sample
+template <typename T, int A>
+__device__ __forceinline__ void b_node(const Grid<T> &g, const Fields<T> &F, const int (&id)[3], long q,
+                                       const NodeTabs<T> &t, T Db, T Dc, T b, T ba, uint32_t cm) {
+  constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
+  if (id[A] > g.M[A] || id[Bx] > g.M[Bx] - 1 || id[Cx] > g.M[Cx] - 1) return;
+  if (t.sig[Bx] + t.sig[Cx] > T(0)) {
+    T p1 = ba;
+    T p2 = b - p1;
+    p1 = fma(-t.gk[Bx], Db, t.eh[Bx] * p1);
+    p2 = fma(t.gk[Cx], Dc, t.eh[Cx] * p2);
+    b = p1 + p2;
+    ba = p1;
+    gptr(F.Ba[A])[q] = ba;
+  } else {
+    b = fma(-t.gk[Bx], Db, fma(t.gk[Cx], Dc, b));
+  }
+  if ((cm >> (3 + A)) & 1) {   // inside a conductor
+    b = T(0);
+    gptr(F.Ba[A])[q] = T(0);
+  }
+  gptr(F.B[A])[q] = b;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_update_B3(Grid<T> g, Fields<T> F) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  const int k = (int)blockIdx.z;
   if (i > g.M[0] || j > g.M[1]) return;
   const int id[3] = {i, j, k};
-  const long q = g.at(i, j, k);
-  update_B_comp<T, DIM, 0>(g, F, id, q);
-  update_B_comp<T, DIM, 1>(g, F, id, q);
-  update_B_comp<T, DIM, 2>(g, F, id, q);
+  const long q = g.at(i, j, k), sy = g.sy, sz = g.sz;
+  uint32_t cm = 0;
+  if (g.cmask) cm = gptr(g.cmask)[q];
+  NodeTabs<T> t;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    t.sig[d] = g.tb(d, T_SIG_C, id[d]);
+    t.gk[d] = g.tb(d, T_GHK_C, id[d]);
+    t.eh[d] = g.tb(d, T_EH_C, id[d]);
+  }
+  const auto *E0 = gptr(F.E[0]), *E1 = gptr(F.E[1]), *E2 = gptr(F.E[2]);
+  const T e0 = E0[q], e0y = E0[q + sy], e0z = E0[q + sz];
+  const T e1 = E1[q], e1x = E1[q + 1], e1z = E1[q + sz];
+  const T e2 = E2[q], e2x = E2[q + 1], e2y = E2[q + sy];
+  const T b0 = gptr(F.B[0])[q], b1 = gptr(F.B[1])[q], b2 = gptr(F.B[2])[q];
+  const T ba0 = gptr(t.sig[1] + t.sig[2] > T(0) ? F.Ba[0] : F.B[0])[q];
+  const T ba1 = gptr(t.sig[2] + t.sig[0] > T(0) ? F.Ba[1] : F.B[1])[q];
+  const T ba2 = gptr(t.sig[0] + t.sig[1] > T(0) ? F.Ba[2] : F.B[2])[q];
+  b_node<T, 0>(g, F, id, q, t, e2y - e2, e1z - e1, b0, ba0, cm);   // B_x: d_y E_z, d_z E_y
+  b_node<T, 1>(g, F, id, q, t, e0z - e0, e2x - e2, b1, ba1, cm);   // B_y: d_z E_x, d_x E_z
+  b_node<T, 2>(g, F, id, q, t, e1x - e1, e0y - e0, b2, ba2, cm);   // B_z: d_x E_y, d_y E_x
+}
+
+template <typename T>
+struct NodeTabsE {
+  T sig[3], gk[3], gg[3], e[3], aC[3], aN[3];
+};
+
+// E_A at the node from Db (along b of B_c), Dc (along c of B_b) and the source J_A
+template <typename T, int A>
+__device__ __forceinline__ void e_node(const Grid<T> &g, const Fields<T> &F, const int (&id)[3], long q,
+                                       const NodeTabsE<T> &t, T Db, T Dc, T e, T ea, T j, uint32_t cm,
+                                       bool fuse_alpha, bool consume) {
+  constexpr int Bx = (A + 1) % 3, Cx = (A + 2) % 3;
+  if (id[A] > g.M[A] - 1) return;
+  if (id[Bx] < 1 || id[Bx] > g.M[Bx] - 1) return;   // PEC: tangential E = 0
+  if (id[Cx] < 1 || id[Cx] > g.M[Cx] - 1) return;
+  if (consume && j != T(0)) gptr(F.J[A])[q] = T(0);   // leaves J zero for the next deposit
+  if (fuse_alpha) {   // alpha_at: the product over the axes in order x, y, z
+    T a = T(1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a *= d == A ? t.aC[d] : t.aN[d];
+    j *= a;
+  }
+  const T sb = t.sig[Bx], sc = t.sig[Cx];
+  if (sb + sc > T(0)) {
+    const T inv = T(1) / (sb + sc);
+    T p1 = ea;
+    T p2 = e - p1;
+    p1 = fma(t.gk[Bx], Db, fma(-t.gg[Bx] * (sb * inv), j, t.e[Bx] * p1));
+    p2 = fma(-t.gk[Cx], Dc, fma(-t.gg[Cx] * (sc * inv), j, t.e[Cx] * p2));
+    e = p1 + p2;
+    gptr(F.Ea[A])[q] = p1;
+  } else {
+    e = fma(t.gk[Bx], Db, fma(-t.gk[Cx], Dc, fma(-g.dt, j, e)));
+  }
+  if ((cm >> A) & 1) {   // inside a conductor
+    e = T(0);
+    gptr(F.Ea[A])[q] = T(0);
+  }
+  gptr(F.E[A])[q] = e;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_update_E3(Grid<T> g, Fields<T> F, bool fuse_alpha, bool consume) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = (int)blockIdx.z;
+  if (i > g.M[0] || j > g.M[1]) return;
+  const int id[3] = {i, j, k};
+  const long q = g.at(i, j, k), sy = g.sy, sz = g.sz;
+  uint32_t cm = 0;
+  if (g.cmask) cm = gptr(g.cmask)[q];
+  NodeTabsE<T> t;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    t.sig[d] = g.tb(d, T_SIG_N, id[d]);
+    t.gk[d] = g.tb(d, T_GK_N, id[d]);
+    t.gg[d] = g.tb(d, T_G_N, id[d]);
+    t.e[d] = g.tb(d, T_E_N, id[d]);
+    t.aC[d] = g.tb(d, T_A_C, id[d]);
+    t.aN[d] = g.tb(d, T_A_N, id[d]);
+  }
+  const auto *B0 = gptr(F.B[0]), *B1 = gptr(F.B[1]), *B2 = gptr(F.B[2]);
+  const T b0 = B0[q], b0y = B0[q - sy], b0z = B0[q - sz];
+  const T b1 = B1[q], b1x = B1[q - 1], b1z = B1[q - sz];
+  const T b2 = B2[q], b2x = B2[q - 1], b2y = B2[q - sy];
+  const T e0 = gptr(F.E[0])[q], e1 = gptr(F.E[1])[q], e2 = gptr(F.E[2])[q];
+  const T j0 = gptr(F.J[0])[q], j1 = gptr(F.J[1])[q], j2 = gptr(F.J[2])[q];
+  const T ea0 = gptr(t.sig[1] + t.sig[2] > T(0) ? F.Ea[0] : F.E[0])[q];
+  const T ea1 = gptr(t.sig[2] + t.sig[0] > T(0) ? F.Ea[1] : F.E[1])[q];
+  const T ea2 = gptr(t.sig[0] + t.sig[1] > T(0) ? F.Ea[2] : F.E[2])[q];
+  // E_x: d_y B_z, d_z B_y; E_y: d_z B_x, d_x B_z; E_z: d_x B_y, d_y B_x
+  e_node<T, 0>(g, F, id, q, t, b2 - b2y, b1 - b1z, e0, ea0, j0, cm, fuse_alpha, consume);
+  e_node<T, 1>(g, F, id, q, t, b0 - b0z, b2 - b2x, e1, ea1, j1, cm, fuse_alpha, consume);
+  e_node<T, 2>(g, F, id, q, t, b1 - b1x, b0 - b0y, e2, ea2, j2, cm, fuse_alpha, consume);
 }
 
 // Cole-Karkkainen B half step (3D), marching along z.  Each CK difference is a weighted
@@ -123,18 +252,47 @@ __global__ void __launch_bounds__(256) k_update_B_ck(Grid<T> g, Fields<T> F, int
   const int j = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int k0 = (int)blockIdx.z * kz, k1 = min(k0 + kz, g.M[2] + 1);
   if (i > g.M[0] || j > g.M[1] || k0 >= k1) return;
+  NodeTabs<T> t;   // x and y entries fixed for the column; z entries per plane (scalar loads)
+  t.sig[0] = g.tb(0, T_SIG_C, i);
+  t.gk[0] = g.tb(0, T_GHK_C, i);
+  t.eh[0] = g.tb(0, T_EH_C, i);
+  t.sig[1] = g.tb(1, T_SIG_C, j);
+  t.gk[1] = g.tb(1, T_GHK_C, j);
+  t.eh[1] = g.tb(1, T_EH_C, j);
   CkPlane<T> pm = ck_plane(g, F, i, j, k0 - 1), p0 = ck_plane(g, F, i, j, k0);
   for (int k = k0; k < k1; ++k) {
-    const CkPlane<T> pp = ck_plane(g, F, i, j, k + 1);
     const int id[3] = {i, j, k};
     const long q = g.at(i, j, k);
+    uint32_t cm = 0;
+    if (g.cmask) cm = gptr(g.cmask)[q];
+    t.sig[2] = g.tb_uniform(2, T_SIG_C, k);
+    t.gk[2] = g.tb_uniform(2, T_GHK_C, k);
+    t.eh[2] = g.tb_uniform(2, T_EH_C, k);
+    const CkPlane<T> pp = ck_plane(g, F, i, j, k + 1);
+    const T b0 = gptr(F.B[0])[q], b1 = gptr(F.B[1])[q], b2 = gptr(F.B[2])[q];
+    const T ba0 = gptr(t.sig[1] + t.sig[2] > T(0) ? F.Ba[0] : F.B[0])[q];
+    const T ba1 = gptr(t.sig[2] + t.sig[0] > T(0) ? F.Ba[1] : F.B[1])[q];
+    const T ba2 = gptr(t.sig[0] + t.sig[1] > T(0) ? F.Ba[2] : F.B[2])[q];
     // B_x: b = y (E_z), c = z (E_y); B_y: b = z (E_x), c = x (E_z); B_z: b = x (E_y), c = y (E_x)
-    update_B_apply<T, 3, 0>(g, F, id, q, p0.S0 + (pm.S1 + pp.S1), pp.P - p0.P);
-    update_B_apply<T, 3, 1>(g, F, id, q, pp.Q - p0.Q, p0.U0 + (pm.U1 + pp.U1));
-    update_B_apply<T, 3, 2>(g, F, id, q, p0.V0 + (pm.V1 + pp.V1), p0.W0 + (pm.W1 + pp.W1));
+    b_node<T, 0>(g, F, id, q, t, p0.S0 + (pm.S1 + pp.S1), pp.P - p0.P, b0, ba0, cm);
+    b_node<T, 1>(g, F, id, q, t, pp.Q - p0.Q, p0.U0 + (pm.U1 + pp.U1), b1, ba1, cm);
+    b_node<T, 2>(g, F, id, q, t, p0.V0 + (pm.V1 + pp.V1), p0.W0 + (pm.W1 + pp.W1), b2, ba2, cm);
     pm = p0;
     p0 = pp;
   }
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_update_B(Grid<T> g, Fields<T> F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.M[0] || j > g.M[1]) return;
+  const int id[3] = {i, j, k};
+  const long q = g.at(i, j, k);
+  update_B_comp<T, DIM, 0>(g, F, id, q);
+  update_B_comp<T, DIM, 1>(g, F, id, q);
+  update_B_comp<T, DIM, 2>(g, F, id, q);
 }
 
 // planes per chunk: 16 on large grids, fewer on small ones so that a launch keeps a few
@@ -219,7 +377,7 @@ void launch_update_B(const Grid<T> &g, const Fields<T> &F, bool /*half*/, hipStr
     const int kz = zchunk(g.M, 1, nchunk);
     hipLaunchKernelGGL((k_update_B_ck<T>), dim3(grd.x, grd.y, nchunk), dim3(256), 0, s, g, F, kz);
   }
-  else hipLaunchKernelGGL((k_update_B<T, 3>), grd, blk, 0, s, g, F);
+  else hipLaunchKernelGGL((k_update_B3<T>), grd, blk, 0, s, g, F);
 }
 
 template <typename T>
@@ -228,7 +386,7 @@ void launch_update_E(const Grid<T> &g, const Fields<T> &F, bool fuse_alpha, int 
   dim3 blk, grd = node_grid(g, blk);
   const bool fa = fuse_alpha && current_alpha(alpha_mode);
   if (g.dim == 2) hipLaunchKernelGGL((k_update_E<T, 2>), grd, blk, 0, s, g, F, fa, consume);
-  else hipLaunchKernelGGL((k_update_E<T, 3>), grd, blk, 0, s, g, F, fa, consume);
+  else hipLaunchKernelGGL((k_update_E3<T>), grd, blk, 0, s, g, F, fa, consume);
 }
 
 // Binomial filter of the deposited current (App. A), 3D, one pass: dst_A(i,j,k) = sum
