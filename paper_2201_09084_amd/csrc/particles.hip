@@ -104,11 +104,16 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     int mn[6] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
     int mx[6] = {-0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF, -0x7FFFFFFF};
     unsigned int out = 0u;
+    // the cells of my particles requested together (a slot past the item reads its last one,
+    // unused): one memory round trip, not one per particle
+    uint32_t cs[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) cs[k] = P.cell[min(p0 + k * TPB + tid, p1 - 1)];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int p = p0 + k * TPB + tid;
       if (p < p1) {
-        const uint32_t c = P.cell[p];
+        const uint32_t c = cs[k];
         if (c != DEAD) {
           int id[3];
           unpack_cell(DIM, c, id[0], id[1], id[2]);
@@ -211,12 +216,31 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
     lsink.lds = lds + (tid % R) * stride;
     __syncthreads();
     GlobalSink<T> gsink{{F.J[0], F.J[1], F.J[2]}, 0, 0, 0};
+    // a particle's state is requested one particle ahead (a slot past the item reads its last
+    // one, unused), so that its round trip overlaps the gather of the one before
+    struct PState {
+      uint32_t c;
+      T f[3], u[3], w;
+    };
+    auto load = [&](int p, PState &st) {
+      const int pc = min(p, p1 - 1);
+      st.c = P.cell[pc];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) st.f[d] = d < DIM ? P.f[d][pc] : T(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) st.u[d] = P.u[d][pc];
+      st.w = P.w[pc];
+    };
+    PState cur;
+    load(p0 + tid, cur);
 #pragma unroll 1
     for (int k = 0; k < PPT; ++k) {
       const int p = p0 + k * TPB + tid;
+      PState nxt;
+      load(p + TPB, nxt);
       bool active = false;
       if (p < p1) {
-        const uint32_t c = P.cell[p];
+        const uint32_t c = cur.c;
         if (c != DEAD) {
           active = true;
           int id[3];
@@ -224,8 +248,8 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
           bool inbox = use_lds;
 #pragma unroll
           for (int d = 0; d < DIM; ++d) inbox = inbox && id[d] >= bmn[d] && id[d] <= bmx[d];
-          T f[3] = {P.f[0][p], P.f[1][p], DIM == 3 ? P.f[2][p] : T(0)};
-          T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+          T f[3] = {cur.f[0], cur.f[1], cur.f[2]};
+          T u[3] = {cur.u[0], cur.u[1], cur.u[2]};
           if (push) {
             T EB[6];
             gather<T, DIM, ORDER>(g, F, id, f, EB);
@@ -238,7 +262,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
           P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
 #pragma unroll
           for (int d = 0; d < DIM; ++d) P.f[d][p] = f[d];
-          const T qw = deposit_charge<T, DIM>(g, P, p, id0, f0, id, f);
+          const T qw = deposit_charge_w<T, DIM>(g, P, p, cur.w, id0, f0, id, f);
           if (inbox) deposit<T, DIM, ORDER>(g, lsink, id0, f0, id, f, u[2] * ig, qw);
           else deposit<T, DIM, ORDER>(g, gsink, id0, f0, id, f, u[2] * ig, qw);
           P.cell[p] = inside ? pack_cell(DIM, id[0], id[1], id[2]) : DEAD;
@@ -246,6 +270,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
       }
       const unsigned long long m = __ballot(active);
       if ((tid & 63) == 0 && m) atomicAdd(&n_pushed, (unsigned int)__popcll(m));
+      cur = nxt;
     }
     __syncthreads();
     if (tid == 0 && n_pushed) atomicAdd(&ctl.pushes[blockIdx.x % N_PUSH_COUNTERS], (unsigned long long)n_pushed);
