@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
   const int t = item.z;
   const int tc[3] = {t % tw.ntile[0], (t / tw.ntile[0]) % tw.ntile[1], t / (tw.ntile[0] * tw.ntile[1])};
   const uint32_t s = (uint32_t)item.x, e = (uint32_t)item.y;
+  if (e <= s) return;   // whole workgroup (the work list holds no empty item)
   // cells [T0, T0 + tile) of the tile; particles in [T0 - 1, T0 + tile] at both ends of their
   // move deposit into the box of nodes [T0 - 1, T0 + tile + 1]
   int T0[3], ext[3], st[3], tl[3];
@@ -110,9 +111,11 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
     for (int d = 0; d < 3; ++d) { q.f[d] = P.f[d][p]; q.u[d] = P.u[d][p]; }
     q.w = P.w[p];
   };
+  // (a slot past the item reads the item's last particle, unused: the same loads on every
+  // path, which the wave then leaves in flight through the current particle's work)
   PState cur;
   uint32_t p = s + (uint32_t)tid;
-  if (p < e) load(p, cur);
+  load(min(p, e - 1), cur);
   for (int q = tid; q < 3 * total; q += P3_TPB) box[q] = 0.0;
   if (tid == 0) { n_pushed = 0u; q_n = 0; }
   __syncthreads();
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
   unsigned int my_pushes = 0u;
   for (; p < e; p += P3_TPB) {
     PState nxt;
-    if (p + P3_TPB < e) load(p + P3_TPB, nxt);
+    load(min(p + P3_TPB, e - 1), nxt);
     const uint32_t c = cur.c;
     if (c == DEAD) { cur = nxt; continue; }
     ++my_pushes;
