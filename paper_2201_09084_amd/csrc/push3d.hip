@@ -130,9 +130,12 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
   for (; p < e; p += P3_TPB) {
     PState nxt;
     load(min(p + P3_TPB, e - 1), nxt);
-    const uint32_t c = cur.c;
-    if (c == DEAD) { cur = nxt; continue; }
-    ++my_pushes;
+    // a removed particle (kept until the next sort drops it) runs the same code on a cell of
+    // the tile, deposits nothing and is written back unchanged: every path issues the same
+    // loads and stores, so the wave waits only for what it uses
+    const bool live = cur.c != DEAD;
+    const uint32_t c = live ? cur.c : pack_cell(3, T0[0], T0[1], T0[2]);
+    my_pushes += live ? 1u : 0u;
     int id[3];
     unpack_cell(3, c, id[0], id[1], id[2]);
     T f[3] = {cur.f[0], cur.f[1], cur.f[2]};
@@ -146,9 +149,13 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
     const T f0[3] = {f[0], f[1], f[2]};
     T ig;
     const bool inside = move<T, 3>(g, id, f, u, ig);
-    P.u[0][p] = u[0]; P.u[1][p] = u[1]; P.u[2][p] = u[2];
-    P.f[0][p] = f[0]; P.f[1][p] = f[1]; P.f[2][p] = f[2];
-    const T qw = deposit_charge_w<T, 3>(g, P, p, cur.w, id0, f0, id, f);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      P.u[d][p] = live ? u[d] : cur.u[d];
+      P.f[d][p] = live ? f[d] : cur.f[d];
+    }
+    T qw = deposit_charge_w<T, 3>(g, P, p, cur.w, id0, f0, id, f);
+    if (!live) qw = T(0);
     cur = nxt;
     bool inbox = true, incell = true;
 #pragma unroll
@@ -157,11 +164,11 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
       inbox = inbox && id0[d] >= lo && id0[d] <= hi && id[d] >= lo && id[d] <= hi;
       incell = incell && id[d] == id0[d];
     }
-    if (inbox && incell) {
+    if (live && inbox && incell) {
       const int q0 = (id0[0] - lsink.lo[0]) + (id0[1] - lsink.lo[1]) * st[1] + (id0[2] - lsink.lo[2]) * st[2];
       deposit_incell_linear3<T>(g, box, q0, st, total, f0, f, qw);
     }
-    const bool queued = !(inbox && incell);
+    const bool queued = live && !(inbox && incell);
     const unsigned long long mq = __ballot(queued);
     if (queued) {
       const int lane = tid & 63;
@@ -184,7 +191,7 @@ __global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F,
         deposit<T, 3, 1>(g, gsink, id0, f0, id, f, T(0), qw);
       }
     }
-    P.cell[p] = inside ? pack_cell(3, id[0], id[1], id[2]) : DEAD;
+    P.cell[p] = live && inside ? pack_cell(3, id[0], id[1], id[2]) : DEAD;
   }
   __syncthreads();
   {   // the queued moves
