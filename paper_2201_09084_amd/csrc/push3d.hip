@@ -54,6 +54,13 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
   }
 }
 
+// Wavefronts per SIMD the compiler must leave room for: FP64 registers otherwise grow past
+// 128 and drop the kernel to 3 wavefronts (measured 2.34 against 1.94 ms on the 3D beam);
+// FP32 is left to the compiler (asked for 4 it trades scheduling for registers: 1.44
+// against 1.11 ms)
+template <typename T> struct P3Occ { static constexpr int MIN_WAVES = 1; };
+template <> struct P3Occ<double> { static constexpr int MIN_WAVES = 4; };
+
 // Workgroup b takes work item b of the list built after the sort (with tw.sel == 2, of the
 // part listing the tiles that are not dense: their full chunks, then their partial ones in
 // tile order, x fastest; at one particle per cell every tile is one partial chunk and
@@ -61,7 +68,7 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
 // and currents).  TS > 0: cubic tiles of TS cells known at compile time (the box
 // strides become immediates); 0: the tile shape of tw.
 template <typename T, int TS>
-__global__ void __launch_bounds__(P3_TPB) k_push3d_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
+__global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3Occ<T>::MIN_WAVES))) k_push3d_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
                                                          int push) {
   __shared__ double box[3 * P3_NODES];
   __shared__ unsigned int n_pushed;
