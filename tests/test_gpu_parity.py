@@ -342,6 +342,57 @@ def test_chunks_drifting_far_from_their_sort_tile(dim):
 
 
 @pytest.mark.parametrize("precision", [64, 32])
+def test_removed_particles_stay_removed_in_3d_tile_push(precision):
+    """Particles that reach the PEC walls are removed at once and stay in the arrays until
+    the next sort (the sort interval here is longer than the run), so the 3D tile push meets
+    them at every later step: they must deposit nothing, stay removed and not count as pushes.
+    Half the particles start within 1.5 cells of a wall moving outwards (most leave in the
+    first steps), the rest anywhere.  Every 2 steps: the push tally equals the live particles
+    the steps began with, and fields and live particles (ids, positions, momenta) match the
+    FP64 oracle."""
+    cfg64 = W.SimConfig(dim=3, n=(20, 18, 22), pml=((4, 4), (4, 4), (4, 4)), dt=0.5, shape_order=1,
+                        alpha_mode=W.ALPHA_DAMPED, sigma_coef=W.cubic_profile(3.2), push=1, precision=64,
+                        tile=(8, 8, 8), sort_interval=100)
+    rng = np.random.default_rng(4242)
+    lo = np.array([-cfg64.pml[d][0] * cfg64.dx[d] for d in range(3)])
+    hi = np.array([(cfg64.n[d] + cfg64.pml[d][1]) * cfg64.dx[d] for d in range(3)])
+    n_wall = 1500
+    axis = rng.integers(0, 3, n_wall)
+    side = rng.integers(0, 2, n_wall)
+    x = lo + (hi - lo) * rng.uniform(0.1, 0.9, (n_wall, 3))
+    depth = rng.uniform(0.2, 1.5, n_wall)
+    u = rng.normal(0.0, 0.5, (n_wall, 3))
+    for k in range(n_wall):
+        a = axis[k]
+        x[k, a] = lo[a] + depth[k] if side[k] == 0 else hi[a] - depth[k]
+        u[k, a] = (-1.0 if side[k] == 0 else 1.0) * rng.uniform(1.5, 4.0)
+    rest = W.random_particles(cfg64, 1500, seed=4243, margin=1.0, umax=2.0)
+    parts = W.Particles(x=np.concatenate([x, rest.x]), u=np.concatenate([u, rest.u]),
+                        w=np.concatenate([rng.uniform(0.5, 1.5, n_wall), rest.w]))
+    cfg = cfg64.replace(precision=precision)
+    g, _ = both(cfg, parts)
+    _, o = both(cfg64, parts)
+    pushes = 0
+    for _ in range(4):
+        for _ in range(2):
+            pushes += len(g.particles()[0])   # the live particles the step pushes
+            g.step(1)
+            o.step(1)
+        assert g.diagnose()["n_pushes"] == pushes
+        if precision == 64:
+            compare_fields(g, o, cfg64, 1e-10, "removed particles fp64")
+            compare_particles(g, o, 1e-10, 1e-10, "removed particles fp64")
+        else:
+            # FP32 could decide a wall crossing differently for a particle that ends a step
+            # within rounding of the wall: the live sets may differ by such a particle
+            compare_fields(g, o, cfg64, 1e-5, "removed particles fp32", l2=True)
+            assert len(set(g.particles()[0]) ^ set(o.particles()[0])) <= 2
+    live = len(o.particles()[0])
+    say("removed particles: live", live, "of", len(parts.w), "pushes", pushes)
+    assert live < len(parts.w) - n_wall // 2   # most of the wall particles left
+
+
+@pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("order", [1, 3])
 def test_one_pass_3d_field_update_equals_three_sweeps(precision, order):
     """The one-pass 3D update_yee_pml (strips of 61 columns, 14 rows, chunks of planes, halo
