@@ -176,6 +176,15 @@ __device__ __forceinline__ int shape_weights_stag(int i, T f, T (&w)[ORDER + 1])
   return ii + shape_weights<ORDER>(ff, w);
 }
 
+// The array of three for a component known only at run time (per lane): a select between
+// the three pointers.  Indexing the kernel argument's array with it makes the compiler load
+// the pointer from memory, and each wait for that load also waits for every store and
+// atomic issued before it.
+template <typename T>
+__device__ __forceinline__ T *pick3(T *const (&a)[3], int c) {
+  return c == 0 ? a[0] : (c == 1 ? a[1] : a[2]);
+}
+
 // --------------------------------------------------------------- atomics
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }

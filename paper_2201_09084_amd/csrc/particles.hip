@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(TPB) k_push_deposit_tiles(Grid<T> g, Fields<T>
         r /= ext[0];
         const int j = r % ext[1];
         const int kk = r / ext[1];
-        atomic_add(&F.J[comp][g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk)], v);
+        atomic_add(pick3(F.J, comp) + g.at(lsink.lo[0] + i, lsink.lo[1] + j, lsink.lo[2] + kk), v);
       }
     }
     __syncthreads();   // the next item reuses the box and the counters

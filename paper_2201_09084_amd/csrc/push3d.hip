@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3O
     const uint32_t r1 = (uq * m0) >> 20, i = uq - r1 * (uint32_t)ext[0];
     const uint32_t r2 = (r1 * m1) >> 20, j = r1 - r2 * (uint32_t)ext[1];
     const uint32_t comp = (r2 * m2) >> 20, k = r2 - comp * (uint32_t)ext[2];
-    atomic_add(&F.J[comp][g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k)], (T)v);
+    atomic_add(pick3(F.J, (int)comp) + g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k), (T)v);
   }
 }
 
