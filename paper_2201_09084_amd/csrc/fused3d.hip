@@ -11,8 +11,8 @@
 // the previous plane kept in registers, y neighbours through LDS (each wavefront publishes
 // its row of B^{n+1/2} and of E^{n+1}).  At plane k it computes B^{n+1/2}(k), E^{n+1}(k)
 // and B^{n+1}(k - 1).  Halo work: lanes 0, 62, 63, the rows y0 - 1 and y0 + 14, and one
-// plane before and after the chunk, computed and thrown away (and the loads of a second
-// plane after it, issued and not used).  Every owned sample in
+// plane before and after the chunk, computed and thrown away (the last plane's loads are
+// issued twice, the second time unused).  Every owned sample in
 // [0, M] is written (a sample the update leaves alone is copied); split parts wherever the
 // split is active.  The current of this step is read (and not cleared); the other current
 // buffer, read by the previous step, is cleared over the owned samples for the next deposit.
@@ -267,9 +267,9 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
     ecz = cur.ez1;
   };
   // the next plane's loads go out before this plane's arithmetic (at the last plane, those
-  // of the plane after it, which are not used: a fixed load count on every path)
+  // of that plane again, cache hits and not used: a fixed load count on every path)
   for (; k <= k1; ++k) {
-    fetch(k + 1, ib);
+    fetch(min(k + 1, k1), ib);
     plane(k, ia);
     ia = ib;
   }
