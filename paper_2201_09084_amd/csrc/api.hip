@@ -270,7 +270,7 @@ void make_layout(const pml_pic_params &p_in, Layout &L) {
   }
   L.off_oldcell = take(4 * cap);
   for (int d = 0; d < 3; ++d) L.off_oldf[d] = d < p.dim ? take(L.esz * cap) : 0;
-  L.tile_push3 = !(p.flags & (PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_NO_SORT)) && push3d_applies(p.dim, p.shape_order, L.tile);
+  L.tile_push3 = !(p.flags & (PML_PIC_FLAG_UNFUSED | PML_PIC_FLAG_NO_SORT)) && push3d_applies(p.dim, p.shape_order, L.tile, L.sz);
   L.off_count = take(8);
   L.off_check = take(4);
   L.off_pushes = take(8 * N_PUSH_COUNTERS);

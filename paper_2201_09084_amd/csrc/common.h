@@ -322,8 +322,9 @@ void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Par
 // 3D linear-shape runs (push3d.hip): gather_push + deposit_current, one workgroup per chunk
 // of a sort tile (the work items of launch_tile_chunks), its current summed in an LDS box of
 // the tile's nodes (tile + 3 per axis) and added to J with global atomics.  Applies to tiles
-// of at least three cells whose box fits in LDS.
-bool push3d_applies(int dim, int order, const int tile[3]);
+// of at least three cells whose box fits in LDS and spans less than 2^32 samples of the grid
+// (plane: the grid's z stride).
+bool push3d_applies(int dim, int order, const int tile[3], long plane);
 template <typename T>
 void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
                    int n_slots, int push, hipStream_t s);

@@ -227,6 +227,10 @@ __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3O
   // q = ((comp ext2 + k) ext1 + j) ext0 + i, divided by multiply-shift (exact for q < 2^12)
   const uint32_t m0 = (1u << 20) / (uint32_t)ext[0] + 1u, m1 = (1u << 20) / (uint32_t)ext[1] + 1u,
                  m2 = (1u << 20) / (uint32_t)ext[2] + 1u;
+  // (offsets from the box origin in 32 bits: push3d_applies admits a box only if it spans
+  // less than 2^32 samples of the grid)
+  const long qlo = g.at(lsink.lo[0], lsink.lo[1], lsink.lo[2]);
+  const uint32_t sy = (uint32_t)g.sy, sz = (uint32_t)g.sz;
   for (int q = tid; q < 3 * total; q += P3_TPB) {
     const double v = box[q];
     if (v == 0.0) continue;
@@ -234,18 +238,23 @@ __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3O
     const uint32_t r1 = (uq * m0) >> 20, i = uq - r1 * (uint32_t)ext[0];
     const uint32_t r2 = (r1 * m1) >> 20, j = r1 - r2 * (uint32_t)ext[1];
     const uint32_t comp = (r2 * m2) >> 20, k = r2 - comp * (uint32_t)ext[2];
-    atomic_add(pick3(F.J, (int)comp) + g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k), (T)v);
+#ifdef PMLPIC_CHECK
+    const long qn = g.at(lsink.lo[0] + (int)i, lsink.lo[1] + (int)j, lsink.lo[2] + (int)k);
+#else
+    const long qn = qlo + (long)(i + j * sy + k * sz);
+#endif
+    atomic_add(pick3(F.J, (int)comp) + qn, (T)v);
   }
 }
 
-bool push3d_applies(int dim, int order, const int tile[3]) {
+bool push3d_applies(int dim, int order, const int tile[3], long plane) {
   if (dim != 3 || order != 1) return false;
   long vol = 1;
   for (int d = 0; d < 3; ++d) {
     if (tile[d] < 3) return false;
     vol *= tile[d] + 3;
   }
-  return vol <= P3_NODES;
+  return vol <= P3_NODES && (tile[2] + 3) * plane < (1L << 32);
 }
 
 template <typename T>
