@@ -54,6 +54,65 @@ __device__ __forceinline__ void deposit_incell_linear3(const Grid<T> &g, double 
   }
 }
 
+// The gather of the linear shape (the same products in the same order as gather_comp) with
+// 32-bit byte offsets from each array's base: the loads take the base from scalar registers
+// and one 32-bit offset per lane, and the six components' stencils differ from the node one
+// by the staggered shift along each axis.  For arrays of fewer than 2^32 bytes.  In FP64 it
+// takes the 3D beam's push from 1.76 to 1.28 ms (the 64-bit address arithmetic held the
+// kernel at its register limit); FP32 keeps the 64-bit form (0.7% faster there).
+template <typename T, int MASK>
+__device__ __forceinline__ T gather_comp_off32(const T *arr, const Shape3<1, T> &S, uint32_t q0, uint32_t sy,
+                                               uint32_t sz) {
+  constexpr bool hx = MASK & 1, hy = MASK & 2, hz = MASK & 4;
+  const auto *bp = (const __attribute__((address_space(1))) char *)gptr(arr);
+  T v[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const auto *rp = (const __attribute__((address_space(1))) T *)(bp + (size_t)((q0 + c * sz + b * sy) * (uint32_t)sizeof(T)));
+      v[c][b][0] = rp[0];
+      v[c][b][1] = rp[1];
+    }
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    T pl = T(0);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T row = T(0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) row += (hx ? S.wc[0][a] : S.wn[0][a]) * v[c][b][a];
+      pl += (hy ? S.wc[1][b] : S.wn[1][b]) * row;
+    }
+    acc += (hz ? S.wc[2][c] : S.wn[2][c]) * pl;
+  }
+  return acc;
+}
+template <typename T>
+__device__ __forceinline__ void gather_linear3_off32(const Grid<T> &g, const Fields<T> &F, const int (&id)[3],
+                                                     const T (&f)[3], T (&EB)[6]) {
+  Shape3<1, T> S;
+  shape_all<T, 3, 1>(id, f, S);
+  // (indices wrap modulo 2^32 through the guard cells' negative coordinates and come back
+  // into [0, nelem))
+  const uint32_t sy = (uint32_t)g.sy, sz = (uint32_t)g.sz;
+  const uint32_t qn = (uint32_t)g.base + (uint32_t)S.sn[0] + (uint32_t)S.sn[1] * sy + (uint32_t)S.sn[2] * sz;
+  const uint32_t dx = (uint32_t)(S.sc[0] - S.sn[0]), dy = (uint32_t)(S.sc[1] - S.sn[1]) * sy,
+                 dz = (uint32_t)(S.sc[2] - S.sn[2]) * sz;
+#ifdef PMLPIC_CHECK
+  const uint32_t qs[6] = {qn + dx, qn + dy, qn + dz, qn + dy + dz, qn + dx + dz, qn + dx + dy};
+  for (int a = 0; a < 6; ++a)
+    if ((long)qs[a] + (long)sz + (long)sy + 1 >= g.nelem) check_failed(g.check, CHECK_SAMPLE);
+#endif
+  EB[0] = gather_comp_off32<T, 1>(F.E[0], S, qn + dx, sy, sz);
+  EB[1] = gather_comp_off32<T, 2>(F.E[1], S, qn + dy, sy, sz);
+  EB[2] = gather_comp_off32<T, 4>(F.E[2], S, qn + dz, sy, sz);
+  EB[3] = gather_comp_off32<T, 6>(F.B[0], S, qn + dy + dz, sy, sz);
+  EB[4] = gather_comp_off32<T, 5>(F.B[1], S, qn + dx + dz, sy, sz);
+  EB[5] = gather_comp_off32<T, 3>(F.B[2], S, qn + dx + dy, sy, sz);
+}
+
 // Wavefronts per SIMD the compiler must leave room for: FP64 registers otherwise grow past
 // 128 and drop the kernel to 3 wavefronts (measured 2.34 against 1.94 ms on the 3D beam);
 // FP32 is left to the compiler (asked for 4 it trades scheduling for registers: 1.44
@@ -66,8 +125,9 @@ template <> struct P3Occ<double> { static constexpr int MIN_WAVES = 4; };
 // tile order, x fastest; at one particle per cell every tile is one partial chunk and
 // neighbouring workgroups take neighbouring tiles, sharing the cache lines of their fields
 // and currents).  TS > 0: cubic tiles of TS cells known at compile time (the box
-// strides become immediates); 0: the tile shape of tw.
-template <typename T, int TS>
+// strides become immediates); 0: the tile shape of tw.  OFF32: the gather with 32-bit
+// offsets (field arrays of fewer than 2^32 bytes).
+template <typename T, int TS, bool OFF32>
 __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3Occ<T>::MIN_WAVES))) k_push3d_tiles(Grid<T> g, Fields<T> F, Parts<T> P, StepCtl ctl, TileWork tw,
                                                          int push) {
   __shared__ double box[3 * P3_NODES];
@@ -107,7 +167,7 @@ __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3O
   st[2] = ext[0] * ext[1];
   const int total = st[2] * ext[2];
   // the first particle's state is requested before the box is cleared, the next one's
-  // before the current one is processed: its memory round trip overlaps the gather's
+  // while the current one is processed
   struct PState {
     uint32_t c;
     T f[3], u[3], w;
@@ -135,8 +195,6 @@ __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3O
   for (int d = 0; d < 3; ++d) lsink.lo[d] = T0[d] - 1;
   unsigned int my_pushes = 0u;
   for (; p < e; p += P3_TPB) {
-    PState nxt;
-    load(min(p + P3_TPB, e - 1), nxt);
     // a removed particle (kept until the next sort drops it) runs the same code on a cell of
     // the tile, deposits nothing and is written back unchanged: every path issues the same
     // loads and stores, so the wave waits only for what it uses
@@ -149,9 +207,17 @@ __global__ void __launch_bounds__(P3_TPB) __attribute__((amdgpu_waves_per_eu(P3O
     T u[3] = {cur.u[0], cur.u[1], cur.u[2]};
     if (push) {
       T EB[6];
-      gather<T, 3, 1>(g, F, id, f, EB);
+      if constexpr (OFF32) gather_linear3_off32<T>(g, F, id, f, EB);
+      else gather<T, 3, 1>(g, F, id, f, EB);
       boris(g.qdt_2m, EB, u);
     }
+    // the next particle's state is requested after the gather's loads, not before them: the
+    // wave's wait for the stencil then leaves it in flight (load counts complete in order),
+    // and it arrives while this particle moves and deposits
+    __builtin_amdgcn_sched_barrier(0);
+    PState nxt;
+    load(min(p + P3_TPB, e - 1), nxt);
+    __builtin_amdgcn_sched_barrier(0);
     const int id0[3] = {id[0], id[1], id[2]};
     const T f0[3] = {f[0], f[1], f[2]};
     T ig;
@@ -263,10 +329,19 @@ void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Step
   if (tw.ntiles <= 0 || n_slots <= 0) return;
   // items: at most one partial chunk per tile, plus the full chunks of the slots
   const unsigned nb = (unsigned)(tw.ntiles + (n_slots + tw.chunk - 1) / tw.chunk);
-  if (tw.tile[0] == 8 && tw.tile[1] == 8 && tw.tile[2] == 8)
-    hipLaunchKernelGGL((k_push3d_tiles<T, 8>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
-  else
-    hipLaunchKernelGGL((k_push3d_tiles<T, 0>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+  const bool cube8 = tw.tile[0] == 8 && tw.tile[1] == 8 && tw.tile[2] == 8;
+  if constexpr (sizeof(T) == 8) {
+    if (g.nelem * (long)sizeof(T) < (1L << 32)) {
+      if (cube8) hipLaunchKernelGGL((k_push3d_tiles<T, 8, true>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+      else hipLaunchKernelGGL((k_push3d_tiles<T, 0, true>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+      return;
+    }
+  }
+  if (cube8) {
+    hipLaunchKernelGGL((k_push3d_tiles<T, 8, false>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+  } else {
+    hipLaunchKernelGGL((k_push3d_tiles<T, 0, false>), dim3(nb), dim3(P3_TPB), 0, s, g, F, P, ctl, tw, push);
+  }
 }
 
 template void launch_push3d<float>(const Grid<float> &, const Fields<float> &, const Parts<float> &, StepCtl,
