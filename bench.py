@@ -246,7 +246,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (calibrates the HBM byte counters)")
+    ap.add_argument("--atomic-rates", action="store_true",
+                    help="only measure the LDS and global float atomic add rates (pml_pic_atomic_rates)")
     args = ap.parse_args()
+    if args.atomic_rates:
+        import torch
+        from paper_2201_09084_amd import binding as B
+        torch.cuda.set_device(0)
+        r = B.atomic_rates()
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        clock_hz = 2.4e9
+        print(json.dumps({"atomic_rates_lane_adds_per_s": r, "compute_units": cus,
+                          "per_cu_per_clock_at_2.4GHz": {k: v / (cus * clock_hz) for k, v in r.items()}}),
+              flush=True)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4

@@ -19,8 +19,9 @@
  *
  * Memory ownership: the caller allocates ONE device buffer of at least
  * pml_pic_workspace_size() bytes (256-byte aligned) and a HIP stream, and passes both
- * to pml_pic_create.  The library never allocates device memory; the handle borrows
- * the buffer and the stream, which must outlive it.  Host arrays passed to the calls
+ * to pml_pic_create.  The calls of a simulation never allocate device memory (only the
+ * measurement aid pml_pic_atomic_rates allocates, and frees, buffers of its own); the
+ * handle borrows the buffer and the stream, which must outlive it.  Host arrays passed to the calls
  * below are read or written before the call returns (the call synchronises the
  * stream when it copies to or from the host) and stay owned by the caller.
  *
@@ -375,6 +376,17 @@ int pml_pic_batch_step_profiled(pml_pic_batch *b, int32_t n_steps, double *phase
 
 const char *pml_pic_batch_last_error(const pml_pic_batch *b);
 void pml_pic_batch_destroy(pml_pic_batch *b);
+
+/* A measurement aid, not a step of the method: the throughput of the float atomic additions
+ * a deposit can accumulate with, on the current device, in lane additions per second:
+ * rates[0] FP64 and rates[1] FP32 atomic adds into LDS (the lanes of a wavefront on consecutive
+ * words of a workgroup's box), rates[2] FP32 and rates[3] FP64 atomic adds into global memory
+ * at distinct consecutive addresses (the pattern of a box's flush to J).  For benchmarks and
+ * design work: which precision an LDS box should hold, and what a flush costs.  Allocates and
+ * frees 72 MiB of device memory and a stream of its own; synchronises that stream.
+ * PML_PIC_E_INVALID_ARG if rates is NULL, PML_PIC_E_HIP (message via
+ * pml_pic_last_error(NULL)) if a HIP call fails. */
+int pml_pic_atomic_rates(double rates[4]);
 
 /* Message of the last failed call on h (or of the last failed create if h is NULL). */
 const char *pml_pic_last_error(const pml_pic_handle *h);

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PMLPIC_LIB") or os.path.join(HERE, "libpmlpic.so")
 
 PML_PIC_OK = 0
+PML_PIC_E_INVALID_ARG = -1
 STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_CFL", -3: "E_WORKSPACE", -4: "E_HIP",
           -5: "E_NONFINITE", -6: "E_CAPACITY", -7: "E_HOST"}
 FLAG_UNFUSED, FLAG_NO_SORT, FLAG_SEPARATE_DAMP, FLAG_KEEP_CURRENT, FLAG_SEPARATE_FIELDS = 1, 2, 4, 8, 16
@@ -33,7 +34,7 @@ EXPORTED = [
     "pml_pic_batch_destroy", "pml_pic_batch_step_profiled", "pml_pic_forward_ckpt",
     "pml_pic_backward", "pml_pic_set_conductor", "pml_pic_set_source", "pml_pic_slab_moments",
     "pml_pic_field_error", "pml_pic_field_error_noalloc", "pml_pic_sort_particles",
-    "pml_pic_particle_adjoint",
+    "pml_pic_particle_adjoint", "pml_pic_atomic_rates",
 ]
 PHASES = ["sort_particles", "clear_current", "gather_push", "deposit_current", "damp_pml_current",
           "update_yee_pml_B", "update_yee_pml_E", "update_yee_pml", "filter_current"]
@@ -114,6 +115,7 @@ def load_library():
             "pml_pic_field_error": (C.c_int, [vp, vp, dp, dp]),
             "pml_pic_field_error_noalloc": (C.c_int, [vp, vp, dp, dp]),
             "pml_pic_sort_particles": (C.c_int, [vp, P(C.c_int32), P(C.c_uint32), i64, P(C.c_int64)]),
+            "pml_pic_atomic_rates": (C.c_int, [dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -176,6 +178,16 @@ def workspace_size(params: Params) -> int:
     if rc != PML_PIC_OK:
         raise PmlPicError(rc, load_library().pml_pic_last_error(None).decode())
     return int(n.value)
+
+
+def atomic_rates() -> dict:
+    """pml_pic_atomic_rates on the current GPU: lane additions per second of FP64 / FP32
+    atomic adds into LDS and into global memory (distinct consecutive addresses)."""
+    r = (C.c_double * 4)()
+    rc = load_library().pml_pic_atomic_rates(r)
+    if rc != PML_PIC_OK:
+        raise PmlPicError(rc, load_library().pml_pic_last_error(None).decode())
+    return {"lds_f64": r[0], "lds_f32": r[1], "global_f32": r[2], "global_f64": r[3]}
 
 
 class PmlPic:

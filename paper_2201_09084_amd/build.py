@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmlpic.so")
 LIB_CHECK = os.path.join(HERE, "libpmlpic_check.so")
 SOURCES = ["api.hip", "fields.hip", "particles.hip", "push3d.hip", "fused3d.hip", "diag.hip", "batch.hip", "adjoint.hip",
-           "adjoint_particles.hip", "beam.hip"]
+           "adjoint_particles.hip", "beam.hip", "probe.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = [

@@ -2310,4 +2310,11 @@ int pml_pic_particle_adjoint(pml_pic_handle *h, int64_t n, double *dU_dx, double
   return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_particle_adjoint_impl(h, n, dU_dx, dU_du); });
 }
 
+int pml_pic_atomic_rates(double *rates) {
+  return abi_guard(&g_create_error, [&] {
+    if (!rates) return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "rates is NULL");
+    return atomic_rates(rates, &g_create_error);
+  });
+}
+
 }  // extern "C"
