@@ -2310,6 +2310,17 @@ int pml_pic_particle_adjoint(pml_pic_handle *h, int64_t n, double *dU_dx, double
   return abi_guard(h ? &h->err : &g_create_error, [&] { return pml_pic_particle_adjoint_impl(h, n, dU_dx, dU_du); });
 }
 
+}  // extern "C"
+
+namespace pmlpic {
+// Lane additions per second of FP64 and FP32 atomic adds into LDS (rates[0], rates[1]) and
+// into global memory at distinct consecutive addresses (rates[2], rates[3]) on the current
+// device (probe.hip); 0 or PML_PIC_E_HIP with the failing call in err.
+int atomic_rates(double rates[4], std::string *err);
+}  // namespace pmlpic
+
+extern "C" {
+
 int pml_pic_atomic_rates(double *rates) {
   return abi_guard(&g_create_error, [&] {
     if (!rates) return fail(&g_create_error, PML_PIC_E_INVALID_ARG, "rates is NULL");

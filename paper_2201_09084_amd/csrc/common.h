@@ -15,8 +15,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <string>
-
 namespace pmlpic {
 
 constexpr int G = 4;                 // guard layers per side
@@ -327,11 +325,6 @@ void launch_deposit(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, Par
 // of at least three cells whose box fits in LDS and spans less than 2^32 samples of the grid
 // (plane: the grid's z stride).
 bool push3d_applies(int dim, int order, const int tile[3], long plane);
-
-// Lane additions per second of FP64 and FP32 atomic adds into LDS (rates[0], rates[1]) and
-// into global memory at distinct consecutive addresses (rates[2], rates[3]) on the current
-// device (probe.hip); 0 or PML_PIC_E_HIP with the failing call in err.
-int atomic_rates(double rates[4], std::string *err);
 template <typename T>
 void launch_push3d(const Grid<T> &g, const Fields<T> &F, const Parts<T> &P, StepCtl ctl, const TileWork &tw,
                    int n_slots, int push, hipStream_t s);
