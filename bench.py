@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -240,7 +241,8 @@ def main():
     ap.add_argument("--input", choices=["straddle", "centre"], default="straddle",
                     help="beams: straddling the PML face they move toward from step 0 (default), or at the box centre")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU comparison run")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "pmlpic_autotune.json"),
+                    help="where the batch autotuner keeps the launch shape it picked")
     ap.add_argument("--precision", type=int, choices=[32, 64], default=32)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
