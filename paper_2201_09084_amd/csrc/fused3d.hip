@@ -115,7 +115,10 @@ constexpr int F3_KZMAX = 64;   // planes per chunk at most
 template <typename T, int F3_ROWS = F3Cfg<T>::ROWS, int F3_WAVES = F3_ROWS + 2>
 __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T> F, Fields<T> D, JZero<T> jz,
                                                             int nstrips, int nrb, int kz, int nchunk, bool fuse_alpha) {
-  __shared__ T sh_bx[F3_WAVES][64], sh_bz[F3_WAVES][64], sh_ex[F3_WAVES][64], sh_ez[F3_WAVES][64];
+  // rows published through LDS, in two sets by plane parity: plane k writes set k & 1 and
+  // reads set (k - 1) & 1 of the plane before, so that one barrier per plane orders them (a
+  // set is rewritten two planes later, after every wavefront has passed the barrier between)
+  __shared__ T sh_bx[2][F3_WAVES][64], sh_bz[2][F3_WAVES][64], sh_ex[2][F3_WAVES][64], sh_ez[2][F3_WAVES][64];
   __shared__ Tab9<T> sh_tz[F3_KZMAX + 3];   // z tables of planes k0 - 1 .. k1 + 1
   // workgroup b runs on XCD b mod 8: each XCD takes a contiguous eighth of the items, so
   // that neighbouring strips and rows (which read each other's halo) share its L2
@@ -204,14 +207,15 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
       if (bx_c && by_y && bz_c) bstep1(bh.y, bh.ya, Zc, X, cur.ex1 - ecx, ez_r - ecz);      // B_y: b = z, c = x
       if (bx_c && by_c && bz_z) bstep1(bh.z, bh.za, X, Y, ey_r - ecy, cur.exr - ecx);       // B_z: b = x, c = y
     }
-    sh_bx[w][lane] = bh.x;
-    sh_bz[w][lane] = bh.z;
+    const int cb = k & 1, pb = cb ^ 1;   // LDS sets of this plane and of the one before
+    sh_bx[cb][w][lane] = bh.x;
+    sh_bz[cb][w][lane] = bh.z;
     __syncthreads();
     // E^{n+1}(k)
     Vec3S<T> en = {ecx, ecy, ecz, cur.exa, cur.eya, cur.eza};
     {
       const T bz_l = __shfl_up(bh.z, 1), by_l = __shfl_up(bh.y, 1);
-      const T bxm = sh_bx[wm][lane], bzm = sh_bz[wm][lane];   // B^{n+1/2} at row j - 1
+      const T bxm = sh_bx[cb][wm][lane], bzm = sh_bz[cb][wm][lane];   // B^{n+1/2} at row j - 1
       T jx = cur.jx, jy = cur.jy, jzv = cur.jz;
       if (fuse_alpha) {   // alpha_at: the product over the axes in order x, y, z
         jx *= (T(1) * X.aC) * Y.aN * Zc.aN;
@@ -239,7 +243,7 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
       const int km = k - 1;
       const bool bz_zm = km <= M2, bz_cm = km <= M2 - 1;   // km >= k0 >= 0
       const T pz_r = __shfl_down(enp.z, 1), py_r = __shfl_down(enp.y, 1);
-      const T exp1 = sh_ex[wp][lane], ezp1 = sh_ez[wp][lane];   // E^{n+1}(k - 1) at row j + 1
+      const T exp1 = sh_ex[pb][wp][lane], ezp1 = sh_ez[pb][wp][lane];   // E^{n+1}(k - 1) at row j + 1
       Vec3S<T> b = bhp;
       if (bx_x && by_c && bz_cm) bstep1(b.x, b.xa, Y, Zp, ezp1 - enp.z, en.y - enp.y);
       if (bx_c && by_y && bz_cm) bstep1(b.y, b.ya, Zp, X, en.x - enp.x, pz_r - enp.z);
@@ -254,9 +258,8 @@ __global__ void __launch_bounds__(64 * F3_WAVES) k_fused_3d(Grid<T> g, Fields<T>
         if (X.sigC + Y.sigC > T(0)) gptr(D.Ba[2])[q] = b.za;
       }
     }
-    __syncthreads();   // every read of this plane's LDS rows is done
-    sh_ex[w][lane] = en.x;
-    sh_ez[w][lane] = en.z;
+    sh_ex[cb][w][lane] = en.x;
+    sh_ez[cb][w][lane] = en.z;
     // advance one plane
     bhp = bh;
     enp = en;
