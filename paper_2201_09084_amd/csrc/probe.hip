@@ -13,6 +13,7 @@
 #include <string>
 
 #include "common.h"
+#include "pml_pic.h"
 
 namespace pmlpic {
 
@@ -81,12 +82,12 @@ bool time_launch(ProbeBuffers &b, Launch launch, double lanes, double *rate, std
 int atomic_rates(double rates[4], std::string *err) {
   ProbeBuffers b;
   const size_t out_bytes = sizeof(double) * (size_t)AR_BLOCKS * AR_TPB;
-  if (!hip_ok(hipMalloc(&b.out, out_bytes), "hipMalloc", err)) return -4;
-  if (!hip_ok(hipMalloc(&b.dst, sizeof(double) * (size_t)AR_GLOBAL), "hipMalloc", err)) return -4;
-  if (!hip_ok(hipStreamCreate(&b.s), "hipStreamCreate", err)) return -4;
-  if (!hip_ok(hipEventCreate(&b.e0), "hipEventCreate", err)) return -4;
-  if (!hip_ok(hipEventCreate(&b.e1), "hipEventCreate", err)) return -4;
-  if (!hip_ok(hipMemsetAsync(b.dst, 0, sizeof(double) * (size_t)AR_GLOBAL, b.s), "hipMemsetAsync", err)) return -4;
+  if (!hip_ok(hipMalloc(&b.out, out_bytes), "hipMalloc", err)) return PML_PIC_E_HIP;
+  if (!hip_ok(hipMalloc(&b.dst, sizeof(double) * (size_t)AR_GLOBAL), "hipMalloc", err)) return PML_PIC_E_HIP;
+  if (!hip_ok(hipStreamCreate(&b.s), "hipStreamCreate", err)) return PML_PIC_E_HIP;
+  if (!hip_ok(hipEventCreate(&b.e0), "hipEventCreate", err)) return PML_PIC_E_HIP;
+  if (!hip_ok(hipEventCreate(&b.e1), "hipEventCreate", err)) return PML_PIC_E_HIP;
+  if (!hip_ok(hipMemsetAsync(b.dst, 0, sizeof(double) * (size_t)AR_GLOBAL, b.s), "hipMemsetAsync", err)) return PML_PIC_E_HIP;
   const double lanes = (double)AR_BLOCKS * AR_TPB * AR_ITERS;
   const dim3 grid(AR_BLOCKS), block(AR_TPB);
   bool ok = time_launch(b, [&] { hipLaunchKernelGGL(k_lds_atomic_rate<double>, grid, block, 0, b.s, (double *)b.out); },
@@ -98,8 +99,8 @@ int atomic_rates(double rates[4], std::string *err) {
             hip_ok(hipMemsetAsync(b.dst, 0, sizeof(double) * (size_t)AR_GLOBAL, b.s), "hipMemsetAsync", err) &&
             time_launch(b, [&] { hipLaunchKernelGGL(k_global_atomic_rate<double>, grid, block, 0, b.s, (double *)b.dst); },
                         lanes, &rates[3], err);
-  if (!ok) return -4;
-  return hip_ok(hipStreamSynchronize(b.s), "hipStreamSynchronize", err) ? 0 : -4;
+  if (!ok) return PML_PIC_E_HIP;
+  return hip_ok(hipStreamSynchronize(b.s), "hipStreamSynchronize", err) ? PML_PIC_OK : PML_PIC_E_HIP;
 }
 
 }  // namespace pmlpic
