@@ -370,6 +370,19 @@ struct pml_pic_handle {
   std::vector<int64_t> src_steps;        // injection step of each source entry (sorted)
   int64_t src_next = 0;                  // first entry not injected yet
   int64_t tail_n = 0;                    // particles injected since the last sort (unsorted tail)
+  // 3D tiled push of a single run: the dense tiles' kernel runs on `side` beside the tile-box
+  // kernel on `stream` (forked after and joined before with the two events); default priority
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  pml_pic_handle() = default;
+  pml_pic_handle(const pml_pic_handle &) = delete;
+  pml_pic_handle &operator=(const pml_pic_handle &) = delete;
+  ~pml_pic_handle() {
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (side) (void)hipStreamDestroy(side);
+  }
 
   template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
   double tab(int axis, int kind, int i) const { return tab64[((size_t)axis * T_NKIND + kind) * L.ntab + i + G]; }
@@ -887,12 +900,25 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
     pt.begin(s);
     if (fused && use_sort && h->L.tile_push3) {
       // dense tiles (a cell with many particles: a beam whose LDS adds would meet on a few
-      // nodes) take the kernel with chunk-sized replicated boxes, the others the tile-box one
+      // nodes) take the kernel with chunk-sized replicated boxes, the others the tile-box one.
+      // The two touch disjoint particles and add into J with atomics, so the dense kernel (a
+      // few workgroups busy for tens of microseconds on a beam) runs on the handle's side
+      // stream beside the tile-box kernel instead of before it.
       TileWork tw = h->tilework();
+      hipStream_t sd = s;
+      if (h->side) {
+        HIPCHK(h, hipEventRecord(h->ev_fork, s));
+        HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        sd = h->side;
+      }
       tw.sel = 1;
-      launch_push_deposit_tiles<T>(g, F, P, ctl, jc, tw, ns, h->p.push, s);
+      launch_push_deposit_tiles<T>(g, F, P, ctl, jc, tw, ns, h->p.push, sd);
       tw.sel = 2;
       launch_push3d<T>(g, F, P, ctl, tw, ns, h->p.push, s);
+      if (h->side) {
+        HIPCHK(h, hipEventRecord(h->ev_join, h->side));
+        HIPCHK(h, hipStreamWaitEvent(s, h->ev_join, 0));
+      }
       if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
     } else if (fused && use_sort) {
       launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);
@@ -1419,7 +1445,20 @@ static int pml_pic_workspace_size_impl(const pml_pic_params *params, size_t *byt
 
 static int pml_pic_create_impl(const pml_pic_params *params, void *device_workspace, size_t bytes, void *stream,
                    pml_pic_handle **out) {
-  return create_handle(params, device_workspace, bytes, stream, out, &g_create_error);
+  const int rc = create_handle(params, device_workspace, bytes, stream, out, &g_create_error);
+  if (rc != PML_PIC_OK || !(*out)->L.tile_push3) return rc;
+  // the stream and events on which the dense tiles' push runs beside the tile-box push
+  pml_pic_handle *h = *out;
+  hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    g_create_error = std::string("HIP error while creating the push stream: ") + hipGetErrorString(e);
+    delete h;
+    *out = nullptr;
+    return PML_PIC_E_HIP;
+  }
+  return PML_PIC_OK;
 }
 
 static int pml_pic_add_particles_impl(pml_pic_handle *h, int64_t n, const double *x, const double *u, const double *w) {
