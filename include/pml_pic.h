@@ -150,9 +150,9 @@ int pml_pic_workspace_size(const pml_pic_params *params, size_t *bytes);
  * device buffer of `bytes` bytes, 256-byte aligned; stream: a hipStream_t (may be
  * NULL for the default stream).  Fields start at zero, there are no particles.  A 3D
  * run with the linear shape and sorting also gets a stream and two events of its own
- * (default priority, released by pml_pic_destroy): part of its push runs there, forked
- * from `stream` and joined back to it within each step, so that work queued on `stream`
- * after a step still follows all of it. */
+ * (default priority, released by pml_pic_destroy): with 2^22 particle slots or more,
+ * part of its push runs there, forked from `stream` and joined back to it within each
+ * step, so that work queued on `stream` after a step still follows all of it. */
 int pml_pic_create(const pml_pic_params *params, void *device_workspace, size_t bytes,
                    void *stream, pml_pic_handle **out);
 

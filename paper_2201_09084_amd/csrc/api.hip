@@ -335,6 +335,10 @@ void make_layout(const pml_pic_params &p_in, Layout &L) {
 
 }  // namespace
 
+// particle slots from which the dense tiles' push of a 3D tiled step runs on the handle's side
+// stream beside the tile-box push (below it, one after the other on the caller's stream)
+constexpr int64_t SIDE_PUSH_MIN_SLOTS = int64_t(1) << 22;
+
 struct pml_pic_handle {
   pml_pic_params p;
   Layout L;
@@ -904,9 +908,12 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       // The two touch disjoint particles and add into J with atomics, so the dense kernel (a
       // few workgroups busy for tens of microseconds on a beam) runs on the handle's side
       // stream beside the tile-box kernel instead of before it.
+      // (the fork and the join cost more than they hide on runs of a few hundred thousand
+      // particles: the cavity's step took 0.145 against 0.133 ms with them)
       TileWork tw = h->tilework();
+      const bool beside = h->side && ns >= SIDE_PUSH_MIN_SLOTS;
       hipStream_t sd = s;
-      if (h->side) {
+      if (beside) {
         HIPCHK(h, hipEventRecord(h->ev_fork, s));
         HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
         sd = h->side;
@@ -915,11 +922,12 @@ int step_t(pml_pic_handle *h, int nsteps, PhaseTimer &pt) {
       launch_push_deposit_tiles<T>(g, F, P, ctl, jc, tw, ns, h->p.push, sd);
       tw.sel = 2;
       launch_push3d<T>(g, F, P, ctl, tw, ns, h->p.push, s);
-      if (h->side) {
+      // the particles injected since the sort (their own slots) also before the join
+      if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
+      if (beside) {
         HIPCHK(h, hipEventRecord(h->ev_join, h->side));
         HIPCHK(h, hipStreamWaitEvent(s, h->ev_join, 0));
       }
-      if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
     } else if (fused && use_sort) {
       launch_push_deposit_tiles<T>(g, F, P, ctl, jc, h->tilework(), ns, h->p.push, s);
       if (h->tail_n > 0) launch_gather_push_tail<T>(g, F, P, ctl, ctl.count + 1, (int)h->tail_n, ns, h->p.push, s);
