@@ -169,11 +169,18 @@ __device__ __forceinline__ int shape_weights(T f, T (&w)[ORDER + 1]) {
 // Same for the half-integer sample positions (index s refers to s + 1/2).
 template <int ORDER, typename T>
 __device__ __forceinline__ int shape_weights_stag(int i, T f, T (&w)[ORDER + 1]) {
-  int ii;
-  T ff;
-  if (f >= T(0.5)) { ii = i; ff = f - T(0.5); }
-  else { ii = i - 1; ff = f + T(0.5); if (ff >= T(1)) { ff = T(0); ii = i; } }
-  return ii + shape_weights<ORDER>(ff, w);
+  if constexpr (sizeof(T) == 4) {   // selects instead of branches (the same arithmetic)
+    const bool hi = f >= T(0.5);
+    const T a = f - T(0.5), b = f + T(0.5);
+    const bool fix = !hi && b >= T(1);
+    return ((hi || fix) ? i : i - 1) + shape_weights<ORDER>(hi ? a : (fix ? T(0) : b), w);
+  } else {
+    int ii;
+    T ff;
+    if (f >= T(0.5)) { ii = i; ff = f - T(0.5); }
+    else { ii = i - 1; ff = f + T(0.5); if (ff >= T(1)) { ff = T(0); ii = i; } }
+    return ii + shape_weights<ORDER>(ff, w);
+  }
 }
 
 // The array of three for a component known only at run time (per lane): a select between

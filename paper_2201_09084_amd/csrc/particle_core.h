@@ -148,10 +148,20 @@ __device__ __forceinline__ bool move(const Grid<T> &g, int (&id)[3], T (&f)[3], 
   for (int d = 0; d < DIM; ++d) {
     const T disp = (g.dt * g.inv_dx[d]) * (u[d] * inv_gamma);
     T nf = f[d] + disp;
-    if (nf >= T(1)) { nf -= T(1); id[d] += 1; }
-    else if (nf < T(0)) {
-      nf += T(1); id[d] -= 1;
-      if (nf >= T(1)) { nf = T(0); id[d] += 1; }
+    if constexpr (sizeof(T) == 4) {
+      // the same arithmetic with selects instead of branches (FP32: fewer scalar and exec-mask
+      // instructions per particle; in FP64 the extra live values make the push kernel spill)
+      const bool hi = nf >= T(1), lo = nf < T(0);
+      const T up = nf - T(1), dn = nf + T(1);
+      const bool fix = lo && dn >= T(1);   // a step just below 0 that rounds to 1 after the wrap
+      nf = hi ? up : (lo ? (fix ? T(0) : dn) : nf);
+      id[d] += hi ? 1 : ((lo && !fix) ? -1 : 0);
+    } else {
+      if (nf >= T(1)) { nf -= T(1); id[d] += 1; }
+      else if (nf < T(0)) {
+        nf += T(1); id[d] -= 1;
+        if (nf >= T(1)) { nf = T(0); id[d] += 1; }
+      }
     }
     f[d] = nf;
     inside = inside && id[d] >= 0 && id[d] < g.M[d];
