@@ -11,7 +11,9 @@ deposit alpha-damped current there).
   on the largest sub-box it steps in seconds, 128^3 + 12 (2,129,920 particles, the same
   densities and the same beam cylinder ending in the +z layer), FP64 and FP32 against the
   oracle over 2 steps; at the full size, properties that hold at any size (FP32 against FP64
-  on the GPU over 16 steps, the FP64 Gauss residual, the particle count).
+  on the GPU over 16 steps, the FP64 Gauss residual, the particle count).  The sub-box again at
+  two particles per cell plus a dense cluster (over 2^22 particles, so that the dense tiles'
+  push runs on the second stream as in the benchmark), against the oracle over 2 steps.
 
 Also the beams at their original place (the box centre, hundreds of cells from the layers):
 * 2D: FP64 and FP32 against the oracle over 4 steps, then FP32 against the oracle-checked FP64
@@ -152,6 +154,33 @@ def test_beam3d_straddling_pml_subbox_against_oracle():
     worst = compare_fields(g32, o, cfg, FP32_TOL, "fp32 3d straddle", l2=True)
     say("fp32 vs oracle worst rel L2 %.3e" % worst)
     compare_particles(g32, o, 1e-4, 1e-4, "fp32 3d straddle")
+
+
+def test_beam3d_straddling_pml_subbox_side_stream_against_oracle():
+    """The same sub-box at two background particles per cell plus a dense cluster (hundreds
+    per cell): with 2^22 particle slots or more the dense tiles' push runs on the handle's
+    second stream beside the tile-box push, as in the benchmark; FP64 and FP32 against the
+    oracle over 2 steps."""
+    cfg = W.beam3d_config(precision=64, n=128)
+    parts = W.beam3d_particles(cfg, background_ppc=2.0, n_beam=32768, straddle=True)
+    rng = np.random.default_rng(1017)
+    n_dense = 4096
+    centre = np.array([cfg.n[d] * 0.5 * cfg.dx[d] for d in range(3)])
+    xd = centre + rng.normal(0.0, 0.7, (n_dense, 3)) * np.array(cfg.dx[:3])
+    parts = W.Particles(x=np.concatenate([parts.x, xd]),
+                        u=np.concatenate([parts.u, rng.normal(0.0, 0.03, (n_dense, 3))]),
+                        w=np.concatenate([parts.w, np.full(n_dense, 0.01)]))
+    say("beam3d 128^3 + 12, 2 per cell + dense cluster: %d particles" % len(parts))
+    assert len(parts) >= 2 ** 22
+    g, o = both(cfg, parts, parallel=True)
+    g32 = _gpu(cfg.replace(precision=32), parts)
+    for s in (g, o, g32):
+        s.step(2)
+    compare_fields(g, o, cfg, 1e-10, "fp64 3d side stream")
+    compare_particles(g, o, 1e-10, 1e-10, "fp64 3d side stream")
+    worst = compare_fields(g32, o, cfg, FP32_TOL, "fp32 3d side stream", l2=True)
+    say("fp32 vs oracle worst rel L2 %.3e" % worst)
+    compare_particles(g32, o, 1e-4, 1e-4, "fp32 3d side stream")
 
 
 def test_beam3d_straddling_pml_full_size_properties():
