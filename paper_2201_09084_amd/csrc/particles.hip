@@ -745,9 +745,36 @@ constexpr int SCAN_BLOCK = 1024;
 constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
+// Exclusive prefix of v over the SCAN_BLOCK threads of the workgroup, and their total:
+// inclusive scans within each wavefront by lane shuffles, then one over the 16 wavefront
+// totals (two barriers; wt holds SCAN_BLOCK / 64 words of LDS)
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wt, uint32_t &total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wt[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t z = lane < SCAN_BLOCK / 64 ? wt[lane] : 0u;
+#pragma unroll
+    for (int off = 1; off < SCAN_BLOCK / 64; off <<= 1) {
+      const uint32_t y = __shfl_up(z, off);
+      if (lane >= off) z += y;
+    }
+    if (lane < SCAN_BLOCK / 64) wt[lane] = z;   // inclusive prefix of the wavefront totals
+  }
+  __syncthreads();
+  total = wt[SCAN_BLOCK / 64 - 1];
+  return (w > 0 ? wt[w - 1] : 0u) + x - v;
+}
+
 // block-wide exclusive scan of SCAN_TILE counts; block totals to blocksums
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_local(uint32_t *counts, int n, uint32_t *blocksums) {
-  __shared__ uint32_t sh[SCAN_BLOCK];
+  __shared__ uint32_t wt[SCAN_BLOCK / 64];
   const int t = threadIdx.x;
   const long base = (long)blockIdx.x * SCAN_TILE + (long)t * SCAN_ITEMS;
   uint32_t v[SCAN_ITEMS];
@@ -757,44 +784,28 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_local(uint32_t *counts, int
     v[e] = (base + e < n) ? counts[base + e] : 0u;
     sum += v[e];
   }
-  sh[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
-    const uint32_t add = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  uint32_t run = sh[t] - sum;   // exclusive prefix of this thread
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(sum, wt, total);   // exclusive prefix of this thread
 #pragma unroll
   for (int e = 0; e < SCAN_ITEMS; ++e) {
     if (base + e < n) counts[base + e] = run;
     run += v[e];
   }
-  if (t == SCAN_BLOCK - 1) blocksums[blockIdx.x] = sh[t];
+  if (t == 0) blocksums[blockIdx.x] = total;
 }
 
 // exclusive scan of the block totals in one block; writes the grand total to *total
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_blocks(uint32_t *blocksums, int nb, int32_t *total) {
-  __shared__ uint32_t sh[SCAN_BLOCK];
-  __shared__ uint32_t carry;
+  __shared__ uint32_t wt[SCAN_BLOCK / 64];
   const int t = threadIdx.x;
-  if (t == 0) carry = 0;
-  __syncthreads();
+  uint32_t carry = 0;   // the same in every thread
   for (int start = 0; start < nb; start += SCAN_BLOCK) {
     const uint32_t v = (start + t < nb) ? blocksums[start + t] : 0u;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
-      const uint32_t add = t >= off ? sh[t - off] : 0u;
-      __syncthreads();
-      sh[t] += add;
-      __syncthreads();
-    }
-    if (start + t < nb) blocksums[start + t] = carry + sh[t] - v;
-    __syncthreads();
-    if (t == SCAN_BLOCK - 1) carry += sh[t];
-    __syncthreads();
+    uint32_t part;
+    const uint32_t ex = block_exclusive_scan(v, wt, part);
+    if (start + t < nb) blocksums[start + t] = carry + ex;
+    carry += part;
+    __syncthreads();   // wt is rewritten by the next pass
   }
   if (t == 0) *total = (int32_t)carry;
 }
