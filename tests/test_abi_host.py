@@ -214,3 +214,9 @@ def test_checked_build_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
 
+
+
+def test_atomic_rates_rejects_null_output_without_a_gpu(lib):
+    # the argument check comes before any HIP call
+    assert lib.pml_pic_atomic_rates(C.POINTER(C.c_double)()) == B.PML_PIC_E_INVALID_ARG
+    assert b"rates is NULL" in lib.pml_pic_last_error(None)
